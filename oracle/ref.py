@@ -1,0 +1,149 @@
+"""ctypes front end of the plain C++ CDDT oracle (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg use this.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "cddt_ref.cpp")
+LIB = os.path.join(HERE, "libcddt_ref.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with the host compiler (no GPU code involved)."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-pthread",
+               SRC, "-o", tmp]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.ref_create.restype = vp
+        L.ref_create.argtypes = [vp, i32, i32, i32, i32, i32]
+        L.ref_destroy.argtypes = [vp]
+        L.ref_edge_count.restype = i64
+        L.ref_edge_count.argtypes = [vp]
+        L.ref_tables.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.ref_sizes.argtypes = [vp, vp, vp, vp]
+        L.ref_export.argtypes = [vp, vp, vp]
+        L.ref_cast.argtypes = [vp, vp, vp, vp, i64, i32, vp, i32]
+        L.ref_cast_bruteforce.argtypes = [vp, vp, vp, vp, i64, i32, vp, i32]
+        L.ref_weight.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, vp, i32, vp, vp, i32]
+        L.ref_update.restype = i32
+        L.ref_update.argtypes = [vp, vp, vp, vp, i64]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def default_threads() -> int:
+    return max(1, len(os.sched_getaffinity(0)))
+
+
+class RefCDDT:
+    """Plain CDDT built on the host: sorted std::vector rows, std::upper/lower_bound."""
+
+    def __init__(self, occ: np.ndarray, theta_bins: int, full_map: bool = False, threads: int = 1):
+        self.occ = np.ascontiguousarray(occ, dtype=np.uint8)
+        self.h, self.w = self.occ.shape
+        self.n = int(theta_bins)
+        self.h_ = lib().ref_create(_p(self.occ), self.w, self.h, self.n, int(full_map), int(threads))
+        if not self.h_:
+            raise ValueError("invalid oracle arguments")
+
+    def close(self):
+        if self.h_:
+            lib().ref_destroy(self.h_)
+            self.h_ = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def edge_count(self) -> int:
+        return int(lib().ref_edge_count(self.h_))
+
+    def tables(self):
+        half = self.n // 2
+        c = np.zeros(half, np.int64)
+        s = np.zeros(half, np.int64)
+        rmin = np.zeros(half, np.int64)
+        nrows = np.zeros(half, np.int64)
+        k = np.zeros(1, np.float32)
+        lib().ref_tables(self.h_, _p(c), _p(s), _p(rmin), _p(nrows), _p(k))
+        return c, s, rmin, nrows, k[0]
+
+    def sizes(self):
+        v = np.zeros(3, np.int64)
+        lib().ref_sizes(self.h_, _p(v[0:]), _p(v[1:]), _p(v[2:]))
+        return int(v[0]), int(v[1]), int(v[2])
+
+    def export(self):
+        """(nrows per slice, row lengths, zero points) in canonical (slice, band) order."""
+        rows, zeros, _ = self.sizes()
+        rl = np.zeros(rows, np.int32)
+        zz = np.zeros(max(zeros, 1), np.int32)
+        lib().ref_export(self.h_, _p(rl), _p(zz))
+        return self.tables()[3], rl, zz[:zeros]
+
+    def cast(self, x, y, th, max_range: int, threads: int = 1, brute: bool = False) -> np.ndarray:
+        x = np.ascontiguousarray(x, np.float32)
+        y = np.ascontiguousarray(y, np.float32)
+        th = np.ascontiguousarray(th, np.float32)
+        out = np.zeros(x.size, np.int32)
+        f = lib().ref_cast_bruteforce if brute else lib().ref_cast
+        f(self.h_, _p(x), _p(y), _p(th), x.size, int(max_range), _p(out), int(threads))
+        return out
+
+    def weight(self, px, py, pth, offsets, obs, log_table, max_range: int, threads: int = 1,
+               want_ranges: bool = False):
+        px = np.ascontiguousarray(px, np.float32)
+        py = np.ascontiguousarray(py, np.float32)
+        pth = np.ascontiguousarray(pth, np.float32)
+        offsets = np.ascontiguousarray(offsets, np.float32)
+        obs = np.ascontiguousarray(obs, np.int32)
+        table = np.ascontiguousarray(log_table, np.float32).ravel()
+        assert table.size == (max_range + 1) ** 2
+        logw = np.zeros(px.size, np.float64)
+        ranges = np.zeros(px.size * offsets.size, np.int32) if want_ranges else None
+        lib().ref_weight(self.h_, _p(px), _p(py), _p(pth), px.size, _p(offsets), _p(obs),
+                         offsets.size, _p(table), int(max_range), _p(logw),
+                         _p(ranges) if want_ranges else None, int(threads))
+        if want_ranges:
+            return logw, ranges.reshape(px.size, offsets.size)
+        return logw
+
+    def update(self, xs, ys, vals) -> int:
+        xs = np.ascontiguousarray(xs, np.int32)
+        ys = np.ascontiguousarray(ys, np.int32)
+        vals = np.ascontiguousarray(vals, np.uint8)
+        r = lib().ref_update(self.h_, _p(xs), _p(ys), _p(vals), xs.size)
+        if r < 0:
+            raise ValueError("op off the map")
+        for x, y, v in zip(xs.tolist(), ys.tolist(), vals.tolist()):
+            self.occ[y, x] = 1 if v else 0
+        return r
