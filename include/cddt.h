@@ -1,0 +1,301 @@
+/* cddt.h -- C ABI of libcddt: Compressed Directional Distance Transform ray
+ * casting and the particle-filter beam sensor model on AMD Instinct MI355X.
+ *
+ * Method: Walsh & Karaman, "CDDT: Fast Approximate 2D Ray Casting for
+ * Accelerated Localization".  Sec. III defines the ray cast on an occupancy
+ * grid; Sec. IV defines the DDT/CDDT, its direct construction (Sec. IV-A),
+ * the query (Sec. IV-B), the theta/theta+pi symmetry, edge map and overlap
+ * check (Sec. IV-C) and the incremental obstacle update (Sec. IV-D); Sec. VI
+ * uses the casts in a beam-model particle filter with 61 rays per particle.
+ *
+ * Conventions for every call:
+ *  - Bulk arrays are DEVICE pointers unless the parameter name ends in _h
+ *    (host memory).  The caller owns every buffer it passes in; the library
+ *    owns the structure behind a cddt_map / cddt_plan / cddt_server.
+ *  - Every call returns cddt_status: 0 on success, a negative code on failure.
+ *    Nothing aborts and nothing throws across the ABI.  cddt_last_error()
+ *    returns a thread-local message describing the last failure.
+ *  - Argument validation happens on the host before any GPU work is queued:
+ *    an invalid call returns CDDT_EINVAL and has no side effects.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls on a stream
+ *    are asynchronous unless stated otherwise; outputs are valid once the
+ *    stream reaches the call.  A cddt_map is not thread-safe: order all calls
+ *    that use one map on one stream (or synchronise between streams).
+ *  - Device data (poses, angles, observations) is never validated on the host;
+ *    it has defined results instead (see cddt_cast).
+ *
+ * Numerical contract (bit-exact; the reading of the paper is fixed here):
+ *  - Cells (i, j) cover [i, i+1) x [j, j+1); the grid is row-major occ[j*W+i];
+ *    theta is measured from +x toward +y; lengths are in cells.
+ *  - theta_bins = n bins over the full circle; the n/2 slices 0 <= s < n/2
+ *    are stored and bin k >= n/2 is answered from slice k - n/2 by searching
+ *    backwards (Sec. IV-C symmetry).
+ *  - Direction table: C[s] = llround(cos(2 pi s/n) 2^30), S[s] likewise with
+ *    sin, computed on the host in double.
+ *  - Zero point of cell (i, j) in slice s: Z = ((2i+1) C + (2j+1) S) >> 15,
+ *    the along-ray coordinate of the cell centre in units of 2^-16 cell.
+ *    It is stored in every band r ("CDDT bin") that the rotated cell square's
+ *    lateral extent [Yc - Hs, Yc + Hs) overlaps, with Yc = (2j+1) C - (2i+1) S,
+ *    Hs = |C| + |S| (units 2^-31) and bands [r, r+1) half-open.
+ *  - Query (x, y, theta), all float32: the answer is 0 if |theta| >= 1e6 or
+ *    theta is not finite, if (x, y) is outside [0, W) x [0, H) or not finite,
+ *    or if the cell under (x, y) is occupied (overlap check, full grid).
+ *    Otherwise xf = floor(x 2^16), yf = floor(y 2^16), bin
+ *    k = floor(fl(fl(theta * K) + 0.5f)) mod n with K = (float)(n / (2 pi))
+ *    and no fused multiply-add, Xq = (xf C + yf S) >> 30,
+ *    r = (yf C - xf S) >> 46.  For k < n/2 the answer uses the smallest zero
+ *    point Z > Xq in band r, otherwise the largest Z < Xq; the range is
+ *    min(max_range, (|Z - Xq| + 2^15) >> 16), or max_range when no such Z.
+ *  - Construction uses the edge map (occupied cells with at least one free or
+ *    off-map 8-neighbour) unless CDDT_FLAG_FULL_MAP is given.
+ */
+#ifndef CDDT_H
+#define CDDT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cddt_status;
+enum {
+  CDDT_OK = 0,
+  CDDT_EINVAL = -1,   /* invalid argument; nothing was done */
+  CDDT_ENOMEM = -2,   /* device allocation failed or the structure exceeds 2^32 entries */
+  CDDT_EDEVICE = -3,  /* a HIP runtime call failed; the message names it */
+  CDDT_EBUSY = -4,    /* server admission refused (budget or slots exhausted) */
+  CDDT_EINTERNAL = -5 /* consistency check failed inside the library */
+};
+
+/* Construction flags. */
+enum {
+  CDDT_FLAG_FULL_MAP = 1u << 0, /* project every occupied cell, not only the edge map */
+  CDDT_FLAG_STATIC = 1u << 1    /* no per-row slack: smallest structure, updates rebuild */
+};
+
+/* Device memory for the structure.  alloc returns a device pointer of at
+ * least `bytes` bytes (NULL on failure); free releases it.  Both are called
+ * from the thread that calls into the library.  NULL allocator -> hipMalloc. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} cddt_allocator;
+
+typedef struct cddt_map_s* cddt_map;
+
+typedef struct {
+  int32_t width, height, theta_bins, slices;
+  uint32_t flags, reserved;
+  int64_t rows;          /* bands over all stored slices */
+  int64_t edge_cells;    /* cells projected (edge map, or all occupied cells) */
+  int64_t zero_points;   /* stored zero points (sum of row lengths) */
+  int64_t capacity;      /* allocated zero-point slots (>= zero_points; slack for updates) */
+  int64_t max_row_len;
+  int64_t device_bytes;  /* bytes the map holds on the device */
+  int64_t rebuilds;      /* updates that overflowed a row and re-laid the structure */
+} cddt_stats;
+
+/* Build a CDDT from an occupancy grid (Sec. IV-A: erosion to the edge map,
+ * projection of every edge cell into every stored slice, per-band sort).
+ *   occ        device, W*H bytes, row-major occ[j*W + i], nonzero = occupied;
+ *              copied into the map (the caller may free it after the call).
+ *   width,height  1..16384.   theta_bins  even, 2..8192.
+ *   flags      CDDT_FLAG_*.   alloc  nullable (hipMalloc).
+ * Blocks until the structure is built (sizes are read back to allocate).
+ * Errors: EINVAL (arguments), ENOMEM, EDEVICE. */
+cddt_status cddt_create(const uint8_t* occ, int32_t width, int32_t height, int32_t theta_bins,
+                        uint32_t flags, const cddt_allocator* alloc, void* stream,
+                        cddt_map* out_h);
+
+/* Wait for the map's outstanding work and release it.  NULL is accepted. */
+cddt_status cddt_destroy(cddt_map m);
+
+/* Incremental obstacle update (Sec. IV-D).  Op k sets cell (xs_h[k], ys_h[k])
+ * to occupied if values_h[k] != 0, else free; ops apply in array order, so
+ * the last write to a cell wins.  Cells within one step of a changed cell are
+ * re-classified against the edge map and their zero points removed from or
+ * inserted into every slice and band they cover, so the structure afterwards
+ * equals cddt_create on the new grid (same rows as multisets).  A row that
+ * runs out of slack triggers a rebuild of the whole structure.
+ *   xs_h, ys_h, values_h  host arrays of n_ops (n_ops >= 0).
+ * Blocks until applied.  Errors: EINVAL if any op is off the map (none is
+ * applied), ENOMEM, EDEVICE. */
+cddt_status cddt_update(cddt_map m, const int32_t* xs_h, const int32_t* ys_h,
+                        const uint8_t* values_h, int64_t n_ops, void* stream);
+
+/* Ray casts (Sec. IV-B query, Sec. IV-C symmetry and overlap check).
+ *   x, y, theta  device float32[n] (structure of arrays).
+ *   max_range    0..65535.   ranges_out  device int32[n].
+ * n = 0 is a no-op.  Asynchronous. */
+cddt_status cddt_cast(cddt_map m, const float* x, const float* y, const float* theta, int64_t n,
+                      int32_t max_range, int32_t* ranges_out, void* stream);
+
+/* Beam-model sensor weights (Sec. VI): for each particle p,
+ *   logw_out[p] = sum_r log_table[clamp(obs_ranges[r], 0, M) * (M + 1) + d_pr]
+ * where d_pr = cast(px[p], py[p], fl(ptheta[p] + ray_offsets[r])) with max
+ * range M.  The sum is float32 in a fixed order that depends only on n_rays.
+ *   px, py, ptheta  device float32[n_particles].
+ *   ray_offsets     device float32[n_rays], 1 <= n_rays <= 1024.
+ *   obs_ranges      device int32[n_rays].
+ *   log_table       device float32[(M+1)*(M+1)], row-major [observed][expected].
+ *   pair_offset     0, or P such that rays r and r+P point in opposite
+ *                   directions: when their bins fall in the same slice, one
+ *                   search answers both (Sec. IV-C radial pairing).  Results
+ *                   do not depend on it.  See cddt_pair_offset.
+ *   logw_out        device float32[n_particles].
+ *   ranges_out      nullable device int32[n_particles * n_rays], [p][r].
+ * Asynchronous. */
+cddt_status cddt_weight(cddt_map m, const float* px, const float* py, const float* ptheta,
+                        int64_t n_particles, const float* ray_offsets, int32_t n_rays,
+                        int32_t pair_offset, const int32_t* obs_ranges, const float* log_table,
+                        int32_t max_range, float* logw_out, int32_t* ranges_out, void* stream);
+
+/* Helper for cddt_weight: the offset P (1 <= P < n_rays) that pairs the most
+ * rays r, r+P whose bearings differ by pi (within 1e-4 rad), or 0.
+ *   offsets_h  host float32[n_rays].  Returns the offset (>= 0). */
+int32_t cddt_pair_offset(const float* offsets_h, int32_t n_rays);
+
+/* Structure facts.  out_h: host.  Errors: EINVAL. */
+cddt_status cddt_info(cddt_map m, cddt_stats* out_h);
+
+/* The per-slice tables (host arrays of theta_bins/2 entries each): direction
+ * C, S (2^30 fixed point), lowest band index, band count, and K. */
+cddt_status cddt_slice_table(cddt_map m, int32_t* c_h, int32_t* s_h, int32_t* row_min_h,
+                             int32_t* nrows_h, float* k_scale_h);
+
+/* Canonical copy of the structure: band lengths (host int32[rows]) in
+ * (slice, band) order and the zero points (host int32[zero_points]) of all
+ * bands concatenated in that order, each band ascending; slack removed.
+ * Either array may be NULL.  Blocks.  Errors: EINVAL, EDEVICE. */
+cddt_status cddt_export(cddt_map m, int32_t* row_len_h, int32_t* zeros_h);
+
+/* Current occupancy grid (host uint8[W*H]).  Blocks. */
+cddt_status cddt_export_grid(cddt_map m, uint8_t* occ_h);
+
+/* ---------------------------------------------------------------------------
+ * Many filters in one persistent launch.
+ * A plan fixes a set of filters (each one cddt_weight call: its own map,
+ * particles, rays, observations and table).  Running a plan launches one
+ * persistent kernel whose waves pull tiles of particles from a device work
+ * counter until all filters are done; results are bit-identical to one
+ * cddt_weight per filter.  Running is capture-safe (kernel launches only, no
+ * allocation, memset or synchronisation), so a run can be recorded into a
+ * hipGraph and replayed each filter step with new data in the same buffers.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  cddt_map map;
+  const float *px, *py, *ptheta;
+  int64_t n_particles;
+  const float* ray_offsets;
+  int32_t n_rays;
+  int32_t pair_offset;
+  const int32_t* obs_ranges;
+  const float* log_table;
+  int32_t max_range;
+  int32_t reserved;
+  float* logw_out;
+  int32_t* ranges_out; /* nullable */
+} cddt_filter;
+
+typedef struct {
+  int32_t particles_per_tile; /* particles a wave takes per queue pop (1..256) */
+  int32_t waves_per_block;    /* 1..16 */
+  int32_t blocks_per_cu;      /* persistent blocks per compute unit (1..32) */
+  int32_t reserved;
+} cddt_tuning;
+
+typedef struct cddt_plan_s* cddt_plan;
+
+/* filters_h: host array of n_filters (1..65536) descriptors, copied.
+ * tuning_h: nullable (library default).  Allocates the device descriptor
+ * table and work counter; blocks until they are uploaded. */
+cddt_status cddt_plan_create(const cddt_filter* filters_h, int32_t n_filters,
+                             const cddt_tuning* tuning_h, void* stream, cddt_plan* out_h);
+cddt_status cddt_plan_set_tuning(cddt_plan p, const cddt_tuning* tuning_h);
+cddt_status cddt_plan_get_tuning(cddt_plan p, cddt_tuning* tuning_h);
+/* One persistent launch (plus a one-thread counter reset kernel). */
+cddt_status cddt_plan_run(cddt_plan p, void* stream);
+/* Record one run into a hipGraph (replacing any previous one) / replay it. */
+cddt_status cddt_plan_capture(cddt_plan p, void* stream);
+cddt_status cddt_plan_replay(cddt_plan p, void* stream);
+/* Run the plan with the given tuning `reps` times and return the mean kernel
+ * milliseconds measured with HIP events on `stream` (used by the autotuner).
+ * Blocks. */
+cddt_status cddt_plan_time(cddt_plan p, const cddt_tuning* tuning_h, int32_t reps, void* stream,
+                           float* ms_h);
+/* The same filters as plain launches: one cddt_weight per filter, in order. */
+cddt_status cddt_plan_run_plain(cddt_plan p, void* stream);
+cddt_status cddt_plan_destroy(cddt_plan p);
+
+/* Number of compute units of the current device (for tuning spaces). */
+int32_t cddt_device_cus(void);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching over resident maps.
+ * A server keeps maps resident and accepts requests (one robot's particles
+ * and one scan) from host threads.  A scheduler thread admits queued requests
+ * whenever a batch slot and enough of the staging budget are free, packs
+ * every admitted request into one persistent batched launch on one of
+ * `n_lanes` streams, and keeps up to n_lanes batches in flight, so requests
+ * that arrive while others run are admitted as slots and memory free up and
+ * their work overlaps on the device.  Results are bit-identical to running
+ * the request alone.
+ * ------------------------------------------------------------------------- */
+typedef struct cddt_server_s* cddt_server;
+
+typedef struct {
+  int64_t budget_bytes;     /* device staging budget for request inputs/outputs */
+  int32_t n_lanes;          /* batches in flight (streams), 1..8 */
+  int32_t max_batch;        /* requests per batch, 1..4096 */
+  int32_t max_rays;         /* rays per request, 1..1024 */
+  int32_t reserved;
+  cddt_tuning tuning;       /* persistent-kernel tuning for server batches */
+} cddt_server_config;
+
+typedef struct {
+  int64_t submitted, completed, rejected;
+  int64_t batches;
+  int64_t rays;
+  int64_t peak_bytes;       /* highest staging bytes in use */
+  double busy_seconds;      /* wall time with at least one batch in flight */
+} cddt_server_stats;
+
+/* maps_h: host array of n_maps resident maps (not owned).  Per map: its ray
+ * layout (offsets float32[n_rays], pair offset), its log table (device
+ * float32[(M+1)^2]) and max range.  offsets_h are host arrays, copied. */
+cddt_status cddt_server_create(const cddt_map* maps_h, int32_t n_maps,
+                               const float* const* offsets_h, const int32_t* n_rays_h,
+                               const float* const* log_tables, const int32_t* max_range_h,
+                               const cddt_server_config* config_h, cddt_server* out_h);
+/* Queue one request (host memory, copied before return): particle poses
+ * px/py/ptheta_h[n_particles], observations obs_h[n_rays of the map].
+ * Returns the request id (>= 0) in *id_h.  EBUSY if the request alone
+ * exceeds the budget; otherwise it waits in the queue until admitted. */
+cddt_status cddt_server_submit(cddt_server s, int32_t map_index, const float* px_h,
+                               const float* py_h, const float* ptheta_h, int32_t n_particles,
+                               const int32_t* obs_h, int64_t* id_h);
+/* Non-blocking: 1 if the request finished (logw copied to logw_h, which must
+ * hold n_particles floats, and the request released), 0 if not yet. */
+cddt_status cddt_server_poll(cddt_server s, int64_t id, float* logw_h, int32_t* done_h);
+/* Blocking form of poll. */
+cddt_status cddt_server_wait(cddt_server s, int64_t id, float* logw_h);
+/* Completion time of a finished request, seconds since server creation
+ * (result visible on the host), and its submit time. */
+cddt_status cddt_server_times(cddt_server s, int64_t id, double* submit_h, double* done_h);
+cddt_status cddt_server_stats_get(cddt_server s, cddt_server_stats* out_h);
+/* Seconds since server creation on the server's clock. */
+double cddt_server_now(cddt_server s);
+/* Drain in-flight work, stop the scheduler and release staging memory. */
+cddt_status cddt_server_destroy(cddt_server s);
+
+/* Thread-local description of the last error (never NULL). */
+const char* cddt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CDDT_H */

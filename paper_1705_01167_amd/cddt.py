@@ -1,0 +1,360 @@
+"""Python binding of libcddt (ctypes).  Argument marshalling only.
+
+Every computation runs in the library's HIP kernels; torch supplies device
+buffers (``tensor.data_ptr()``) and the stream (``cuda_stream``).  The binding
+refuses to run without the compiled library: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcddt.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EBUSY, EINTERNAL = 0, -1, -2, -3, -4, -5
+FLAG_FULL_MAP = 1
+FLAG_STATIC = 2
+
+
+class CddtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libcddt error {code}: {msg}")
+        self.code = code
+
+
+class Stats(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("theta_bins", C.c_int32),
+                ("slices", C.c_int32), ("flags", C.c_uint32), ("reserved", C.c_uint32),
+                ("rows", C.c_int64), ("edge_cells", C.c_int64), ("zero_points", C.c_int64),
+                ("capacity", C.c_int64), ("max_row_len", C.c_int64), ("device_bytes", C.c_int64),
+                ("rebuilds", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class Filter(C.Structure):
+    _fields_ = [("map", C.c_void_p), ("px", C.c_void_p), ("py", C.c_void_p), ("ptheta", C.c_void_p),
+                ("n_particles", C.c_int64), ("ray_offsets", C.c_void_p), ("n_rays", C.c_int32),
+                ("pair_offset", C.c_int32), ("obs_ranges", C.c_void_p), ("log_table", C.c_void_p),
+                ("max_range", C.c_int32), ("reserved", C.c_int32), ("logw_out", C.c_void_p),
+                ("ranges_out", C.c_void_p)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("particles_per_tile", C.c_int32), ("waves_per_block", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_tuple(self):
+        return (self.particles_per_tile, self.waves_per_block, self.blocks_per_cu)
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("budget_bytes", C.c_int64), ("n_lanes", C.c_int32), ("max_batch", C.c_int32),
+                ("max_rays", C.c_int32), ("reserved", C.c_int32), ("tuning", Tuning)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
+                ("batches", C.c_int64), ("rays", C.c_int64), ("peak_bytes", C.c_int64),
+                ("busy_seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_vp, _i32, _i64, _u32, _f32p = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_void_p
+SIGNATURES = {
+    "cddt_create": (_i32, [_vp, _i32, _i32, _i32, _u32, _vp, _vp, C.POINTER(_vp)]),
+    "cddt_destroy": (_i32, [_vp]),
+    "cddt_update": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp]),
+    "cddt_cast": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _vp, _vp]),
+    "cddt_weight": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp]),
+    "cddt_pair_offset": (_i32, [_vp, _i32]),
+    "cddt_info": (_i32, [_vp, C.POINTER(Stats)]),
+    "cddt_slice_table": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "cddt_export": (_i32, [_vp, _vp, _vp]),
+    "cddt_export_grid": (_i32, [_vp, _vp]),
+    "cddt_plan_create": (_i32, [_vp, _i32, _vp, _vp, C.POINTER(_vp)]),
+    "cddt_plan_set_tuning": (_i32, [_vp, C.POINTER(Tuning)]),
+    "cddt_plan_get_tuning": (_i32, [_vp, C.POINTER(Tuning)]),
+    "cddt_plan_run": (_i32, [_vp, _vp]),
+    "cddt_plan_capture": (_i32, [_vp, _vp]),
+    "cddt_plan_replay": (_i32, [_vp, _vp]),
+    "cddt_plan_time": (_i32, [_vp, C.POINTER(Tuning), _i32, _vp, C.POINTER(C.c_float)]),
+    "cddt_plan_run_plain": (_i32, [_vp, _vp]),
+    "cddt_plan_destroy": (_i32, [_vp]),
+    "cddt_device_cus": (_i32, []),
+    "cddt_server_create": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, C.POINTER(ServerConfig), C.POINTER(_vp)]),
+    "cddt_server_submit": (_i32, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, C.POINTER(_i64)]),
+    "cddt_server_poll": (_i32, [_vp, _i64, _vp, C.POINTER(_i32)]),
+    "cddt_server_wait": (_i32, [_vp, _i64, _vp]),
+    "cddt_server_times": (_i32, [_vp, _i64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "cddt_server_stats_get": (_i32, [_vp, C.POINTER(ServerStats)]),
+    "cddt_server_now": (C.c_double, [_vp]),
+    "cddt_server_destroy": (_i32, [_vp]),
+    "cddt_last_error": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load libcddt.so; raise if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1705_01167_amd/build_lib.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != OK:
+        raise CddtError(code, lib().cddt_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _need(t, dtype, what, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous {dtype} tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what} must have {numel} elements, has {t.numel()}")
+
+
+def pair_offset(offsets) -> int:
+    a = np.ascontiguousarray(np.asarray(offsets, np.float32))
+    return int(lib().cddt_pair_offset(a.ctypes.data_as(C.c_void_p), a.size))
+
+
+def torch_allocator():
+    """A cddt_allocator backed by torch's caching allocator (current device and stream)."""
+    import torch
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = Allocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
+    return a
+
+
+class Map:
+    """A CDDT resident on the GPU (cddt_create / cddt_destroy)."""
+
+    def __init__(self, occ, theta_bins: int, full_map: bool = False, static: bool = False,
+                 allocator: Allocator | None = None, stream=None):
+        import torch
+        _need(occ, torch.uint8, "occ")
+        if occ.dim() != 2:
+            raise ValueError("occ must be 2-D [height, width]")
+        self.height, self.width = int(occ.shape[0]), int(occ.shape[1])
+        self.theta_bins = int(theta_bins)
+        self._alloc = allocator       # keep callbacks alive
+        flags = (FLAG_FULL_MAP if full_map else 0) | (FLAG_STATIC if static else 0)
+        h = C.c_void_p()
+        _check(lib().cddt_create(_ptr(occ), self.width, self.height, self.theta_bins, flags,
+                                 C.byref(allocator) if allocator is not None else None,
+                                 _stream(stream), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().cddt_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- queries -----------------------------------------------------------
+    def cast(self, x, y, theta, max_range: int, out=None, stream=None):
+        import torch
+        n = x.numel()
+        for t, w in ((x, "x"), (y, "y"), (theta, "theta")):
+            _need(t, torch.float32, w, n)
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device=x.device)
+        _need(out, torch.int32, "out", n)
+        _check(lib().cddt_cast(self.handle, _ptr(x), _ptr(y), _ptr(theta), n, int(max_range), _ptr(out),
+                               _stream(stream)))
+        return out
+
+    def weight(self, px, py, pth, offsets, obs, log_table, max_range: int, pair: int | None = None,
+               logw=None, ranges=False, stream=None):
+        import torch
+        n = px.numel()
+        for t, w in ((px, "px"), (py, "py"), (pth, "ptheta")):
+            _need(t, torch.float32, w, n)
+        nr = offsets.numel()
+        _need(offsets, torch.float32, "ray_offsets")
+        _need(obs, torch.int32, "obs_ranges", nr)
+        _need(log_table, torch.float32, "log_table", (max_range + 1) ** 2)
+        if pair is None:
+            pair = pair_offset(offsets.cpu().numpy())
+        if logw is None:
+            logw = torch.empty(n, dtype=torch.float32, device=px.device)
+        rng = torch.empty((n, nr), dtype=torch.int32, device=px.device) if ranges else None
+        _check(lib().cddt_weight(self.handle, _ptr(px), _ptr(py), _ptr(pth), n, _ptr(offsets), nr, int(pair),
+                                 _ptr(obs), _ptr(log_table), int(max_range), _ptr(logw), _ptr(rng),
+                                 _stream(stream)))
+        return (logw, rng) if ranges else logw
+
+    def update(self, xs, ys, values, stream=None):
+        xs = np.ascontiguousarray(np.asarray(xs), np.int32)
+        ys = np.ascontiguousarray(np.asarray(ys), np.int32)
+        vs = np.ascontiguousarray(np.asarray(values), np.uint8)
+        if not (xs.size == ys.size == vs.size):
+            raise ValueError("xs, ys, values must have the same length")
+        _check(lib().cddt_update(self.handle, xs.ctypes.data_as(C.c_void_p), ys.ctypes.data_as(C.c_void_p),
+                                 vs.ctypes.data_as(C.c_void_p), xs.size, _stream(stream)))
+
+    # -- inspection ----------------------------------------------------------
+    def info(self) -> dict:
+        s = Stats()
+        _check(lib().cddt_info(self.handle, C.byref(s)))
+        return s.as_dict()
+
+    def slice_table(self):
+        half = self.theta_bins // 2
+        c = np.zeros(half, np.int32)
+        s = np.zeros(half, np.int32)
+        rmin = np.zeros(half, np.int32)
+        nrows = np.zeros(half, np.int32)
+        k = np.zeros(1, np.float32)
+        _check(lib().cddt_slice_table(self.handle, *(a.ctypes.data_as(C.c_void_p) for a in (c, s, rmin, nrows, k))))
+        return c, s, rmin, nrows, k[0]
+
+    def export(self):
+        """(nrows per slice, band lengths, zero points) in canonical order (host numpy)."""
+        st = self.info()
+        rl = np.zeros(st["rows"], np.int32)
+        zz = np.zeros(max(st["zero_points"], 1), np.int32)
+        _check(lib().cddt_export(self.handle, rl.ctypes.data_as(C.c_void_p), zz.ctypes.data_as(C.c_void_p)))
+        return self.slice_table()[3], rl, zz[:st["zero_points"]]
+
+    def grid(self) -> np.ndarray:
+        g = np.zeros((self.height, self.width), np.uint8)
+        _check(lib().cddt_export_grid(self.handle, g.ctypes.data_as(C.c_void_p)))
+        return g
+
+
+def make_filter(m: Map, px, py, pth, offsets, obs, log_table, max_range: int, logw, ranges=None,
+                pair: int | None = None) -> Filter:
+    if pair is None:
+        pair = pair_offset(offsets.cpu().numpy())
+    f = Filter()
+    f.map = m.handle.value
+    f.px, f.py, f.ptheta = px.data_ptr(), py.data_ptr(), pth.data_ptr()
+    f.n_particles = px.numel()
+    f.ray_offsets = offsets.data_ptr()
+    f.n_rays = offsets.numel()
+    f.pair_offset = int(pair)
+    f.obs_ranges = obs.data_ptr()
+    f.log_table = log_table.data_ptr()
+    f.max_range = int(max_range)
+    f.logw_out = logw.data_ptr()
+    f.ranges_out = ranges.data_ptr() if ranges is not None else None
+    return f
+
+
+class Plan:
+    """Many filters in one persistent launch (cddt_plan_*)."""
+
+    def __init__(self, filters, tuning: tuple | None = None, stream=None, keepalive=None):
+        arr = (Filter * len(filters))(*filters)
+        t = Tuning(*tuning, 0) if tuning is not None else None
+        h = C.c_void_p()
+        _check(lib().cddt_plan_create(C.cast(arr, C.c_void_p), len(filters),
+                                      C.byref(t) if t is not None else None, _stream(stream), C.byref(h)))
+        self.handle = h
+        self.n_filters = len(filters)
+        self._keep = keepalive
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().cddt_plan_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def tuning(self):
+        t = Tuning()
+        _check(lib().cddt_plan_get_tuning(self.handle, C.byref(t)))
+        return t.as_tuple()
+
+    @tuning.setter
+    def tuning(self, v):
+        t = Tuning(*v, 0)
+        _check(lib().cddt_plan_set_tuning(self.handle, C.byref(t)))
+
+    def run(self, stream=None):
+        _check(lib().cddt_plan_run(self.handle, _stream(stream)))
+
+    def run_plain(self, stream=None):
+        _check(lib().cddt_plan_run_plain(self.handle, _stream(stream)))
+
+    def capture(self, stream):
+        _check(lib().cddt_plan_capture(self.handle, _stream(stream)))
+
+    def replay(self, stream=None):
+        _check(lib().cddt_plan_replay(self.handle, _stream(stream)))
+
+    def time(self, tuning, reps: int = 5, stream=None) -> float:
+        t = Tuning(*tuning, 0)
+        ms = C.c_float()
+        _check(lib().cddt_plan_time(self.handle, C.byref(t), int(reps), _stream(stream), C.byref(ms)))
+        return float(ms.value)
+
+
+def device_cus() -> int:
+    return int(lib().cddt_device_cus())

@@ -1,0 +1,261 @@
+// Many particle filters in one persistent launch.
+//
+// A plan holds a device table of filter descriptors (map, particles, rays,
+// observations, table, outputs) and the prefix sums of their tile counts.
+// The persistent grid has blocks_per_cu blocks per compute unit; every wave
+// repeatedly takes the next tile index from a 64-bit device counter, finds
+// its filter by binary search over the prefix sums and computes the tile's
+// particle weights with the same per-particle routine as the plain kernel, so
+// the results are identical bit for bit.  A wave leaves when the counter
+// passes the last tile, so the grid always drains.
+//
+// Each run is two kernel launches (counter reset, persistent kernel) and
+// nothing else, so a run can be captured into a hipGraph and replayed.
+#include <algorithm>
+
+#include "query_device.h"
+
+namespace cddt {
+FilterDev filter_dev(const cddt_filter& f);
+cddt_status validate_filter(const cddt_filter& f, const char* who);
+}  // namespace cddt
+
+struct cddt_plan_s {
+  std::vector<cddt_filter> filters;
+  std::vector<cddt::FilterDev> fdev;
+  std::vector<int64_t> prefix;  // n_filters + 1 tile offsets for the current tuning
+  cddt::FilterDev* d_filters = nullptr;
+  int64_t* d_prefix = nullptr;
+  unsigned long long* d_counter = nullptr;
+  cddt_tuning tuning{};
+  int64_t total_tiles = 0;
+  int32_t cus = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace cddt {
+namespace {
+
+__global__ void k_reset_counter(unsigned long long* counter) {
+  if (threadIdx.x == 0) *counter = 0ull;
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__global__ void k_batch(const FilterDev* __restrict__ filters, const int64_t* __restrict__ prefix,
+                        int32_t n_filters, int64_t total_tiles, int32_t ppt,
+                        unsigned long long* __restrict__ counter) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (;;) {
+    uint64_t t = 0;
+    if (lane == 0) t = atomicAdd(counter, 1ull);
+    t = __shfl((unsigned long long)t, 0);
+    t = uniform_u64(t);
+    if (t >= (uint64_t)total_tiles) break;
+    int32_t lo = 0, hi = n_filters;  // prefix[lo] <= t < prefix[hi]
+    while (hi - lo > 1) {
+      int32_t mid = (lo + hi) >> 1;
+      if ((uint64_t)prefix[mid] <= t)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const FilterDev f = filters[lo];
+    const int64_t p0 = (int64_t)(t - (uint64_t)prefix[lo]) * ppt;
+    const int64_t p1 = p0 + ppt < f.n_particles ? p0 + ppt : f.n_particles;
+    for (int64_t p = p0; p < p1; ++p) {
+      float lw = wave_particle_logw(f.map, f.px[p], f.py[p], f.pth[p], f.offsets, f.obs, f.n_rays, f.pair_offset,
+                                    f.table, f.max_range, f.ranges ? f.ranges + p * f.n_rays : nullptr);
+      if (lane == 0) f.logw[p] = lw;
+    }
+  }
+}
+
+cddt_status check_tuning(const cddt_tuning& t) {
+  if (t.particles_per_tile < 1 || t.particles_per_tile > 256)
+    return fail(CDDT_EINVAL, "tuning: particles_per_tile must be in 1..256");
+  if (t.waves_per_block < 1 || t.waves_per_block > 16)
+    return fail(CDDT_EINVAL, "tuning: waves_per_block must be in 1..16");
+  if (t.blocks_per_cu < 1 || t.blocks_per_cu > 32) return fail(CDDT_EINVAL, "tuning: blocks_per_cu must be in 1..32");
+  return CDDT_OK;
+}
+
+cddt_tuning default_tuning() {
+  cddt_tuning t{};
+  t.particles_per_tile = 4;
+  t.waves_per_block = 4;
+  t.blocks_per_cu = 8;
+  return t;
+}
+
+// Recompute tile prefix sums for the plan's tuning and upload them (blocking).
+cddt_status apply_tuning(cddt_plan_s* p, const cddt_tuning& t, hipStream_t st) {
+  CDDT_TRY(check_tuning(t));
+  const int64_t ppt = t.particles_per_tile;
+  p->prefix.assign(p->filters.size() + 1, 0);
+  for (size_t f = 0; f < p->filters.size(); ++f)
+    p->prefix[f + 1] = p->prefix[f] + (p->filters[f].n_particles + ppt - 1) / ppt;
+  p->total_tiles = p->prefix.back();
+  CDDT_HIP(hipMemcpyAsync(p->d_prefix, p->prefix.data(), sizeof(int64_t) * p->prefix.size(), hipMemcpyHostToDevice,
+                          st));
+  CDDT_HIP(hipStreamSynchronize(st));
+  p->tuning = t;
+  return CDDT_OK;
+}
+
+cddt_status launch_plan(cddt_plan_s* p, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, p->d_counter);
+  if (p->total_tiles > 0) {
+    const unsigned blocks = (unsigned)std::max(1, p->cus * p->tuning.blocks_per_cu);
+    const unsigned threads = (unsigned)(kWave * p->tuning.waves_per_block);
+    hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(threads), 0, st, (const FilterDev*)p->d_filters,
+                       (const int64_t*)p->d_prefix, (int32_t)p->filters.size(), p->total_tiles,
+                       p->tuning.particles_per_tile, p->d_counter);
+  }
+  CDDT_HIP(hipGetLastError());
+  return CDDT_OK;
+}
+
+void drop_graph(cddt_plan_s* p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+}
+
+}  // namespace
+}  // namespace cddt
+
+using namespace cddt;
+
+extern "C" {
+
+cddt_status cddt_plan_create(const cddt_filter* filters_h, int32_t n_filters, const cddt_tuning* tuning_h,
+                             void* stream, cddt_plan* out_h) {
+  if (!out_h) return fail(CDDT_EINVAL, "cddt_plan_create: out_h is NULL");
+  *out_h = nullptr;
+  if (!filters_h || n_filters < 1 || n_filters > 65536)
+    return fail(CDDT_EINVAL, "cddt_plan_create: need 1..65536 filters");
+  for (int32_t f = 0; f < n_filters; ++f) CDDT_TRY(validate_filter(filters_h[f], "cddt_plan_create"));
+  cddt_tuning t = tuning_h ? *tuning_h : default_tuning();
+  CDDT_TRY(check_tuning(t));
+  hipStream_t st = (hipStream_t)stream;
+  cddt_plan_s* p = new cddt_plan_s();
+  p->filters.assign(filters_h, filters_h + n_filters);
+  for (auto& f : p->filters) p->fdev.push_back(filter_dev(f));
+  p->cus = cddt_device_cus();
+  if (p->cus <= 0) {
+    delete p;
+    return fail(CDDT_EDEVICE, "cddt_plan_create: cannot query the device");
+  }
+  auto bail = [&](const std::string& msg) {
+    if (p->d_filters) (void)hipFree(p->d_filters);
+    if (p->d_prefix) (void)hipFree(p->d_prefix);
+    if (p->d_counter) (void)hipFree(p->d_counter);
+    delete p;
+    return fail(CDDT_EDEVICE, msg);
+  };
+  if (hipMalloc(&p->d_filters, sizeof(FilterDev) * n_filters) != hipSuccess ||
+      hipMalloc(&p->d_prefix, sizeof(int64_t) * (n_filters + 1)) != hipSuccess ||
+      hipMalloc(&p->d_counter, sizeof(unsigned long long)) != hipSuccess)
+    return bail("cddt_plan_create: hipMalloc failed");
+  if (hipMemcpyAsync(p->d_filters, p->fdev.data(), sizeof(FilterDev) * n_filters, hipMemcpyHostToDevice, st) !=
+      hipSuccess)
+    return bail("cddt_plan_create: descriptor upload failed");
+  cddt_status s = apply_tuning(p, t, st);
+  if (s != CDDT_OK) return bail(cddt_last_error());
+  *out_h = p;
+  return CDDT_OK;
+}
+
+cddt_status cddt_plan_set_tuning(cddt_plan p, const cddt_tuning* tuning_h) {
+  if (!p || !tuning_h) return fail(CDDT_EINVAL, "cddt_plan_set_tuning: NULL argument");
+  CDDT_TRY(check_tuning(*tuning_h));
+  drop_graph(p);
+  return apply_tuning(p, *tuning_h, nullptr);
+}
+
+cddt_status cddt_plan_get_tuning(cddt_plan p, cddt_tuning* tuning_h) {
+  if (!p || !tuning_h) return fail(CDDT_EINVAL, "cddt_plan_get_tuning: NULL argument");
+  *tuning_h = p->tuning;
+  return CDDT_OK;
+}
+
+cddt_status cddt_plan_run(cddt_plan p, void* stream) {
+  if (!p) return fail(CDDT_EINVAL, "cddt_plan_run: plan is NULL");
+  return launch_plan(p, (hipStream_t)stream);
+}
+
+cddt_status cddt_plan_capture(cddt_plan p, void* stream) {
+  if (!p) return fail(CDDT_EINVAL, "cddt_plan_capture: plan is NULL");
+  if (!stream) return fail(CDDT_EINVAL, "cddt_plan_capture: capture needs a non-default stream");
+  hipStream_t st = (hipStream_t)stream;
+  drop_graph(p);
+  CDDT_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  cddt_status s = launch_plan(p, st);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(st, &g);
+  if (s != CDDT_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return fail(CDDT_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  p->graph = g;
+  CDDT_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+  return CDDT_OK;
+}
+
+cddt_status cddt_plan_replay(cddt_plan p, void* stream) {
+  if (!p) return fail(CDDT_EINVAL, "cddt_plan_replay: plan is NULL");
+  if (!p->exec) return fail(CDDT_EINVAL, "cddt_plan_replay: no captured graph");
+  CDDT_HIP(hipGraphLaunch(p->exec, (hipStream_t)stream));
+  return CDDT_OK;
+}
+
+cddt_status cddt_plan_time(cddt_plan p, const cddt_tuning* tuning_h, int32_t reps, void* stream, float* ms_h) {
+  if (!p || !ms_h || reps < 1) return fail(CDDT_EINVAL, "cddt_plan_time: bad argument");
+  hipStream_t st = (hipStream_t)stream;
+  cddt_tuning keep = p->tuning;
+  if (tuning_h) CDDT_TRY(apply_tuning(p, *tuning_h, st));
+  hipEvent_t a, b;
+  CDDT_HIP(hipEventCreate(&a));
+  CDDT_HIP(hipEventCreate(&b));
+  cddt_status s = launch_plan(p, st);  // warm-up
+  if (s == CDDT_OK) {
+    (void)hipEventRecord(a, st);
+    for (int32_t r = 0; r < reps && s == CDDT_OK; ++r) s = launch_plan(p, st);
+    (void)hipEventRecord(b, st);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    *ms_h = ms / reps;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (tuning_h) CDDT_TRY(apply_tuning(p, keep, st));
+  return s;
+}
+
+cddt_status cddt_plan_run_plain(cddt_plan p, void* stream) {
+  if (!p) return fail(CDDT_EINVAL, "cddt_plan_run_plain: plan is NULL");
+  for (auto& f : p->fdev) CDDT_TRY(launch_weight(f, (hipStream_t)stream));
+  return CDDT_OK;
+}
+
+cddt_status cddt_plan_destroy(cddt_plan p) {
+  if (!p) return CDDT_OK;
+  (void)hipDeviceSynchronize();
+  drop_graph(p);
+  if (p->d_filters) (void)hipFree(p->d_filters);
+  if (p->d_prefix) (void)hipFree(p->d_prefix);
+  if (p->d_counter) (void)hipFree(p->d_counter);
+  delete p;
+  return CDDT_OK;
+}
+
+}  // extern "C"

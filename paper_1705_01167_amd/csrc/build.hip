@@ -1,0 +1,399 @@
+// CDDT construction on the GPU (Sec. IV-A: edge map by erosion, projection of
+// every edge cell into every stored slice, one sorted zero-point list per band).
+//
+// Pipeline (one stream):
+//   k_edges    (x2)  8-neighbour erosion test per cell; a count pass, then a
+//                    compaction pass (wave ballot + one atomic per wave).
+//   k_project  (count) per (slice, edge cell): the bands its rotated square
+//                    covers; atomic per-band counters.
+//   scan             per-band capacity = length + slack; exclusive scan gives
+//                    each band's start (3-phase block scan, 64-bit totals).
+//   k_project  (fill) scatter each zero point into its bands through per-band
+//                    cursors (order inside a band is arbitrary here).
+//   k_sort_small     one wave per band: bands of <= 64 sorted in registers
+//                    (bitonic over lanes); longer bands are queued.
+//   k_sort_large     persistent blocks take queued bands; bitonic network in
+//                    LDS (<= 16384 values) or in place in global memory.
+// Each band ends as the ascending multiset of its zero points, which is unique,
+// so the result does not depend on atomic ordering.
+#include <climits>
+
+#include "cddt_common.h"
+
+namespace cddt {
+namespace {
+
+constexpr int kScanThreads = 1024;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kLdsSortCap = 16384;
+
+// Small device scalars used during a build.
+struct BuildCounters {
+  uint32_t edges;
+  uint32_t big;
+  uint64_t total_cap;
+  uint64_t total_len;
+  uint64_t max_len;
+};
+
+__device__ __forceinline__ bool edge_cell(const uint8_t* __restrict__ occ, int w, int h, int i, int j,
+                                          int full) {
+  if (occ[(size_t)j * w + i] == 0) return false;
+  if (full) return true;
+  for (int dj = -1; dj <= 1; ++dj) {
+    int b = j + dj;
+    if (b < 0 || b >= h) return true;  // off-map neighbour counts as free
+    for (int di = -1; di <= 1; ++di) {
+      int a = i + di;
+      if (a < 0 || a >= w) return true;
+      if (occ[(size_t)b * w + a] == 0) return true;
+    }
+  }
+  return false;
+}
+
+// Edge cells are packed as i | j << 16 (both < 2^14).
+__global__ void k_edges(const uint8_t* __restrict__ occ, int w, int h, int full,
+                        uint32_t* __restrict__ list, BuildCounters* ctr, int write) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool e = false;
+  int i = 0, j = 0;
+  if (idx < (int64_t)w * h) {
+    j = (int)(idx / w);
+    i = (int)(idx - (int64_t)j * w);
+    e = edge_cell(occ, w, h, i, j, full);
+  }
+  uint64_t mask = __ballot(e);
+  int lane = threadIdx.x & 63;
+  uint32_t base = 0;
+  if (lane == 0 && mask) base = atomicAdd(&ctr->edges, (uint32_t)__popcll(mask));
+  base = __shfl(base, 0);
+  if (write && e) {
+    uint64_t below = mask & ((1ull << lane) - 1ull);
+    list[base + (uint32_t)__popcll(below)] = (uint32_t)i | ((uint32_t)j << 16);
+  }
+}
+
+// Per (slice = blockIdx.y, edge cell): count (fill == 0) or scatter (fill == 1).
+__global__ void k_project(const SliceDev* __restrict__ slices, const uint32_t* __restrict__ cells,
+                          uint32_t n_cells, uint32_t* __restrict__ cnt,
+                          const int2* __restrict__ hdr, int32_t* __restrict__ zeros, int fill) {
+  uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_cells) return;
+  const SliceDev sl = slices[blockIdx.y];
+  const uint32_t packed = cells[e];
+  const int64_t i2 = 2 * (int64_t)(packed & 0xffffu) + 1;
+  const int64_t j2 = 2 * (int64_t)(packed >> 16) + 1;
+  const int64_t yc = j2 * sl.c - i2 * sl.s;
+  const int64_t hs = (int64_t)abs(sl.c) + (int64_t)abs(sl.s);
+  const int32_t lo = (int32_t)((yc - hs) >> 31);
+  const int32_t hi = (int32_t)((yc + hs - 1) >> 31);
+  const int32_t z = (int32_t)((i2 * sl.c + j2 * sl.s) >> 15);
+  for (int32_t r = lo; r <= hi; ++r) {
+    const int32_t row = sl.row_base + (r - sl.row_min);
+    if (!fill) {
+      atomicAdd(&cnt[row], 1u);
+    } else {
+      uint32_t pos = atomicAdd(&cnt[row], 1u);
+      zeros[(uint32_t)hdr[row].x + pos] = z;
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t slack_of(uint32_t len, int no_slack) {
+  return no_slack ? 0u : 8u + (len >> 3);
+}
+
+// Inclusive scan of one value per thread across the block (uint64).
+__device__ uint64_t block_inclusive_scan(uint64_t v, uint64_t* wave_tot) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint64_t t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  if (lane == 63) wave_tot[wid] = v;
+  __syncthreads();
+  if (wid == 0) {
+    uint64_t t = lane < nw ? wave_tot[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      uint64_t u = __shfl_up(t, o);
+      if (lane >= o) t += u;
+    }
+    if (lane < nw) wave_tot[lane] = t;
+  }
+  __syncthreads();
+  if (wid > 0) v += wave_tot[wid - 1];
+  __syncthreads();
+  return v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_sum(const uint32_t* __restrict__ cnt, int64_t n,
+                                                           int no_slack, uint64_t* __restrict__ tile_sum) {
+  __shared__ uint64_t wt[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) {
+      uint32_t c = cnt[base + k];
+      s += c + slack_of(c, no_slack);
+    }
+  uint64_t inc = block_inclusive_scan(s, wt);
+  if (threadIdx.x == blockDim.x - 1) tile_sum[blockIdx.x] = inc;
+}
+
+// Single block: exclusive scan of the tile sums, total capacity into ctr.
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(uint64_t* __restrict__ tile_sum, int64_t ntiles,
+                                                             BuildCounters* ctr) {
+  __shared__ uint64_t wt[kScanThreads / 64];
+  __shared__ uint64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t b = 0; b < ntiles; b += kScanThreads) {
+    int64_t t = b + threadIdx.x;
+    uint64_t v = t < ntiles ? tile_sum[t] : 0;
+    uint64_t inc = block_inclusive_scan(v, wt);
+    uint64_t c = carry;
+    if (t < ntiles) tile_sum[t] = c + inc - v;
+    __syncthreads();
+    if (threadIdx.x == blockDim.x - 1) carry = c + inc;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ctr->total_cap = carry;
+}
+
+// Band starts and capacities; cnt is reset to 0 to serve as the fill cursor.
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint32_t* __restrict__ cnt, int64_t n, int no_slack,
+                                                             const uint64_t* __restrict__ tile_off,
+                                                             int2* __restrict__ hdr,
+                                                             uint32_t* __restrict__ cap,
+                                                             BuildCounters* ctr) {
+  __shared__ uint64_t wt[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t len[kScanItems];
+  uint64_t s = 0, lsum = 0;
+  uint32_t lmax = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    len[k] = base + k < n ? cnt[base + k] : 0u;
+    s += len[k] + (base + k < n ? slack_of(len[k], no_slack) : 0u);
+    lsum += len[k];
+    lmax = len[k] > lmax ? len[k] : lmax;
+  }
+  uint64_t off = block_inclusive_scan(s, wt) - s + tile_off[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) {
+      uint32_t c = len[k] + slack_of(len[k], no_slack);
+      hdr[base + k] = make_int2((int32_t)(uint32_t)off, (int32_t)len[k]);
+      cap[base + k] = c;
+      cnt[base + k] = 0;
+      off += c;
+    }
+  }
+  // block totals of lengths and max length: one atomic per wave
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lsum += __shfl_xor(lsum, o);
+    uint32_t t = __shfl_xor(lmax, o);
+    lmax = t > lmax ? t : lmax;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (lsum) atomicAdd((unsigned long long*)&ctr->total_len, (unsigned long long)lsum);
+    if (lmax) atomicMax((unsigned long long*)&ctr->max_len, (unsigned long long)lmax);
+  }
+}
+
+// Bitonic sort of one value per lane across a wave (ascending).
+__device__ __forceinline__ int32_t wave_bitonic(int32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      int32_t p = __shfl_xor(v, j);
+      bool asc = (lane & k) == 0;
+      bool low = (lane & j) == 0;
+      v = (low == asc) ? min(v, p) : max(v, p);
+    }
+  }
+  return v;
+}
+
+__global__ void k_sort_small(const int2* __restrict__ hdr, int32_t* __restrict__ zeros, int64_t nrows,
+                             uint32_t* __restrict__ big_list, BuildCounters* ctr) {
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= nrows) return;
+  const int lane = threadIdx.x & 63;
+  const int2 hd = hdr[row];
+  if (hd.y <= 1) return;
+  if (hd.y > 64) {
+    if (lane == 0) big_list[atomicAdd(&ctr->big, 1u)] = (uint32_t)row;
+    return;
+  }
+  int32_t* z = zeros + (uint32_t)hd.x;
+  int32_t v = lane < hd.y ? z[lane] : INT_MAX;
+  v = wave_bitonic(v);
+  if (lane < hd.y) z[lane] = v;
+}
+
+// Sorting network over a[0, len) with every comparator ascending (min to the
+// lower index); indices >= len behave as +infinity and are never touched.
+template <typename Ptr>
+__device__ void block_sort_network(Ptr a, int32_t len) {
+  int32_t p2 = 1;
+  while (p2 < len) p2 <<= 1;
+  for (int32_t k = 2; k <= p2; k <<= 1) {
+    for (int32_t j = k >> 1; j > 0; j >>= 1) {
+      const bool flip = j == (k >> 1);
+      for (int32_t t = threadIdx.x; t < (p2 >> 1); t += blockDim.x) {
+        // t-th pair: insert a zero bit at position log2(j)
+        int32_t lo = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+        int32_t hi = flip ? (lo ^ (k - 1)) : (lo | j);
+        if (hi < len) {
+          int32_t x = a[lo], y = a[hi];
+          if (y < x) {
+            a[lo] = y;
+            a[hi] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sort_large(const int2* __restrict__ hdr, int32_t* __restrict__ zeros,
+                                                    const uint32_t* __restrict__ big_list,
+                                                    const BuildCounters* ctr) {
+  __shared__ int32_t buf[kLdsSortCap];
+  const uint32_t nbig = ctr->big;
+  for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
+    const int2 hd = hdr[big_list[b]];
+    int32_t* z = zeros + (uint32_t)hd.x;
+    if (hd.y <= kLdsSortCap) {
+      for (int32_t t = threadIdx.x; t < hd.y; t += blockDim.x) buf[t] = z[t];
+      __syncthreads();
+      block_sort_network(buf, hd.y);
+      for (int32_t t = threadIdx.x; t < hd.y; t += blockDim.x) z[t] = buf[t];
+    } else {
+      block_sort_network(z, hd.y);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// RAII holder for build temporaries.
+struct Temp {
+  Allocator* a;
+  void* p = nullptr;
+  explicit Temp(Allocator* al) : a(al) {}
+  ~Temp() {
+    if (p) a->release(p);
+  }
+  cddt_status get(size_t bytes, const char* what) { return a->alloc(&p, bytes ? bytes : 16, what); }
+};
+
+unsigned grid_for(int64_t n, int threads) {
+  int64_t b = (n + threads - 1) / threads;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+void free_structure(cddt_map_s* m) {
+  if (m->d_hdr) m->alloc.release(m->d_hdr);
+  if (m->d_cap) m->alloc.release(m->d_cap);
+  if (m->d_zeros) m->alloc.release(m->d_zeros);
+  m->d_hdr = nullptr;
+  m->d_cap = nullptr;
+  m->d_zeros = nullptr;
+}
+
+// Builds hdr / cap / zeros from m->d_occ and m->d_slices.  Blocks on `st`.
+cddt_status build_structure(cddt_map_s* m, hipStream_t st) {
+  free_structure(m);
+  const int64_t cells = (int64_t)m->w * m->h;
+  const int64_t R = m->rows;
+  Temp ctr_t(&m->alloc), edges_t(&m->alloc), cnt_t(&m->alloc), tiles_t(&m->alloc), big_t(&m->alloc);
+  CDDT_TRY(ctr_t.get(sizeof(BuildCounters), "build counters"));
+  BuildCounters* ctr = (BuildCounters*)ctr_t.p;
+  CDDT_HIP(hipMemsetAsync(ctr, 0, sizeof(BuildCounters), st));
+  const int full = (m->flags & CDDT_FLAG_FULL_MAP) ? 1 : 0;
+  const int no_slack = (m->flags & CDDT_FLAG_STATIC) ? 1 : 0;
+
+  // 1. edge map: count, then compact
+  hipLaunchKernelGGL(k_edges, dim3(grid_for(cells, 256)), dim3(256), 0, st, m->d_occ, m->w, m->h, full,
+                     (uint32_t*)nullptr, ctr, 0);
+  CDDT_HIP(hipGetLastError());
+  BuildCounters hc{};
+  CDDT_HIP(hipMemcpyAsync(&hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
+  CDDT_HIP(hipStreamSynchronize(st));
+  const uint32_t n_edges = hc.edges;
+  m->edge_cells = n_edges;
+  CDDT_TRY(edges_t.get((size_t)n_edges * 4, "edge list"));
+  CDDT_HIP(hipMemsetAsync(ctr, 0, sizeof(BuildCounters), st));
+  if (n_edges)
+    hipLaunchKernelGGL(k_edges, dim3(grid_for(cells, 256)), dim3(256), 0, st, m->d_occ, m->w, m->h, full,
+                       (uint32_t*)edges_t.p, ctr, 1);
+
+  // 2. per-band counts
+  CDDT_TRY(cnt_t.get((size_t)R * 4, "band counters"));
+  uint32_t* cnt = (uint32_t*)cnt_t.p;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(R, 256) < 65536 ? grid_for(R, 256) : 65536), dim3(256), 0, st,
+                     cnt, R, 0u);
+  if (n_edges)
+    hipLaunchKernelGGL(k_project, dim3(grid_for(n_edges, 256), m->half), dim3(256), 0, st, m->d_slices,
+                       (const uint32_t*)edges_t.p, n_edges, cnt, (const int2*)nullptr, (int32_t*)nullptr, 0);
+  CDDT_HIP(hipGetLastError());
+
+  // 3. band layout
+  CDDT_TRY(m->alloc.alloc((void**)&m->d_hdr, (size_t)R * sizeof(int2), "band headers"));
+  CDDT_TRY(m->alloc.alloc((void**)&m->d_cap, (size_t)R * 4, "band capacities"));
+  const int64_t ntiles = (R + kScanTile - 1) / kScanTile;
+  CDDT_TRY(tiles_t.get((size_t)ntiles * 8, "scan tiles"));
+  uint64_t* tiles = (uint64_t*)tiles_t.p;
+  hipLaunchKernelGGL(k_tile_sum, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, cnt, R, no_slack, tiles);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, st, tiles, ntiles, ctr);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, cnt, R, no_slack,
+                     (const uint64_t*)tiles, m->d_hdr, m->d_cap, ctr);
+  CDDT_HIP(hipGetLastError());
+  CDDT_HIP(hipMemcpyAsync(&hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
+  CDDT_HIP(hipStreamSynchronize(st));
+  if (hc.total_cap >= (1ull << 32)) {
+    free_structure(m);
+    return fail(CDDT_ENOMEM, "structure needs more than 2^32 zero-point slots");
+  }
+  m->capacity = (int64_t)hc.total_cap;
+  m->zero_points = (int64_t)hc.total_len;
+  m->max_row_len = (int64_t)hc.max_len;
+
+  // 4. fill and sort
+  cddt_status st_alloc = m->alloc.alloc((void**)&m->d_zeros, (size_t)(m->capacity ? m->capacity : 1) * 4,
+                                        "zero points");
+  if (st_alloc != CDDT_OK) {
+    free_structure(m);
+    return st_alloc;
+  }
+  if (n_edges)
+    hipLaunchKernelGGL(k_project, dim3(grid_for(n_edges, 256), m->half), dim3(256), 0, st, m->d_slices,
+                       (const uint32_t*)edges_t.p, n_edges, cnt, (const int2*)m->d_hdr, m->d_zeros, 1);
+  CDDT_TRY(big_t.get((size_t)R * 4, "long-band list"));
+  hipLaunchKernelGGL(k_sort_small, dim3(grid_for(R, 4)), dim3(256), 0, st, (const int2*)m->d_hdr, m->d_zeros, R,
+                     (uint32_t*)big_t.p, ctr);
+  hipLaunchKernelGGL(k_sort_large, dim3(2048), dim3(256), 0, st, (const int2*)m->d_hdr, m->d_zeros,
+                     (const uint32_t*)big_t.p, (const BuildCounters*)ctr);
+  CDDT_HIP(hipGetLastError());
+  CDDT_HIP(hipStreamSynchronize(st));
+  return CDDT_OK;
+}
+
+}  // namespace cddt

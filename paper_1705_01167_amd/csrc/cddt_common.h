@@ -1,0 +1,133 @@
+// Internal declarations shared by the libcddt translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cddt.h"
+
+namespace cddt {
+
+// One stored slice: direction (2^30 fixed point), lowest band index, and the
+// index of its first band in the global band arrays.
+struct SliceDev {
+  int32_t c, s, row_min, row_base;
+};
+
+// Everything a query needs about one map, passed by value to kernels.
+struct MapDev {
+  const uint8_t* occ;        // W*H grid, row-major, nonzero = occupied
+  const SliceDev* slices;    // n/2 entries
+  const int2* hdr;           // per band: {start, len} into zeros
+  const int32_t* zeros;      // zero points (Q16), each band ascending
+  int32_t w, h, n, half;
+  float k_scale;             // (float)(n / (2 pi))
+  int32_t pad;
+};
+
+// One filter of a batched step (device copy of cddt_filter plus its map).
+struct FilterDev {
+  MapDev map;
+  const float* px;
+  const float* py;
+  const float* pth;
+  const float* offsets;
+  const int32_t* obs;
+  const float* table;
+  float* logw;
+  int32_t* ranges;
+  int64_t n_particles;
+  int32_t n_rays, pair_offset, max_range, pad;
+};
+
+constexpr int kWave = 64;
+constexpr int kMaxSide = 16384;
+constexpr int kMaxBins = 8192;
+constexpr int kMaxRays = 1024;
+
+// ---------------------------------------------------------------------------
+// Error reporting
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+cddt_status fail(cddt_status code, const std::string& msg);
+
+#define CDDT_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return ::cddt::fail(CDDT_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CDDT_TRY(expr)                 \
+  do {                                 \
+    cddt_status s_ = (expr);           \
+    if (s_ != CDDT_OK) return s_;      \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Device memory through the caller's allocator (or hipMalloc)
+// ---------------------------------------------------------------------------
+struct Allocator {
+  cddt_allocator cb{};
+  bool custom = false;
+  cddt_status alloc(void** p, size_t bytes, const char* what);
+  void release(void* p);
+};
+
+// Growable device scratch owned by a map.
+struct Scratch {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+cddt_status ensure(Allocator& a, Scratch& s, size_t bytes, const char* what);
+
+}  // namespace cddt
+
+// Host-side state of a map.
+struct cddt_map_s {
+  int32_t w = 0, h = 0, n = 0, half = 0;
+  uint32_t flags = 0;
+  cddt::Allocator alloc;
+  float k_scale = 0.f;
+  std::vector<int32_t> c, s, row_min, nrows, row_base;
+  int64_t rows = 0;
+  uint8_t* d_occ = nullptr;
+  cddt::SliceDev* d_slices = nullptr;
+  int2* d_hdr = nullptr;         // {start, len}
+  uint32_t* d_cap = nullptr;     // per band capacity (len + slack)
+  int32_t* d_zeros = nullptr;
+  int64_t capacity = 0, zero_points = 0, edge_cells = 0, max_row_len = 0, rebuilds = 0;
+  int64_t device_bytes = 0;
+  // update scratch
+  cddt::Scratch upd_ops, upd_changed, upd_cand, upd_edits, upd_rec, upd_rowcnt, upd_misc;
+  cddt::MapDev dev() const {
+    cddt::MapDev m;
+    m.occ = d_occ;
+    m.slices = d_slices;
+    m.hdr = d_hdr;
+    m.zeros = d_zeros;
+    m.w = w;
+    m.h = h;
+    m.n = n;
+    m.half = half;
+    m.k_scale = k_scale;
+    m.pad = 0;
+    return m;
+  }
+};
+
+namespace cddt {
+// build.hip
+cddt_status build_structure(cddt_map_s* m, hipStream_t st);
+void free_structure(cddt_map_s* m);
+// query.hip
+cddt_status launch_cast(const MapDev& m, const float* x, const float* y, const float* th, int64_t n,
+                        int32_t max_range, int32_t* out, hipStream_t st);
+cddt_status launch_weight(const FilterDev& f, hipStream_t st);
+// update.hip
+cddt_status apply_update(cddt_map_s* m, const int32_t* xs, const int32_t* ys, const uint8_t* vals,
+                         int64_t n_ops, hipStream_t st);
+}  // namespace cddt

@@ -1,0 +1,51 @@
+// Plain query kernels: one lane per ray (cast) and one wave per particle
+// (beam-model weight).  The per-ray and per-particle arithmetic lives in
+// query_device.h and is shared with the persistent batched kernel.
+#include "query_device.h"
+
+namespace cddt {
+namespace {
+
+constexpr int kCastThreads = 256;
+constexpr int kWeightThreads = 256;  // 4 particles (waves) per block
+
+__global__ __launch_bounds__(kCastThreads) void k_cast(MapDev m, const float* __restrict__ x,
+                                                       const float* __restrict__ y,
+                                                       const float* __restrict__ th, int64_t n,
+                                                       int32_t max_range, int32_t* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    out[i] = cast_one(m, x[i], y[i], th[i], max_range);
+}
+
+__global__ __launch_bounds__(kWeightThreads) void k_weight(FilterDev f) {
+  const int64_t p = (int64_t)blockIdx.x * (kWeightThreads / kWave) + (threadIdx.x >> 6);
+  if (p >= f.n_particles) return;  // whole wave leaves together
+  float lw = wave_particle_logw(f.map, f.px[p], f.py[p], f.pth[p], f.offsets, f.obs, f.n_rays, f.pair_offset,
+                                f.table, f.max_range, f.ranges ? f.ranges + p * f.n_rays : nullptr);
+  if ((threadIdx.x & 63) == 0) f.logw[p] = lw;
+}
+
+}  // namespace
+
+cddt_status launch_cast(const MapDev& m, const float* x, const float* y, const float* th, int64_t n,
+                        int32_t max_range, int32_t* out, hipStream_t st) {
+  if (n == 0) return CDDT_OK;
+  int64_t blocks = (n + kCastThreads - 1) / kCastThreads;
+  if (blocks > (1 << 20)) blocks = 1 << 20;
+  hipLaunchKernelGGL(k_cast, dim3((unsigned)blocks), dim3(kCastThreads), 0, st, m, x, y, th, n, max_range, out);
+  CDDT_HIP(hipGetLastError());
+  return CDDT_OK;
+}
+
+cddt_status launch_weight(const FilterDev& f, hipStream_t st) {
+  if (f.n_particles == 0) return CDDT_OK;
+  const int per_block = kWeightThreads / kWave;
+  int64_t blocks = (f.n_particles + per_block - 1) / per_block;
+  if (blocks > 0x7fffffffLL) return fail(CDDT_EINVAL, "too many particles for one launch");
+  hipLaunchKernelGGL(k_weight, dim3((unsigned)blocks), dim3(kWeightThreads), 0, st, f);
+  CDDT_HIP(hipGetLastError());
+  return CDDT_OK;
+}
+
+}  // namespace cddt

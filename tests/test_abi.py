@@ -1,0 +1,66 @@
+"""The C ABI library loads and exports every function cddt.h declares.
+
+CPU only: no call here reaches the GPU (validation failures return before any
+HIP call; cddt_pair_offset is host-only).
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cddt.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cddt_[a-z_]+)\s*\(", text)))
+
+
+def _lib():
+    from paper_1705_01167_amd import cddt
+    if not os.path.exists(cddt.LIB_PATH):
+        pytest.fail("libcddt.so is not built (run __graft_entry__.build())")
+    return cddt
+
+
+def test_every_declared_symbol_is_exported():
+    cddt = _lib()
+    names = _declared()
+    assert len(names) >= 25
+    L = C.CDLL(cddt.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # and the binding covers all of them
+    assert set(names) <= set(cddt.SIGNATURES)
+
+
+def test_validation_needs_no_gpu():
+    cddt = _lib()
+    L = cddt.lib()
+    out = C.c_void_p()
+    occ = C.c_void_p(1)   # never dereferenced: validation fails first
+    assert L.cddt_create(occ, 0, 5, 8, 0, None, None, C.byref(out)) == cddt.EINVAL
+    assert b"width" in L.cddt_last_error()
+    assert L.cddt_create(occ, 5, 5, 7, 0, None, None, C.byref(out)) == cddt.EINVAL
+    assert L.cddt_create(occ, 5, 5, 8192 + 2, 0, None, None, C.byref(out)) == cddt.EINVAL
+    assert L.cddt_create(occ, 5, 16385, 8, 0, None, None, C.byref(out)) == cddt.EINVAL
+    assert L.cddt_create(occ, 5, 5, 8, 1 << 7, None, None, C.byref(out)) == cddt.EINVAL
+    assert L.cddt_create(None, 5, 5, 8, 0, None, None, C.byref(out)) == cddt.EINVAL
+    assert not out.value
+    assert L.cddt_cast(None, None, None, None, 1, 5, None, None) == cddt.EINVAL
+    assert L.cddt_update(None, None, None, None, 1, None) == cddt.EINVAL
+    assert L.cddt_destroy(None) == cddt.OK
+    assert L.cddt_plan_create(None, 0, None, None, C.byref(out)) == cddt.EINVAL
+
+
+def test_pair_offset_host_helper():
+    cddt = _lib()
+    from paper_1705_01167_amd import workloads as wl
+    assert cddt.pair_offset(wl.ray_offsets(61)) == 40
+    assert cddt.pair_offset(wl.ray_offsets(7, fov=np.pi / 2)) == 0
+    assert cddt.pair_offset(np.array([0.0, np.pi], np.float32)) == 1
+    assert cddt.pair_offset(np.array([0.5], np.float32)) == 0

@@ -1,0 +1,293 @@
+"""GPU parity: libcddt (HIP) against the CPU oracle, element by element.
+
+Ranges and exported structures must be bit-identical; log-weights agree within
+1e-5 * max(1, |L|) of the oracle's double sum.  Inputs come from the seeded
+generators only.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ref as oref
+from paper_1705_01167_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-5
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(a, dtype=None):
+    torch = _torch()
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _gpu_map(occ, n, **kw):
+    from paper_1705_01167_amd import cddt
+    return cddt.Map(_dev(occ), n, **kw)
+
+
+def _expand(px, py, pth, off):
+    """Per-ray SoA of (x, y, fl(theta + offset)) for particle p, ray r at index p*R + r."""
+    R = off.size
+    x = np.repeat(px, R)
+    y = np.repeat(py, R)
+    th = (np.repeat(pth, R) + np.tile(off, px.size)).astype(np.float32)
+    return x, y, th
+
+
+def _check_structure(gm, rm):
+    g_nrows, g_len, g_z = gm.export()
+    r_nrows, r_len, r_z = rm.export()
+    c, s, rmin, nrows, k = gm.slice_table()
+    oc, os_, ormin, onrows, ok = rm.tables()
+    assert (c == oc).all() and (s == os_).all() and (rmin == ormin).all() and (nrows == onrows).all()
+    assert k == ok
+    assert (g_len == r_len).all()
+    assert (g_z == r_z).all()
+    info = gm.info()
+    assert info["zero_points"] == r_z.size and info["edge_cells"] == rm.edge_count
+
+
+def test_small_rect_map_full():
+    """256^2 rectangles map, 108 bins, 1000 particles x 61 rays: every ray and weight."""
+    torch = _torch()
+    _say("small rect map: build")
+    occ = wl.rect_map(wl.rng_for(wl.SMALL, wl.S_MAP))
+    n, M = 108, 500
+    rm = oref.RefCDDT(occ, n)
+    gm = _gpu_map(occ, n)
+    _check_structure(gm, rm)
+    px, py, pth = wl.free_poses(wl.rng_for(wl.SMALL, wl.S_POSES), occ, 1000)
+    off = wl.ray_offsets(61)
+    x, y, th = _expand(px, py, pth, off)
+    _say("small rect map: cast")
+    want = rm.cast(x, y, th, M, threads=8)
+    got = gm.cast(_dev(x), _dev(y), _dev(th), M).cpu().numpy()
+    assert (got == want).all(), f"{(got != want).sum()} rays differ"
+    table = wl.beam_table(M, wl.beam_params(wl.rng_for(wl.SMALL, wl.S_TABLE)))
+    obs, _ = wl.observations(wl.rng_for(wl.SMALL, wl.S_OBS), occ, off, M)
+    _say("small rect map: weight")
+    ref_lw, ref_r = rm.weight(px, py, pth, off, obs, table, M, threads=8, want_ranges=True)
+    lw, rr = gm.weight(_dev(px), _dev(py), _dev(pth), _dev(off), _dev(obs), _dev(table), M, ranges=True)
+    assert (rr.cpu().numpy() == ref_r).all()
+    assert (rr.cpu().numpy().ravel() == got).all()   # fused ranges == plain cast ranges
+    lw = lw.cpu().numpy().astype(np.float64)
+    assert (np.abs(lw - ref_lw) <= RTOL * np.maximum(1.0, np.abs(ref_lw))).all()
+    # pairing on / off gives identical bits
+    lw0 = gm.weight(_dev(px), _dev(py), _dev(pth), _dev(off), _dev(obs), _dev(table), M, pair=0)
+    lw40 = gm.weight(_dev(px), _dev(py), _dev(pth), _dev(off), _dev(obs), _dev(table), M, pair=40)
+    assert torch.equal(lw0, lw40)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_tiny_maps(seed):
+    """Random small maps, all flags, awkward bins, off-map/NaN/huge queries: exact."""
+    rng = wl.rng_for(301, seed)
+    w, h = int(rng.integers(1, 70)), int(rng.integers(1, 70))
+    occ = wl.random_map(rng, w, h, float(rng.uniform(0.0, 0.6)))
+    n = int(rng.choice([2, 4, 6, 8, 12, 36, 108, 200, 360, 1000]))
+    full = bool(rng.integers(0, 2))
+    static = bool(rng.integers(0, 2))
+    M = int(rng.choice([0, 1, 7, 100, 65535]))
+    _say(f"tiny map seed={seed} {w}x{h} n={n} full={full} static={static} M={M}")
+    rm = oref.RefCDDT(occ, n, full_map=full)
+    gm = _gpu_map(occ, n, full_map=full, static=static)
+    _check_structure(gm, rm)
+    k = 20000 + int(rng.integers(0, 77))   # ragged tail
+    x = rng.uniform(-2, w + 2, k).astype(np.float32)
+    y = rng.uniform(-2, h + 2, k).astype(np.float32)
+    th = rng.uniform(-40, 40, k).astype(np.float32)
+    x[:5] = [np.nan, np.inf, -0.0, np.float32(w), np.float32(w) - np.float32(1e-3)]
+    th[5:9] = [np.nan, np.inf, 1e6, -1e7]
+    # axis-aligned bins at cell-edge coordinates
+    x[9:200] = np.floor(x[9:200])
+    th[9:200] = (2 * math.pi * rng.integers(0, 4, 191) / 4).astype(np.float32)
+    want = rm.cast(x, y, th, M, threads=4)
+    got = gm.cast(_dev(x), _dev(y), _dev(th), M).cpu().numpy()
+    assert (got == want).all(), f"{(got != want).sum()} rays differ"
+
+
+def test_building_floor_2000():
+    """2000^2 room/corridor floor, 200 bins, 2500 particles x 61 rays, fused beam model."""
+    _say("floor 2000: generate")
+    occ = wl.building_map(wl.rng_for(wl.FLOOR, wl.S_MAP), 2000, 2000)
+    n, M = 200, 500
+    _say("floor 2000: oracle build")
+    rm = oref.RefCDDT(occ, n, threads=8)
+    _say("floor 2000: gpu build")
+    gm = _gpu_map(occ, n)
+    _check_structure(gm, rm)
+    off = wl.ray_offsets(61)
+    px, py, pth = wl.free_poses(wl.rng_for(wl.FLOOR, wl.S_POSES), occ, 2500)
+    table = wl.beam_table(M, wl.beam_params(wl.rng_for(wl.FLOOR, wl.S_TABLE)))
+    obs, _ = wl.observations(wl.rng_for(wl.FLOOR, wl.S_OBS), occ, off, M)
+    _say("floor 2000: weights")
+    ref_lw, ref_r = rm.weight(px, py, pth, off, obs, table, M, threads=8, want_ranges=True)
+    lw, rr = _gpu_map_weight(gm, px, py, pth, off, obs, table, M)
+    assert (rr == ref_r).all(), f"{(rr != ref_r).sum()} ranges differ"
+    assert (np.abs(lw - ref_lw) <= RTOL * np.maximum(1.0, np.abs(ref_lw))).all()
+    x, y, th = _expand(px, py, pth, off)
+    got = gm.cast(_dev(x), _dev(y), _dev(th), M).cpu().numpy()
+    assert (got == ref_r.ravel()).all()
+
+
+def _gpu_map_weight(gm, px, py, pth, off, obs, table, M, pair=None):
+    lw, rr = gm.weight(_dev(px), _dev(py), _dev(pth), _dev(off), _dev(obs), _dev(table), M,
+                       ranges=True, pair=pair)
+    return lw.cpu().numpy().astype(np.float64), rr.cpu().numpy()
+
+
+@pytest.mark.parametrize("n_rays", [1, 7, 61, 64, 65, 200, 1024])
+def test_weight_ray_counts(n_rays):
+    """Ray chunks of 64 with ragged tails, pairing wherever offsets allow."""
+    rng = wl.rng_for(302, n_rays)
+    occ = wl.rect_map(rng, 120, 90, n_rects=15)
+    n, M = 36, 150
+    rm = oref.RefCDDT(occ, n)
+    gm = _gpu_map(occ, n)
+    off = wl.ray_offsets(n_rays, fov=2 * math.pi * (n_rays - 1) / max(1, n_rays)) if n_rays > 1 \
+        else wl.ray_offsets(1)
+    px, py, pth = wl.free_poses(rng, occ, 333)
+    obs = rng.integers(-3, M + 5, n_rays).astype(np.int32)
+    table = wl.beam_table(M, wl.beam_params(rng))
+    ref_lw, ref_r = rm.weight(px, py, pth, off, obs, table, M, threads=4, want_ranges=True)
+    from paper_1705_01167_amd import cddt
+    for pair in {0, cddt.pair_offset(off)}:
+        lw, rr = _gpu_map_weight(gm, px, py, pth, off, obs, table, M, pair=pair)
+        assert (rr == ref_r).all()
+        assert (np.abs(lw - ref_lw) <= RTOL * np.maximum(1.0, np.abs(ref_lw))).all()
+
+
+def test_empty_and_degenerate():
+    torch = _torch()
+    from paper_1705_01167_amd import cddt
+    # empty map: every in-map ray runs to max range; 1x1 maps
+    for occ in (np.zeros((5, 7), np.uint8), np.ones((1, 1), np.uint8), np.zeros((1, 1), np.uint8),
+                np.ones((6, 6), np.uint8)):
+        gm = _gpu_map(occ, 8)
+        rm = oref.RefCDDT(occ, 8)
+        _check_structure(gm, rm)
+        rng = np.random.default_rng(0)
+        x = rng.uniform(-1, occ.shape[1] + 1, 999).astype(np.float32)
+        y = rng.uniform(-1, occ.shape[0] + 1, 999).astype(np.float32)
+        th = rng.uniform(0, 7, 999).astype(np.float32)
+        assert (gm.cast(_dev(x), _dev(y), _dev(th), 33).cpu().numpy() == rm.cast(x, y, th, 33)).all()
+    # zero-length inputs are no-ops
+    e = torch.empty(0, dtype=torch.float32, device="cuda")
+    out = gm.cast(e, e, e, 10)
+    assert out.numel() == 0
+    off = _dev(wl.ray_offsets(61))
+    lw = gm.weight(e, e, e, off, _dev(np.zeros(61, np.int32)), _dev(np.zeros(11 * 11, np.float32)), 10)
+    assert lw.numel() == 0
+    # invalid arguments are refused without side effects
+    with pytest.raises(cddt.CddtError):
+        gm.cast(e, e, e, 70000)
+    with pytest.raises(cddt.CddtError):
+        cddt.Map(_dev(np.zeros((4, 4), np.uint8)), 7)
+
+
+def test_torch_allocator_and_static_flag():
+    from paper_1705_01167_amd import cddt
+    occ = wl.rect_map(wl.rng_for(303, 0), 300, 200, n_rects=30)
+    a = cddt.torch_allocator()
+    g1 = cddt.Map(_dev(occ), 120, allocator=a)
+    g2 = cddt.Map(_dev(occ), 120, static=True)
+    for p, q in zip(g1.export(), g2.export()):
+        assert (p == q).all()
+    assert g2.info()["capacity"] == g2.info()["zero_points"]
+    assert g1.info()["capacity"] > g1.info()["zero_points"]
+    g1.close()
+
+
+def test_build_is_deterministic():
+    occ = wl.building_map(wl.rng_for(304, 0), 700, 500)
+    a = _gpu_map(occ, 360).export()
+    b = _gpu_map(occ, 360).export()
+    for p, q in zip(a, b):
+        assert p.dtype == q.dtype and (p == q).all()
+
+
+def test_long_rows_sort():
+    """Bands longer than the LDS sort capacity (16384) take the in-memory network."""
+    occ = np.zeros((3, 16384), np.uint8)
+    occ[1, ::1] = 1          # a 16384-cell wall along x: band 1 of slice 0 holds every cell
+    occ[0, ::2] = 1          # and a dotted row above it
+    n = 8
+    rm = oref.RefCDDT(occ, n)
+    gm = _gpu_map(occ, n)
+    _check_structure(gm, rm)
+    assert gm.info()["max_row_len"] == 16384
+    # two adjacent 45-degree diagonals: band 0 of the 45-degree slice holds both (> 16384)
+    side = 8300
+    occ = np.zeros((side, side), np.uint8)
+    i = np.arange(side - 1)
+    occ[i, i] = 1
+    occ[i + 1, i] = 1
+    rm = oref.RefCDDT(occ, n)
+    gm = _gpu_map(occ, n)
+    _check_structure(gm, rm)
+    assert gm.info()["max_row_len"] > 16384
+
+
+def test_batched_plan_equals_plain():
+    """Several filters on uneven maps in one persistent launch == one launch per filter."""
+    torch = _torch()
+    from paper_1705_01167_amd import cddt
+    rng = wl.rng_for(305, 0)
+    keep, filters, plain = [], [], []
+    for f in range(5):
+        side = int(rng.integers(100, 600))
+        occ = wl.building_map(rng, side, side + 37)
+        n = int(wl.THETA_CHOICES[f % 3])
+        M = int(rng.integers(50, 501))
+        gm = _gpu_map(occ, n)
+        P = int(rng.integers(0 if f == 2 else 1, 3000))
+        px, py, pth = wl.free_poses(rng, occ, P)
+        off = wl.ray_offsets(61)
+        obs = rng.integers(0, M + 1, 61).astype(np.int32)
+        table = wl.beam_table(M, wl.beam_params(rng))
+        t = dict(px=_dev(px), py=_dev(py), pth=_dev(pth), off=_dev(off), obs=_dev(obs), table=_dev(table))
+        lw = torch.full((P,), float("nan"), device="cuda")
+        rr = torch.full((P, 61), -1, dtype=torch.int32, device="cuda")
+        filters.append(cddt.make_filter(gm, t["px"], t["py"], t["pth"], t["off"], t["obs"], t["table"], M, lw, rr))
+        ref_lw, ref_r = gm.weight(t["px"], t["py"], t["pth"], t["off"], t["obs"], t["table"], M, ranges=True)
+        plain.append((ref_lw, ref_r))
+        keep.append((gm, t, lw, rr))
+    plan = cddt.Plan(filters, keepalive=keep)
+    for tuning in [(1, 1, 1), (4, 4, 8), (16, 2, 4), (3, 8, 2)]:
+        for (_, _, lw, rr) in keep:
+            lw.fill_(float("nan"))
+            rr.fill_(-1)
+        plan.tuning = tuning
+        plan.run()
+        torch.cuda.synchronize()
+        for (_, _, lw, rr), (ref_lw, ref_r) in zip(keep, plain):
+            assert torch.equal(lw, ref_lw) and torch.equal(rr, ref_r)
+    # graph capture and replays, with eager work in between
+    s = torch.cuda.Stream()
+    plan.capture(s)
+    for rep in range(3):
+        for (_, _, lw, rr) in keep:
+            lw.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.replay(s)
+        s.synchronize()
+        for (_, _, lw, rr), (ref_lw, ref_r) in zip(keep, plain):
+            assert torch.equal(lw, ref_lw)
+    plan.close()
