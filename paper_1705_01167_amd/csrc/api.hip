@@ -4,6 +4,7 @@
 #include <cstring>
 #include <string>
 
+#include "band_layout.h"
 #include "cddt_common.h"
 
 namespace cddt {
@@ -279,7 +280,8 @@ cddt_status cddt_info(cddt_map m, cddt_stats* out_h) {
   s.zero_points = m->zero_points;
   s.capacity = m->capacity;
   s.max_row_len = m->max_row_len;
-  s.device_bytes = (int64_t)m->w * m->h + (int64_t)sizeof(SliceDev) * m->half + m->rows * 12 + m->capacity * 4;
+  s.device_bytes = (int64_t)m->w * m->h + (int64_t)sizeof(SliceDev) * m->half + m->rows * kNodeInts * 4 +
+                   m->capacity * 4;
   s.rebuilds = m->rebuilds;
   *out_h = s;
   return CDDT_OK;
@@ -301,15 +303,17 @@ cddt_status cddt_slice_table(cddt_map m, int32_t* c_h, int32_t* s_h, int32_t* ro
 cddt_status cddt_export(cddt_map m, int32_t* row_len_h, int32_t* zeros_h) {
   if (!m) return fail(CDDT_EINVAL, "cddt_export: map is NULL");
   CDDT_HIP(hipDeviceSynchronize());
-  std::vector<int2> hdr((size_t)m->rows);
-  CDDT_HIP(hipMemcpy(hdr.data(), m->d_hdr, sizeof(int2) * hdr.size(), hipMemcpyDeviceToHost));
+  std::vector<int32_t> hdr((size_t)m->rows * kNodeInts);
+  CDDT_HIP(hipMemcpy(hdr.data(), m->d_hdr, 4 * hdr.size(), hipMemcpyDeviceToHost));
   std::vector<int32_t> z((size_t)std::max<int64_t>(m->capacity, 1));
   if (m->capacity) CDDT_HIP(hipMemcpy(z.data(), m->d_zeros, 4 * (size_t)m->capacity, hipMemcpyDeviceToHost));
   int64_t o = 0;
-  for (size_t r = 0; r < hdr.size(); ++r) {
-    if (row_len_h) row_len_h[r] = hdr[r].y;
-    if (zeros_h) std::memcpy(zeros_h + o, z.data() + (uint32_t)hdr[r].x, 4 * (size_t)hdr[r].y);
-    o += hdr[r].y;
+  for (int64_t r = 0; r < m->rows; ++r) {
+    const uint32_t start = (uint32_t)hdr[r * kNodeInts];
+    const int32_t len = hdr[r * kNodeInts + 1];
+    if (row_len_h) row_len_h[r] = len;
+    if (zeros_h) std::memcpy(zeros_h + o, z.data() + start, 4 * (size_t)len);
+    o += len;
   }
   if (o != m->zero_points) return fail(CDDT_EINTERNAL, "cddt_export: band lengths do not add up");
   return CDDT_OK;

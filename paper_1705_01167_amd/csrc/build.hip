@@ -6,18 +6,22 @@
 //                    compaction pass (wave ballot + one atomic per wave).
 //   k_project  (count) per (slice, edge cell): the bands its rotated square
 //                    covers; atomic per-band counters.
-//   scan             per-band capacity = length + slack; exclusive scan gives
-//                    each band's start (3-phase block scan, 64-bit totals).
+//   scan             per-band region = key capacity (length + slack, whole
+//                    128-byte lines) + sample levels; exclusive scan gives each
+//                    band's start (3-phase block scan, 64-bit totals).
 //   k_project  (fill) scatter each zero point into its bands through per-band
 //                    cursors (order inside a band is arbitrary here).
 //   k_sort_small     one wave per band: bands of <= 64 sorted in registers
 //                    (bitonic over lanes); longer bands are queued.
 //   k_sort_large     persistent blocks take queued bands; bitonic network in
 //                    LDS (<= 16384 values) or in place in global memory.
+//   k_finalize       one wave per band: sample levels and the header node's
+//                    top level (band_layout.h).
 // Each band ends as the ascending multiset of its zero points, which is unique,
 // so the result does not depend on atomic ordering.
 #include <climits>
 
+#include "band_layout.h"
 #include "cddt_common.h"
 
 namespace cddt {
@@ -78,7 +82,7 @@ __global__ void k_edges(const uint8_t* __restrict__ occ, int w, int h, int full,
 // Per (slice = blockIdx.y, edge cell): count (fill == 0) or scatter (fill == 1).
 __global__ void k_project(const SliceDev* __restrict__ slices, const uint32_t* __restrict__ cells,
                           uint32_t n_cells, uint32_t* __restrict__ cnt,
-                          const int2* __restrict__ hdr, int32_t* __restrict__ zeros, int fill) {
+                          const int32_t* __restrict__ hdr, int32_t* __restrict__ zeros, int fill) {
   uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_cells) return;
   const SliceDev sl = slices[blockIdx.y];
@@ -96,13 +100,13 @@ __global__ void k_project(const SliceDev* __restrict__ slices, const uint32_t* _
       atomicAdd(&cnt[row], 1u);
     } else {
       uint32_t pos = atomicAdd(&cnt[row], 1u);
-      zeros[(uint32_t)hdr[row].x + pos] = z;
+      zeros[(uint32_t)hdr[(int64_t)row * kNodeInts] + pos] = z;
     }
   }
 }
 
-__device__ __forceinline__ uint32_t slack_of(uint32_t len, int no_slack) {
-  return no_slack ? 0u : 8u + (len >> 3);
+__device__ __forceinline__ uint64_t region_of(uint32_t len, int no_slack) {
+  return region_slots(key_capacity(len, no_slack != 0));
 }
 
 // Inclusive scan of one value per thread across the block (uint64).
@@ -138,8 +142,7 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_sum(const uint32_t* __res
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k)
     if (base + k < n) {
-      uint32_t c = cnt[base + k];
-      s += c + slack_of(c, no_slack);
+      s += region_of(cnt[base + k], no_slack);
     }
   uint64_t inc = block_inclusive_scan(s, wt);
   if (threadIdx.x == blockDim.x - 1) tile_sum[blockIdx.x] = inc;
@@ -168,8 +171,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(uint64_t* __restric
 // Band starts and capacities; cnt is reset to 0 to serve as the fill cursor.
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint32_t* __restrict__ cnt, int64_t n, int no_slack,
                                                              const uint64_t* __restrict__ tile_off,
-                                                             int2* __restrict__ hdr,
-                                                             uint32_t* __restrict__ cap,
+                                                             int32_t* __restrict__ hdr,
                                                              BuildCounters* ctr) {
   __shared__ uint64_t wt[kScanThreads / 64];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint32_t* __restric
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     len[k] = base + k < n ? cnt[base + k] : 0u;
-    s += len[k] + (base + k < n ? slack_of(len[k], no_slack) : 0u);
+    s += base + k < n ? region_of(len[k], no_slack) : 0u;
     lsum += len[k];
     lmax = len[k] > lmax ? len[k] : lmax;
   }
@@ -187,11 +189,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint32_t* __restric
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     if (base + k < n) {
-      uint32_t c = len[k] + slack_of(len[k], no_slack);
-      hdr[base + k] = make_int2((int32_t)(uint32_t)off, (int32_t)len[k]);
-      cap[base + k] = c;
+      int32_t* h = hdr + (base + k) * kNodeInts;
+      h[0] = (int32_t)(uint32_t)off;
+      h[1] = (int32_t)len[k];
+      h[2] = (int32_t)key_capacity(len[k], no_slack != 0);
       cnt[base + k] = 0;
-      off += c;
+      off += region_of(len[k], no_slack);
     }
   }
   // block totals of lengths and max length: one atomic per wave
@@ -223,12 +226,12 @@ __device__ __forceinline__ int32_t wave_bitonic(int32_t v) {
   return v;
 }
 
-__global__ void k_sort_small(const int2* __restrict__ hdr, int32_t* __restrict__ zeros, int64_t nrows,
+__global__ void k_sort_small(const int32_t* __restrict__ hdr, int32_t* __restrict__ zeros, int64_t nrows,
                              uint32_t* __restrict__ big_list, BuildCounters* ctr) {
   const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (row >= nrows) return;
   const int lane = threadIdx.x & 63;
-  const int2 hd = hdr[row];
+  const int2 hd = make_int2(hdr[row * kNodeInts], hdr[row * kNodeInts + 1]);
   if (hd.y <= 1) return;
   if (hd.y > 64) {
     if (lane == 0) big_list[atomicAdd(&ctr->big, 1u)] = (uint32_t)row;
@@ -266,13 +269,14 @@ __device__ void block_sort_network(Ptr a, int32_t len) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_sort_large(const int2* __restrict__ hdr, int32_t* __restrict__ zeros,
+__global__ __launch_bounds__(256) void k_sort_large(const int32_t* __restrict__ hdr, int32_t* __restrict__ zeros,
                                                     const uint32_t* __restrict__ big_list,
                                                     const BuildCounters* ctr) {
   __shared__ int32_t buf[kLdsSortCap];
   const uint32_t nbig = ctr->big;
   for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
-    const int2 hd = hdr[big_list[b]];
+    const int64_t row = big_list[b];
+    const int2 hd = make_int2(hdr[row * kNodeInts], hdr[row * kNodeInts + 1]);
     int32_t* z = zeros + (uint32_t)hd.x;
     if (hd.y <= kLdsSortCap) {
       for (int32_t t = threadIdx.x; t < hd.y; t += blockDim.x) buf[t] = z[t];
@@ -289,6 +293,12 @@ __global__ __launch_bounds__(256) void k_sort_large(const int2* __restrict__ hdr
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
+}
+
+__global__ void k_finalize(int32_t* __restrict__ hdr, int32_t* __restrict__ zeros, int64_t nrows) {
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= nrows) return;
+  finalize_band(hdr + row * kNodeInts, zeros);
 }
 
 // RAII holder for build temporaries.
@@ -311,14 +321,13 @@ unsigned grid_for(int64_t n, int threads) {
 
 void free_structure(cddt_map_s* m) {
   if (m->d_hdr) m->alloc.release(m->d_hdr);
-  if (m->d_cap) m->alloc.release(m->d_cap);
   if (m->d_zeros) m->alloc.release(m->d_zeros);
   m->d_hdr = nullptr;
-  m->d_cap = nullptr;
   m->d_zeros = nullptr;
 }
 
-// Builds hdr / cap / zeros from m->d_occ and m->d_slices.  Blocks on `st`.
+// Builds the header nodes and band regions from m->d_occ and m->d_slices.
+// Blocks on `st`.
 cddt_status build_structure(cddt_map_s* m, hipStream_t st) {
   free_structure(m);
   const int64_t cells = (int64_t)m->w * m->h;
@@ -352,19 +361,18 @@ cddt_status build_structure(cddt_map_s* m, hipStream_t st) {
                      cnt, R, 0u);
   if (n_edges)
     hipLaunchKernelGGL(k_project, dim3(grid_for(n_edges, 256), m->half), dim3(256), 0, st, m->d_slices,
-                       (const uint32_t*)edges_t.p, n_edges, cnt, (const int2*)nullptr, (int32_t*)nullptr, 0);
+                       (const uint32_t*)edges_t.p, n_edges, cnt, (const int32_t*)nullptr, (int32_t*)nullptr, 0);
   CDDT_HIP(hipGetLastError());
 
   // 3. band layout
-  CDDT_TRY(m->alloc.alloc((void**)&m->d_hdr, (size_t)R * sizeof(int2), "band headers"));
-  CDDT_TRY(m->alloc.alloc((void**)&m->d_cap, (size_t)R * 4, "band capacities"));
+  CDDT_TRY(m->alloc.alloc((void**)&m->d_hdr, (size_t)R * kNodeInts * 4, "band header nodes"));
   const int64_t ntiles = (R + kScanTile - 1) / kScanTile;
   CDDT_TRY(tiles_t.get((size_t)ntiles * 8, "scan tiles"));
   uint64_t* tiles = (uint64_t*)tiles_t.p;
   hipLaunchKernelGGL(k_tile_sum, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, cnt, R, no_slack, tiles);
   hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, st, tiles, ntiles, ctr);
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, cnt, R, no_slack,
-                     (const uint64_t*)tiles, m->d_hdr, m->d_cap, ctr);
+                     (const uint64_t*)tiles, m->d_hdr, ctr);
   CDDT_HIP(hipGetLastError());
   CDDT_HIP(hipMemcpyAsync(&hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
   CDDT_HIP(hipStreamSynchronize(st));
@@ -376,7 +384,7 @@ cddt_status build_structure(cddt_map_s* m, hipStream_t st) {
   m->zero_points = (int64_t)hc.total_len;
   m->max_row_len = (int64_t)hc.max_len;
 
-  // 4. fill and sort
+  // 4. fill, sort, finalize
   cddt_status st_alloc = m->alloc.alloc((void**)&m->d_zeros, (size_t)(m->capacity ? m->capacity : 1) * 4,
                                         "zero points");
   if (st_alloc != CDDT_OK) {
@@ -385,12 +393,13 @@ cddt_status build_structure(cddt_map_s* m, hipStream_t st) {
   }
   if (n_edges)
     hipLaunchKernelGGL(k_project, dim3(grid_for(n_edges, 256), m->half), dim3(256), 0, st, m->d_slices,
-                       (const uint32_t*)edges_t.p, n_edges, cnt, (const int2*)m->d_hdr, m->d_zeros, 1);
+                       (const uint32_t*)edges_t.p, n_edges, cnt, (const int32_t*)m->d_hdr, m->d_zeros, 1);
   CDDT_TRY(big_t.get((size_t)R * 4, "long-band list"));
-  hipLaunchKernelGGL(k_sort_small, dim3(grid_for(R, 4)), dim3(256), 0, st, (const int2*)m->d_hdr, m->d_zeros, R,
-                     (uint32_t*)big_t.p, ctr);
-  hipLaunchKernelGGL(k_sort_large, dim3(2048), dim3(256), 0, st, (const int2*)m->d_hdr, m->d_zeros,
+  hipLaunchKernelGGL(k_sort_small, dim3(grid_for(R, 4)), dim3(256), 0, st, (const int32_t*)m->d_hdr, m->d_zeros,
+                     R, (uint32_t*)big_t.p, ctr);
+  hipLaunchKernelGGL(k_sort_large, dim3(2048), dim3(256), 0, st, (const int32_t*)m->d_hdr, m->d_zeros,
                      (const uint32_t*)big_t.p, (const BuildCounters*)ctr);
+  hipLaunchKernelGGL(k_finalize, dim3(grid_for(R, 4)), dim3(256), 0, st, m->d_hdr, m->d_zeros, R);
   CDDT_HIP(hipGetLastError());
   CDDT_HIP(hipStreamSynchronize(st));
   return CDDT_OK;

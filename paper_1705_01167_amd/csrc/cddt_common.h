@@ -21,8 +21,8 @@ struct SliceDev {
 struct MapDev {
   const uint8_t* occ;        // W*H grid, row-major, nonzero = occupied
   const SliceDev* slices;    // n/2 entries
-  const int2* hdr;           // per band: {start, len} into zeros
-  const int32_t* zeros;      // zero points (Q16), each band ascending
+  const int32_t* hdr;        // per band: a 128-byte header node (band_layout.h)
+  const int32_t* zeros;      // band regions: keys (Q16, ascending) and sample levels
   int32_t w, h, n, half;
   float k_scale;             // (float)(n / (2 pi))
   int32_t pad;
@@ -96,9 +96,8 @@ struct cddt_map_s {
   int64_t rows = 0;
   uint8_t* d_occ = nullptr;
   cddt::SliceDev* d_slices = nullptr;
-  int2* d_hdr = nullptr;         // {start, len}
-  uint32_t* d_cap = nullptr;     // per band capacity (len + slack)
-  int32_t* d_zeros = nullptr;
+  int32_t* d_hdr = nullptr;      // rows * kNodeInts header nodes
+  int32_t* d_zeros = nullptr;    // band regions
   int64_t capacity = 0, zero_points = 0, edge_cells = 0, max_row_len = 0, rebuilds = 0;
   int64_t device_bytes = 0;
   // update scratch

@@ -9,13 +9,22 @@ namespace {
 constexpr int kCastThreads = 256;
 constexpr int kWeightThreads = 256;  // 4 particles (waves) per block
 
+// One wave takes 64 consecutive rays at a time (lane = ray); the loop bound is
+// the same for every lane of a wave so the cooperative search stays converged.
 __global__ __launch_bounds__(kCastThreads) void k_cast(MapDev m, const float* __restrict__ x,
                                                        const float* __restrict__ y,
                                                        const float* __restrict__ th, int64_t n,
                                                        int32_t max_range, int32_t* __restrict__ out) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    out[i] = cast_one(m, x[i], y[i], th[i], max_range);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t waves = (int64_t)gridDim.x * (kCastThreads / kWave);
+  const int64_t chunks = (n + kWave - 1) / kWave;
+  for (int64_t c = (int64_t)blockIdx.x * (kCastThreads / kWave) + (threadIdx.x >> 6); c < chunks; c += waves) {
+    const int64_t i = c * kWave + lane;
+    const bool active = i < n;
+    const float xi = active ? x[i] : 0.0f, yi = active ? y[i] : 0.0f, ti = active ? th[i] : 0.0f;
+    const int32_t r = wave_cast(m, active, xi, yi, ti, max_range);
+    if (active) out[i] = r;
+  }
 }
 
 __global__ __launch_bounds__(kWeightThreads) void k_weight(FilterDev f) {
@@ -32,7 +41,7 @@ cddt_status launch_cast(const MapDev& m, const float* x, const float* y, const f
                         int32_t max_range, int32_t* out, hipStream_t st) {
   if (n == 0) return CDDT_OK;
   int64_t blocks = (n + kCastThreads - 1) / kCastThreads;
-  if (blocks > (1 << 20)) blocks = 1 << 20;
+  if (blocks > (1 << 16)) blocks = 1 << 16;
   hipLaunchKernelGGL(k_cast, dim3((unsigned)blocks), dim3(kCastThreads), 0, st, m, x, y, th, n, max_range, out);
   CDDT_HIP(hipGetLastError());
   return CDDT_OK;

@@ -1,0 +1,74 @@
+"""Autotuner for the persistent batched kernel.
+
+Times every tuning in a small grid (particles per tile x waves per block x
+blocks per CU) on the plan itself with HIP events (cddt_plan_time) and keeps
+the fastest.  Results are cached in a JSON file keyed by device and a plan
+signature (filter count, particle total bucket, theta-bin set), so a later run
+with the same shape skips the sweep.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+
+from . import cddt
+
+SPACE_PPT = (1, 2, 4, 8, 16, 32)
+SPACE_WAVES = (1, 2, 4, 8)
+SPACE_BLOCKS = (2, 4, 8, 16)
+
+
+def cache_path() -> str:
+    return os.environ.get("CDDT_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "cddt", "tuning.json"))
+
+
+def signature(n_filters: int, total_particles: int, theta_bins, device_name: str) -> str:
+    bucket = int(round(math.log2(max(1, total_particles))))
+    return f"{device_name}|f{n_filters}|p2^{bucket}|n{'-'.join(map(str, sorted(set(theta_bins))))}"
+
+
+def _load() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(d: dict) -> None:
+    p = cache_path()
+    try:
+        os.makedirs(os.path.dirname(p), exist_ok=True)
+        tmp = p + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+        os.replace(tmp, p)
+    except OSError:
+        pass
+
+
+def autotune(plan: "cddt.Plan", sig: str, reps: int = 3, use_cache: bool = True, stream=None):
+    """Pick and apply the fastest tuning; returns (tuning, ms, table of all timings)."""
+    cache = _load() if use_cache else {}
+    if use_cache and sig in cache:
+        t = tuple(cache[sig]["tuning"])
+        plan.tuning = t
+        return t, cache[sig]["ms"], []
+    results = []
+    for t in itertools.product(SPACE_PPT, SPACE_WAVES, SPACE_BLOCKS):
+        ms = plan.time(t, reps=reps, stream=stream)
+        results.append((ms, t))
+    results.sort()
+    best_ms, best = results[0]
+    # confirm the top few with more repetitions
+    confirm = [(plan.time(t, reps=3 * reps, stream=stream), t) for _, t in results[:4]]
+    confirm.sort()
+    best_ms, best = confirm[0]
+    plan.tuning = best
+    cache = _load()
+    cache[sig] = {"tuning": list(best), "ms": best_ms}
+    _store(cache)
+    return best, best_ms, results

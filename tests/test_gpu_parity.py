@@ -210,8 +210,8 @@ def test_torch_allocator_and_static_flag():
     g2 = cddt.Map(_dev(occ), 120, static=True)
     for p, q in zip(g1.export(), g2.export()):
         assert (p == q).all()
-    assert g2.info()["capacity"] == g2.info()["zero_points"]
-    assert g1.info()["capacity"] > g1.info()["zero_points"]
+    # capacities count whole 128-byte lines and sample levels; static has no slack
+    assert g2.info()["zero_points"] <= g2.info()["capacity"] < g1.info()["capacity"]
     g1.close()
 
 
