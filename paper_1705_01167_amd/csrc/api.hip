@@ -62,11 +62,12 @@ namespace {
 
 void release_scratch(cddt_map_s* m) {
   for (Scratch* s : {&m->upd_ops, &m->upd_changed, &m->upd_cand, &m->upd_edits, &m->upd_rec, &m->upd_rowcnt,
-                     &m->upd_misc}) {
+                     &m->upd_misc, &m->upd_slot, &m->upd_touched, &m->upd_grp, &m->upd_tiles}) {
     if (s->ptr) m->alloc.release(s->ptr);
     s->ptr = nullptr;
     s->bytes = 0;
   }
+  m->upd_rowcnt_clear = false;
 }
 
 void release_all(cddt_map_s* m) {
@@ -307,6 +308,9 @@ cddt_status cddt_export(cddt_map m, int32_t* row_len_h, int32_t* zeros_h) {
   CDDT_HIP(hipMemcpy(hdr.data(), m->d_hdr, 4 * hdr.size(), hipMemcpyDeviceToHost));
   std::vector<int32_t> z((size_t)std::max<int64_t>(m->capacity, 1));
   if (m->capacity) CDDT_HIP(hipMemcpy(z.data(), m->d_zeros, 4 * (size_t)m->capacity, hipMemcpyDeviceToHost));
+  int64_t total = 0;
+  for (int64_t r = 0; r < m->rows; ++r) total += hdr[r * kNodeInts + 1];
+  if (total != m->zero_points) return fail(CDDT_EINTERNAL, "cddt_export: band lengths do not add up");
   int64_t o = 0;
   for (int64_t r = 0; r < m->rows; ++r) {
     const uint32_t start = (uint32_t)hdr[r * kNodeInts];
@@ -315,7 +319,6 @@ cddt_status cddt_export(cddt_map m, int32_t* row_len_h, int32_t* zeros_h) {
     if (zeros_h) std::memcpy(zeros_h + o, z.data() + start, 4 * (size_t)len);
     o += len;
   }
-  if (o != m->zero_points) return fail(CDDT_EINTERNAL, "cddt_export: band lengths do not add up");
   return CDDT_OK;
 }
 

@@ -19,6 +19,7 @@
 //                    top level (band_layout.h).
 // Each band ends as the ascending multiset of its zero points, which is unique,
 // so the result does not depend on atomic ordering.
+#include <algorithm>
 #include <climits>
 
 #include "band_layout.h"
@@ -40,22 +41,6 @@ struct BuildCounters {
   uint64_t total_len;
   uint64_t max_len;
 };
-
-__device__ __forceinline__ bool edge_cell(const uint8_t* __restrict__ occ, int w, int h, int i, int j,
-                                          int full) {
-  if (occ[(size_t)j * w + i] == 0) return false;
-  if (full) return true;
-  for (int dj = -1; dj <= 1; ++dj) {
-    int b = j + dj;
-    if (b < 0 || b >= h) return true;  // off-map neighbour counts as free
-    for (int di = -1; di <= 1; ++di) {
-      int a = i + di;
-      if (a < 0 || a >= w) return true;
-      if (occ[(size_t)b * w + a] == 0) return true;
-    }
-  }
-  return false;
-}
 
 // Edge cells are packed as i | j << 16 (both < 2^14).
 __global__ void k_edges(const uint8_t* __restrict__ occ, int w, int h, int full,
@@ -295,6 +280,26 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
     p[i] = v;
 }
 
+// Sum and maximum of the band lengths (header word 1 of every node).
+__global__ void k_len_stats(const int32_t* __restrict__ hdr, int64_t nrows, BuildCounters* ctr) {
+  uint64_t sum = 0, mx = 0;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t l = (uint32_t)hdr[r * kNodeInts + 1];
+    sum += l;
+    mx = l > mx ? l : mx;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sum += __shfl_xor(sum, o);
+    const uint64_t t = __shfl_xor(mx, o);
+    mx = t > mx ? t : mx;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (sum) atomicAdd((unsigned long long*)&ctr->total_len, (unsigned long long)sum);
+    if (mx) atomicMax((unsigned long long*)&ctr->max_len, (unsigned long long)mx);
+  }
+}
+
 __global__ void k_finalize(int32_t* __restrict__ hdr, int32_t* __restrict__ zeros, int64_t nrows) {
   const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (row >= nrows) return;
@@ -324,6 +329,24 @@ void free_structure(cddt_map_s* m) {
   if (m->d_zeros) m->alloc.release(m->d_zeros);
   m->d_hdr = nullptr;
   m->d_zeros = nullptr;
+}
+
+// Exact zero-point total and longest band, from the header nodes.  Blocks.
+cddt_status refresh_stats(cddt_map_s* m, hipStream_t st) {
+  Temp ctr_t(&m->alloc);
+  CDDT_TRY(ctr_t.get(sizeof(BuildCounters), "stats counters"));
+  BuildCounters* ctr = (BuildCounters*)ctr_t.p;
+  CDDT_HIP(hipMemsetAsync(ctr, 0, sizeof(BuildCounters), st));
+  const int64_t blocks = std::min<int64_t>((m->rows + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_len_stats, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st,
+                     (const int32_t*)m->d_hdr, m->rows, ctr);
+  CDDT_HIP(hipGetLastError());
+  BuildCounters hc{};
+  CDDT_HIP(hipMemcpyAsync(&hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
+  CDDT_HIP(hipStreamSynchronize(st));
+  m->zero_points = (int64_t)hc.total_len;
+  m->max_row_len = (int64_t)hc.max_len;
+  return CDDT_OK;
 }
 
 // Builds the header nodes and band regions from m->d_occ and m->d_slices.

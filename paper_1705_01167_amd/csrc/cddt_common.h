@@ -44,6 +44,23 @@ struct FilterDev {
 };
 
 constexpr int kWave = 64;
+
+// Edge-map test of cell (i, j) (Sec. IV-C): occupied, and at least one of its
+// 8 neighbours is free or off the map.  With `full` every occupied cell counts.
+__device__ __forceinline__ bool edge_cell(const uint8_t* __restrict__ occ, int w, int h, int i, int j, int full) {
+  if (occ[(size_t)j * w + i] == 0) return false;
+  if (full) return true;
+  for (int dj = -1; dj <= 1; ++dj) {
+    const int b = j + dj;
+    if (b < 0 || b >= h) return true;  // off-map neighbour counts as free
+    for (int di = -1; di <= 1; ++di) {
+      const int a = i + di;
+      if (a < 0 || a >= w) return true;
+      if (occ[(size_t)b * w + a] == 0) return true;
+    }
+  }
+  return false;
+}
 constexpr int kMaxSide = 16384;
 constexpr int kMaxBins = 8192;
 constexpr int kMaxRays = 1024;
@@ -100,8 +117,10 @@ struct cddt_map_s {
   int32_t* d_zeros = nullptr;    // band regions
   int64_t capacity = 0, zero_points = 0, edge_cells = 0, max_row_len = 0, rebuilds = 0;
   int64_t device_bytes = 0;
-  // update scratch
+  // update scratch (grown on demand, released with the map)
   cddt::Scratch upd_ops, upd_changed, upd_cand, upd_edits, upd_rec, upd_rowcnt, upd_misc;
+  cddt::Scratch upd_slot, upd_touched, upd_grp, upd_tiles;
+  bool upd_rowcnt_clear = false;  // upd_rowcnt holds zeros for every band
   cddt::MapDev dev() const {
     cddt::MapDev m;
     m.occ = d_occ;
@@ -122,6 +141,7 @@ namespace cddt {
 // build.hip
 cddt_status build_structure(cddt_map_s* m, hipStream_t st);
 void free_structure(cddt_map_s* m);
+cddt_status refresh_stats(cddt_map_s* m, hipStream_t st);
 // query.hip
 cddt_status launch_cast(const MapDev& m, const float* x, const float* y, const float* th, int64_t n,
                         int32_t max_range, int32_t* out, hipStream_t st);

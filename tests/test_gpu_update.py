@@ -1,0 +1,163 @@
+"""GPU incremental update (Sec. IV-D) against the oracle and against a rebuild.
+
+After every batch of ops the GPU structure must equal, band for band, both the
+oracle's incrementally updated structure and a fresh build of the new grid;
+casts must stay bit-exact.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ref as oref
+from paper_1705_01167_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(a):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _map(occ, n, **kw):
+    from paper_1705_01167_amd import cddt
+    return cddt.Map(_dev(occ), n, **kw)
+
+
+def _same_export(a, b):
+    return all(x.shape == y.shape and (x == y).all() for x, y in zip(a, b))
+
+
+def _random_queries(rng, w, h, k):
+    return (rng.uniform(-1, w + 1, k).astype(np.float32), rng.uniform(-1, h + 1, k).astype(np.float32),
+            rng.uniform(-7, 7, k).astype(np.float32))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_updates_match_oracle(seed):
+    rng = wl.rng_for(401, seed)
+    w, h = int(rng.integers(2, 60)), int(rng.integers(2, 60))
+    occ = wl.random_map(rng, w, h, float(rng.uniform(0.05, 0.5)))
+    n = int(rng.choice([4, 8, 36, 108, 200]))
+    full = seed % 3 == 2
+    static = seed % 4 == 3
+    _say(f"updates seed={seed} {w}x{h} n={n} full={full} static={static}")
+    gm = _map(occ, n, full_map=full, static=static)
+    rm = oref.RefCDDT(occ, n, full_map=full)
+    cur = occ.copy()
+    for step in range(5):
+        k = int(rng.integers(0, 300))
+        xs = rng.integers(0, w, k).astype(np.int32)
+        ys = rng.integers(0, h, k).astype(np.int32)
+        vals = rng.integers(0, 2, k).astype(np.uint8)
+        if k > 4:
+            xs[-2:], ys[-2:] = xs[:2], ys[:2]      # repeated cells: last write wins
+        gm.update(xs, ys, vals)
+        rm.update(xs, ys, vals)
+        wl.apply_ops(cur, xs, ys, vals)
+        assert (gm.grid() == cur).all()
+        fresh = oref.RefCDDT(cur, n, full_map=full)
+        g = gm.export()
+        assert _same_export(g, rm.export()), f"step {step}: GPU update != oracle update"
+        assert _same_export(g, fresh.export()), f"step {step}: GPU update != rebuild"
+        x, y, th = _random_queries(rng, w, h, 5000)
+        got = gm.cast(_dev(x), _dev(y), _dev(th), 80).cpu().numpy()
+        assert (got == fresh.cast(x, y, th, 80)).all()
+
+
+def test_overflow_relays_structure():
+    """A static empty map has no room in any band: the first insertions re-lay the structure."""
+    occ = np.zeros((50, 70), np.uint8)
+    gm = _map(occ, 108, static=True)
+    assert gm.info()["capacity"] == 0
+    rng = wl.rng_for(404, 0)
+    xs = rng.integers(0, 70, 200).astype(np.int32)
+    ys = rng.integers(0, 50, 200).astype(np.int32)
+    gm.update(xs, ys, np.ones(200, np.uint8))
+    cur = occ.copy()
+    wl.apply_ops(cur, xs, ys, np.ones(200, np.uint8))
+    assert gm.info()["rebuilds"] >= 1
+    assert _same_export(gm.export(), oref.RefCDDT(cur, 108).export())
+    # a non-static map re-lays only when a band runs out of slack
+    gm2 = _map(occ, 108)
+    gm2.update(xs, ys, np.ones(200, np.uint8))
+    assert _same_export(gm2.export(), gm.export())
+
+
+def test_chunked_ops_last_write_wins():
+    """More ops than one device chunk (4096); a cell written in two chunks keeps the later value."""
+    rng = wl.rng_for(402, 0)
+    occ = wl.building_map(rng, 300, 200)
+    gm = _map(occ, 108)
+    k = 10000
+    xs = rng.integers(0, 300, k).astype(np.int32)
+    ys = rng.integers(0, 200, k).astype(np.int32)
+    vals = rng.integers(0, 2, k).astype(np.uint8)
+    xs[9000], ys[9000], vals[9000] = xs[10], ys[10], 1 - vals[10]   # same cell, chunks 0 and 2
+    gm.update(xs, ys, vals)
+    cur = occ.copy()
+    wl.apply_ops(cur, xs, ys, vals)
+    assert (gm.grid() == cur).all()
+    assert _same_export(gm.export(), oref.RefCDDT(cur, 108).export())
+
+
+def test_invalid_ops_change_nothing():
+    from paper_1705_01167_amd import cddt
+    occ = wl.rect_map(wl.rng_for(403, 0), 64, 48, n_rects=8)
+    gm = _map(occ, 36)
+    before = gm.export()
+    with pytest.raises(cddt.CddtError) as e:
+        gm.update([1, 64], [1, 1], [1, 1])
+    assert e.value.code == cddt.EINVAL
+    with pytest.raises(cddt.CddtError):
+        gm.update([1], [-1], [1])
+    gm.update([], [], [])
+    assert (gm.grid() == occ).all() and _same_export(gm.export(), before)
+
+
+def test_reveal_and_hide_interior():
+    """Deleting an edge cell of a block reveals interior cells; refilling hides them again."""
+    occ = np.zeros((40, 40), np.uint8)
+    occ[10:30, 10:30] = 1
+    gm = _map(occ, 200)
+    ref = oref.RefCDDT(occ, 200)
+    ops = [([10], [10], [0]), ([20], [20], [0]), ([20], [20], [1]), ([10], [10], [1])]
+    for xs, ys, vs in ops:
+        gm.update(xs, ys, vs)
+        ref.update(np.array(xs, np.int32), np.array(ys, np.int32), np.array(vs, np.uint8))
+        assert _same_export(gm.export(), ref.export())
+    assert _same_export(gm.export(), oref.RefCDDT(occ, 200).export())
+
+
+def test_toggle_workload_4000():
+    """4000^2 floor, 200 bins, 1000 random toggles per step: update == GPU rebuild == oracle rays."""
+    import torch
+    _say("toggles 4000: build")
+    occ = wl.building_map(wl.rng_for(wl.UPDATES, wl.S_MAP), 4000, 4000)
+    n, M = 200, 500
+    gm = _map(occ, n)
+    cur = occ.copy()
+    rng = wl.rng_for(wl.UPDATES, wl.S_OPS)
+    for step in range(3):
+        xs, ys, vals = wl.toggle_ops(rng, cur, 1000)
+        gm.update(xs, ys, vals)
+        wl.apply_ops(cur, xs, ys, vals)
+        _say(f"toggles 4000: step {step} rebuild compare")
+        fresh = _map(cur, n)
+        assert _same_export(gm.export(), fresh.export())
+        fresh.close()
+        torch.cuda.empty_cache()
+    _say("toggles 4000: oracle brute-force sample")
+    rm = oref.RefCDDT(cur, n, threads=16)
+    px, py, pth = wl.free_poses(wl.rng_for(wl.UPDATES, wl.S_POSES), cur, 4000)
+    got = gm.cast(_dev(px), _dev(py), _dev(pth), M).cpu().numpy()
+    assert (got == rm.cast(px, py, pth, M, threads=16)).all()
+    sel = slice(0, 400)
+    assert (got[sel] == rm.cast(px[sel], py[sel], pth[sel], M, threads=16, brute=True)).all()
