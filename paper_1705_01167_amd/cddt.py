@@ -358,3 +358,81 @@ class Plan:
 
 def device_cus() -> int:
     return int(lib().cddt_device_cus())
+
+
+class Server:
+    """Continuous-batching server over resident maps (cddt_server_*)."""
+
+    def __init__(self, maps, offsets, tables, max_ranges, budget_bytes: int = 1 << 30, n_lanes: int = 4,
+                 max_batch: int = 256, tuning=(4, 4, 8)):
+        n = len(maps)
+        self._offsets = [np.ascontiguousarray(np.asarray(o, np.float32)) for o in offsets]
+        self._tables = list(tables)              # keep device tables alive
+        self._maps = list(maps)
+        self._n_rays = [o.size for o in self._offsets]
+        cfg = ServerConfig(int(budget_bytes), int(n_lanes), int(max_batch), int(max(self._n_rays)), 0,
+                           Tuning(*tuning, 0))
+        handles = (C.c_void_p * n)(*[m.handle.value for m in maps])
+        offp = (C.c_void_p * n)(*[o.ctypes.data for o in self._offsets])
+        nr = (C.c_int32 * n)(*self._n_rays)
+        tabs = (C.c_void_p * n)(*[t.data_ptr() for t in tables])
+        mr = (C.c_int32 * n)(*[int(v) for v in max_ranges])
+        h = C.c_void_p()
+        _check(lib().cddt_server_create(C.cast(handles, C.c_void_p), n, C.cast(offp, C.c_void_p),
+                                        C.cast(nr, C.c_void_p), C.cast(tabs, C.c_void_p), C.cast(mr, C.c_void_p),
+                                        C.byref(cfg), C.byref(h)))
+        self.handle = h
+        self._sizes = {}
+
+    def submit(self, map_index: int, px, py, pth, obs) -> int:
+        px = np.ascontiguousarray(px, np.float32)
+        py = np.ascontiguousarray(py, np.float32)
+        pth = np.ascontiguousarray(pth, np.float32)
+        obs = np.ascontiguousarray(obs, np.int32)
+        if obs.size != self._n_rays[map_index]:
+            raise ValueError("obs must hold one range per ray of the map")
+        rid = C.c_int64()
+        _check(lib().cddt_server_submit(self.handle, int(map_index), px.ctypes.data_as(C.c_void_p),
+                                        py.ctypes.data_as(C.c_void_p), pth.ctypes.data_as(C.c_void_p), px.size,
+                                        obs.ctypes.data_as(C.c_void_p), C.byref(rid)))
+        self._sizes[rid.value] = px.size
+        return rid.value
+
+    def poll(self, rid: int):
+        out = np.empty(self._sizes[rid], np.float32)
+        done = C.c_int32()
+        _check(lib().cddt_server_poll(self.handle, int(rid), out.ctypes.data_as(C.c_void_p), C.byref(done)))
+        if done.value:
+            del self._sizes[rid]
+            return out
+        return None
+
+    def wait(self, rid: int):
+        out = np.empty(self._sizes[rid], np.float32)
+        _check(lib().cddt_server_wait(self.handle, int(rid), out.ctypes.data_as(C.c_void_p)))
+        del self._sizes[rid]
+        return out
+
+    def times(self, rid: int):
+        a, b = C.c_double(), C.c_double()
+        _check(lib().cddt_server_times(self.handle, int(rid), C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().cddt_server_stats_get(self.handle, C.byref(s)))
+        return s.as_dict()
+
+    def now(self) -> float:
+        return float(lib().cddt_server_now(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().cddt_server_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

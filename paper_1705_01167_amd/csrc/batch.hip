@@ -15,11 +15,6 @@
 
 #include "query_device.h"
 
-namespace cddt {
-FilterDev filter_dev(const cddt_filter& f);
-cddt_status validate_filter(const cddt_filter& f, const char* who);
-}  // namespace cddt
-
 struct cddt_plan_s {
   std::vector<cddt_filter> filters;
   std::vector<cddt::FilterDev> fdev;
@@ -76,6 +71,23 @@ __global__ void k_batch(const FilterDev* __restrict__ filters, const int64_t* __
   }
 }
 
+}  // namespace
+
+// Counter reset plus one persistent launch over the tiles of n_filters filters.
+cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, int32_t n_filters,
+                         int64_t total_tiles, const cddt_tuning& t, unsigned long long* d_counter, int32_t cus,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, d_counter);
+  if (total_tiles > 0) {
+    const unsigned blocks = (unsigned)std::max(1, cus * t.blocks_per_cu);
+    const unsigned threads = (unsigned)(kWave * t.waves_per_block);
+    hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(threads), 0, st, d_filters, d_prefix, n_filters, total_tiles,
+                       t.particles_per_tile, d_counter);
+  }
+  CDDT_HIP(hipGetLastError());
+  return CDDT_OK;
+}
+
 cddt_status check_tuning(const cddt_tuning& t) {
   if (t.particles_per_tile < 1 || t.particles_per_tile > 256)
     return fail(CDDT_EINVAL, "tuning: particles_per_tile must be in 1..256");
@@ -93,6 +105,8 @@ cddt_tuning default_tuning() {
   return t;
 }
 
+namespace {
+
 // Recompute tile prefix sums for the plan's tuning and upload them (blocking).
 cddt_status apply_tuning(cddt_plan_s* p, const cddt_tuning& t, hipStream_t st) {
   CDDT_TRY(check_tuning(t));
@@ -109,16 +123,8 @@ cddt_status apply_tuning(cddt_plan_s* p, const cddt_tuning& t, hipStream_t st) {
 }
 
 cddt_status launch_plan(cddt_plan_s* p, hipStream_t st) {
-  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, p->d_counter);
-  if (p->total_tiles > 0) {
-    const unsigned blocks = (unsigned)std::max(1, p->cus * p->tuning.blocks_per_cu);
-    const unsigned threads = (unsigned)(kWave * p->tuning.waves_per_block);
-    hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(threads), 0, st, (const FilterDev*)p->d_filters,
-                       (const int64_t*)p->d_prefix, (int32_t)p->filters.size(), p->total_tiles,
-                       p->tuning.particles_per_tile, p->d_counter);
-  }
-  CDDT_HIP(hipGetLastError());
-  return CDDT_OK;
+  return launch_batch(p->d_filters, p->d_prefix, (int32_t)p->filters.size(), p->total_tiles, p->tuning,
+                      p->d_counter, p->cus, st);
 }
 
 void drop_graph(cddt_plan_s* p) {

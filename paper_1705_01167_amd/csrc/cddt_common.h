@@ -146,6 +146,15 @@ cddt_status refresh_stats(cddt_map_s* m, hipStream_t st);
 cddt_status launch_cast(const MapDev& m, const float* x, const float* y, const float* th, int64_t n,
                         int32_t max_range, int32_t* out, hipStream_t st);
 cddt_status launch_weight(const FilterDev& f, hipStream_t st);
+// batch.hip
+cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, int32_t n_filters,
+                         int64_t total_tiles, const cddt_tuning& t, unsigned long long* d_counter, int32_t cus,
+                         hipStream_t st);
+cddt_status check_tuning(const cddt_tuning& t);
+cddt_tuning default_tuning();
+// api.hip
+FilterDev filter_dev(const cddt_filter& f);
+cddt_status validate_filter(const cddt_filter& f, const char* who);
 // update.hip
 cddt_status apply_update(cddt_map_s* m, const int32_t* xs, const int32_t* ys, const uint8_t* vals,
                          int64_t n_ops, hipStream_t st);

@@ -1,17 +1,436 @@
-// Serving loop -- placeholder.
+// Continuous-batching server over resident CDDT maps.
+//
+// Requests (one robot: its particles and one scan on one resident map) are
+// queued by host threads.  A scheduler thread owns `n_lanes` lanes; each lane
+// has its own stream, a device arena of budget_bytes / n_lanes and pinned host
+// staging.  Whenever a lane is idle, the scheduler admits queued requests in
+// arrival order while the lane's arena and batch size allow, packs their
+// inputs and filter descriptors into the staging buffer, and issues one
+// upload, one persistent batched launch (the same kernel as cddt_plan_run) and
+// one download on the lane's stream, followed by an event.  Up to n_lanes
+// batches are in flight at once, so requests that arrive while others run are
+// admitted as lanes and memory free up and their work overlaps on the device.
+// A batch's requests complete when its event has fired: their log-weights are
+// copied out and their completion time is stamped on the host clock.
+//
+// Results are bit-identical to running each request alone: every particle's
+// weight is computed by the same per-particle routine, in a fixed order.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
 #include "cddt_common.h"
+
+namespace cddt {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct ServedMap {
+  cddt_map map;
+  float* d_offsets;
+  int32_t n_rays;
+  int32_t pair;
+  const float* table;
+  int32_t max_range;
+};
+
+struct Request {
+  int64_t id;
+  int32_t map;
+  int32_t n;
+  std::vector<float> poses;   // px[n], py[n], pth[n]
+  std::vector<int32_t> obs;
+  std::vector<float> logw;
+  size_t bytes;
+  double submit_t = 0, done_t = 0;
+  bool done = false;
+};
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+struct Lane {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  char* d_arena = nullptr;   // device: [descriptors][prefix][counter][inputs...][outputs...]
+  char* h_in = nullptr;      // pinned staging of the same layout (inputs part)
+  float* h_out = nullptr;    // pinned log-weights
+  size_t arena = 0;
+  std::vector<Request*> batch;
+  std::vector<size_t> out_off;  // per request: float offset of its log-weights in h_out
+  size_t bytes = 0;
+  bool busy = false;
+};
+
+}  // namespace
+}  // namespace cddt
+
+struct cddt_server_s {
+  std::vector<cddt::ServedMap> maps;
+  cddt_server_config cfg{};
+  int32_t cus = 0;
+  int device = 0;
+  std::vector<cddt::Lane> lanes;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<cddt::Request*> queue;
+  std::unordered_map<int64_t, cddt::Request*> live;
+  std::unordered_map<int64_t, std::pair<double, double>> times;
+  std::thread sched;
+  bool stop = false;
+  int64_t next_id = 0;
+  cddt_server_stats stats{};
+  int64_t bytes_in_flight = 0;
+  cddt::Clock::time_point t0;
+  double busy_since = -1.0;
+  std::string error;
+  double now() const { return std::chrono::duration<double>(cddt::Clock::now() - t0).count(); }
+};
+
+namespace cddt {
+namespace {
+
+size_t request_bytes(const cddt_server_s* s, int32_t map, int32_t n) {
+  const ServedMap& m = s->maps[map];
+  // poses + log-weights + observations + descriptor + prefix entry, each padded
+  return align_up((size_t)n * 12) + align_up((size_t)n * 4) + align_up((size_t)m.n_rays * 4) + sizeof(FilterDev) +
+         sizeof(int64_t);
+}
+
+// Pack a lane's admitted batch into its staging buffer and launch it.  Called
+// with the lock held; HIP calls only enqueue work.
+cddt_status launch_lane(cddt_server_s* s, Lane& L) {
+  const size_t nb = L.batch.size();
+  const size_t desc_bytes = align_up(sizeof(FilterDev) * nb);
+  const size_t prefix_bytes = align_up(sizeof(int64_t) * (nb + 1));
+  const size_t counter_off = desc_bytes + prefix_bytes;
+  size_t off = counter_off + kAlign;
+  std::vector<FilterDev> fd(nb);
+  std::vector<int64_t> prefix(nb + 1, 0);
+  L.out_off.assign(nb, 0);
+  size_t out_floats = 0;
+  const int64_t ppt = s->cfg.tuning.particles_per_tile;
+  for (size_t k = 0; k < nb; ++k) {
+    Request* r = L.batch[k];
+    const ServedMap& m = s->maps[r->map];
+    const size_t n = (size_t)r->n;
+    float* hp = (float*)(L.h_in + off);
+    std::memcpy(hp, r->poses.data(), n * 12);
+    const char* dp = L.d_arena + off;
+    off += align_up(n * 12);
+    std::memcpy(L.h_in + off, r->obs.data(), (size_t)m.n_rays * 4);
+    const int32_t* dobs = (const int32_t*)(L.d_arena + off);
+    off += align_up((size_t)m.n_rays * 4);
+    FilterDev d{};
+    d.map = m.map->dev();
+    d.px = (const float*)dp;
+    d.py = (const float*)dp + n;
+    d.pth = (const float*)dp + 2 * n;
+    d.offsets = m.d_offsets;
+    d.obs = dobs;
+    d.table = m.table;
+    d.ranges = nullptr;
+    d.n_particles = (int64_t)n;
+    d.n_rays = m.n_rays;
+    d.pair_offset = m.pair;
+    d.max_range = m.max_range;
+    L.out_off[k] = out_floats;
+    out_floats += align_up(n * 4) / 4;
+    fd[k] = d;
+    prefix[k + 1] = prefix[k] + ((int64_t)n + ppt - 1) / ppt;
+  }
+  const size_t in_bytes = off;
+  for (size_t k = 0; k < nb; ++k) fd[k].logw = (float*)(L.d_arena + in_bytes) + L.out_off[k];
+  std::memcpy(L.h_in, fd.data(), sizeof(FilterDev) * nb);
+  std::memcpy(L.h_in + desc_bytes, prefix.data(), sizeof(int64_t) * (nb + 1));
+  CDDT_HIP(hipMemcpyAsync(L.d_arena, L.h_in, in_bytes, hipMemcpyHostToDevice, L.stream));
+  CDDT_TRY(launch_batch((const FilterDev*)L.d_arena, (const int64_t*)(L.d_arena + desc_bytes), (int32_t)nb,
+                        prefix[nb], s->cfg.tuning, (unsigned long long*)(L.d_arena + counter_off), s->cus,
+                        L.stream));
+  CDDT_HIP(hipMemcpyAsync(L.h_out, L.d_arena + in_bytes, out_floats * 4, hipMemcpyDeviceToHost, L.stream));
+  CDDT_HIP(hipEventRecord(L.done, L.stream));
+  return CDDT_OK;
+}
+
+void fail_batch(cddt_server_s* s, Lane& L) {
+  const double t = s->now();
+  for (Request* r : L.batch) {  // report NaN weights for a batch that could not run
+    r->logw.assign((size_t)r->n, __builtin_nanf(""));
+    r->done = true;
+    r->done_t = t;
+    s->times[r->id] = {r->submit_t, t};
+  }
+  L.batch.clear();
+  s->cv_done.notify_all();
+}
+
+void scheduler(cddt_server_s* s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    bool any_busy = false;
+    // retire finished batches
+    for (Lane& L : s->lanes) {
+      if (!L.busy) continue;
+      const hipError_t q = hipEventQuery(L.done);
+      if (q == hipErrorNotReady) {
+        any_busy = true;
+        continue;
+      }
+      if (q != hipSuccess) {
+        s->error = hipGetErrorString(q);
+        s->bytes_in_flight -= (int64_t)L.bytes;
+        L.bytes = 0;
+        L.busy = false;
+        fail_batch(s, L);
+        continue;
+      }
+      const double t = s->now();
+      for (size_t k = 0; k < L.batch.size(); ++k) {
+        Request* r = L.batch[k];
+        r->logw.assign(L.h_out + L.out_off[k], L.h_out + L.out_off[k] + r->n);
+        r->done_t = t;
+        r->done = true;
+        s->times[r->id] = {r->submit_t, t};
+        s->stats.completed++;
+        s->stats.rays += (int64_t)r->n * s->maps[r->map].n_rays;
+        r->poses.clear();
+        r->poses.shrink_to_fit();
+      }
+      s->bytes_in_flight -= (int64_t)L.bytes;
+      L.batch.clear();
+      L.bytes = 0;
+      L.busy = false;
+      s->cv_done.notify_all();
+    }
+    // admit queued requests into idle lanes
+    for (Lane& L : s->lanes) {
+      if (L.busy || s->queue.empty()) continue;
+      size_t used = 0;
+      while (!s->queue.empty() && (int32_t)L.batch.size() < s->cfg.max_batch) {
+        Request* r = s->queue.front();
+        if (used + r->bytes > L.arena) break;
+        used += r->bytes;
+        L.batch.push_back(r);
+        s->queue.pop_front();
+      }
+      if (L.batch.empty()) continue;
+      L.bytes = used;
+      if (launch_lane(s, L) != CDDT_OK) {
+        s->error = cddt_last_error();
+        L.bytes = 0;
+        fail_batch(s, L);
+        continue;
+      }
+      L.busy = true;
+      any_busy = true;
+      s->stats.batches++;
+      s->bytes_in_flight += (int64_t)used;
+      s->stats.peak_bytes = std::max<int64_t>(s->stats.peak_bytes, s->bytes_in_flight);
+    }
+    const double t = s->now();
+    if (any_busy && s->busy_since < 0) s->busy_since = t;
+    if (!any_busy && s->busy_since >= 0) {
+      s->stats.busy_seconds += t - s->busy_since;
+      s->busy_since = -1.0;
+    }
+    if (s->stop && !any_busy) break;
+    if (any_busy) {
+      // batches in flight: poll their events again shortly (new arrivals wake us too)
+      s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+    } else if (s->queue.empty()) {
+      s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+    }
+  }
+}
+
+void destroy_lanes(cddt_server_s* s) {
+  for (Lane& L : s->lanes) {
+    if (L.done) (void)hipEventDestroy(L.done);
+    if (L.stream) (void)hipStreamDestroy(L.stream);
+    if (L.d_arena) (void)hipFree(L.d_arena);
+    if (L.h_in) (void)hipHostFree(L.h_in);
+    if (L.h_out) (void)hipHostFree(L.h_out);
+  }
+  s->lanes.clear();
+  for (auto& m : s->maps)
+    if (m.d_offsets) (void)hipFree(m.d_offsets);
+  s->maps.clear();
+}
+
+}  // namespace
+}  // namespace cddt
+
 using namespace cddt;
+
 extern "C" {
-cddt_status cddt_server_create(const cddt_map*, int32_t, const float* const*, const int32_t*, const float* const*,
-                               const int32_t*, const cddt_server_config*, cddt_server*) {
-  return fail(CDDT_EINTERNAL, "server not available in this build");
+
+cddt_status cddt_server_create(const cddt_map* maps_h, int32_t n_maps, const float* const* offsets_h,
+                               const int32_t* n_rays_h, const float* const* log_tables, const int32_t* max_range_h,
+                               const cddt_server_config* config_h, cddt_server* out_h) {
+  if (!out_h) return fail(CDDT_EINVAL, "cddt_server_create: out_h is NULL");
+  *out_h = nullptr;
+  if (!maps_h || !offsets_h || !n_rays_h || !log_tables || !max_range_h || !config_h || n_maps < 1)
+    return fail(CDDT_EINVAL, "cddt_server_create: NULL argument or no maps");
+  const cddt_server_config& c = *config_h;
+  if (c.n_lanes < 1 || c.n_lanes > 8) return fail(CDDT_EINVAL, "cddt_server_create: n_lanes must be in 1..8");
+  if (c.max_batch < 1 || c.max_batch > 4096) return fail(CDDT_EINVAL, "cddt_server_create: max_batch in 1..4096");
+  if (c.max_rays < 1 || c.max_rays > kMaxRays) return fail(CDDT_EINVAL, "cddt_server_create: max_rays in 1..1024");
+  if (c.budget_bytes < (int64_t)c.n_lanes * 4096) return fail(CDDT_EINVAL, "cddt_server_create: budget too small");
+  CDDT_TRY(check_tuning(c.tuning));
+  for (int32_t i = 0; i < n_maps; ++i) {
+    if (!maps_h[i] || !offsets_h[i] || !log_tables[i]) return fail(CDDT_EINVAL, "cddt_server_create: NULL map entry");
+    if (n_rays_h[i] < 1 || n_rays_h[i] > c.max_rays) return fail(CDDT_EINVAL, "cddt_server_create: bad n_rays");
+    if (max_range_h[i] < 0 || max_range_h[i] > 65535) return fail(CDDT_EINVAL, "cddt_server_create: bad max_range");
+  }
+  cddt_server_s* s = new cddt_server_s();
+  s->cfg = c;
+  s->cus = cddt_device_cus();
+  (void)hipGetDevice(&s->device);
+  s->t0 = Clock::now();
+  auto bail = [&](const std::string& msg) {
+    destroy_lanes(s);
+    delete s;
+    return fail(CDDT_EDEVICE, msg);
+  };
+  for (int32_t i = 0; i < n_maps; ++i) {
+    ServedMap m{};
+    m.map = maps_h[i];
+    m.n_rays = n_rays_h[i];
+    m.pair = cddt_pair_offset(offsets_h[i], n_rays_h[i]);
+    m.table = log_tables[i];
+    m.max_range = max_range_h[i];
+    if (hipMalloc(&m.d_offsets, 4 * (size_t)m.n_rays) != hipSuccess) return bail("cddt_server_create: hipMalloc");
+    s->maps.push_back(m);
+    if (hipMemcpy(m.d_offsets, offsets_h[i], 4 * (size_t)m.n_rays, hipMemcpyHostToDevice) != hipSuccess)
+      return bail("cddt_server_create: offsets upload");
+  }
+  const size_t arena = (size_t)(c.budget_bytes / c.n_lanes);
+  s->lanes.resize(c.n_lanes);
+  for (Lane& L : s->lanes) {
+    L.arena = arena;
+    const size_t fixed = align_up(sizeof(FilterDev) * c.max_batch) + align_up(sizeof(int64_t) * (c.max_batch + 1)) +
+                         kAlign;
+    if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&L.d_arena, fixed + arena) != hipSuccess ||
+        hipHostMalloc((void**)&L.h_in, fixed + arena, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&L.h_out, arena, hipHostMallocDefault) != hipSuccess)
+      return bail("cddt_server_create: lane allocation failed");
+  }
+  s->sched = std::thread(scheduler, s);
+  *out_h = s;
+  return CDDT_OK;
 }
-cddt_status cddt_server_submit(cddt_server, int32_t, const float*, const float*, const float*, int32_t,
-                               const int32_t*, int64_t*) { return CDDT_EINTERNAL; }
-cddt_status cddt_server_poll(cddt_server, int64_t, float*, int32_t*) { return CDDT_EINTERNAL; }
-cddt_status cddt_server_wait(cddt_server, int64_t, float*) { return CDDT_EINTERNAL; }
-cddt_status cddt_server_times(cddt_server, int64_t, double*, double*) { return CDDT_EINTERNAL; }
-cddt_status cddt_server_stats_get(cddt_server, cddt_server_stats*) { return CDDT_EINTERNAL; }
-double cddt_server_now(cddt_server) { return 0.0; }
-cddt_status cddt_server_destroy(cddt_server) { return CDDT_OK; }
+
+cddt_status cddt_server_submit(cddt_server s, int32_t map_index, const float* px_h, const float* py_h,
+                               const float* ptheta_h, int32_t n_particles, const int32_t* obs_h, int64_t* id_h) {
+  if (!s || !id_h) return fail(CDDT_EINVAL, "cddt_server_submit: NULL argument");
+  if (map_index < 0 || map_index >= (int32_t)s->maps.size()) return fail(CDDT_EINVAL, "cddt_server_submit: bad map");
+  if (n_particles < 0 || (n_particles > 0 && (!px_h || !py_h || !ptheta_h)) || !obs_h)
+    return fail(CDDT_EINVAL, "cddt_server_submit: bad particle or observation arrays");
+  const size_t bytes = request_bytes(s, map_index, n_particles);
+  Request* r = new Request();
+  r->map = map_index;
+  r->n = n_particles;
+  r->bytes = bytes;
+  r->poses.resize((size_t)n_particles * 3);
+  std::memcpy(r->poses.data(), px_h, 4 * (size_t)n_particles);
+  std::memcpy(r->poses.data() + n_particles, py_h, 4 * (size_t)n_particles);
+  std::memcpy(r->poses.data() + 2 * (size_t)n_particles, ptheta_h, 4 * (size_t)n_particles);
+  r->obs.assign(obs_h, obs_h + s->maps[map_index].n_rays);
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (bytes > s->lanes[0].arena || s->stop) {
+      s->stats.rejected++;
+      delete r;
+      return fail(CDDT_EBUSY, "cddt_server_submit: request larger than a lane's share of the budget");
+    }
+    r->id = s->next_id++;
+    r->submit_t = s->now();
+    s->live[r->id] = r;
+    s->queue.push_back(r);
+    s->stats.submitted++;
+    *id_h = r->id;
+  }
+  s->cv_work.notify_one();
+  return CDDT_OK;
 }
+
+cddt_status cddt_server_poll(cddt_server s, int64_t id, float* logw_h, int32_t* done_h) {
+  if (!s || !done_h) return fail(CDDT_EINVAL, "cddt_server_poll: NULL argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->live.find(id);
+  if (it == s->live.end()) return fail(CDDT_EINVAL, "cddt_server_poll: unknown or already collected request");
+  Request* r = it->second;
+  *done_h = r->done ? 1 : 0;
+  if (r->done) {
+    if (logw_h) std::memcpy(logw_h, r->logw.data(), 4 * r->logw.size());
+    s->live.erase(it);
+    delete r;
+  }
+  return CDDT_OK;
+}
+
+cddt_status cddt_server_wait(cddt_server s, int64_t id, float* logw_h) {
+  if (!s) return fail(CDDT_EINVAL, "cddt_server_wait: NULL server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->live.find(id);
+  if (it == s->live.end()) return fail(CDDT_EINVAL, "cddt_server_wait: unknown or already collected request");
+  Request* r = it->second;
+  s->cv_done.wait(lk, [&] { return r->done; });
+  if (logw_h) std::memcpy(logw_h, r->logw.data(), 4 * r->logw.size());
+  s->live.erase(id);
+  delete r;
+  return CDDT_OK;
+}
+
+cddt_status cddt_server_times(cddt_server s, int64_t id, double* submit_h, double* done_h) {
+  if (!s || !submit_h || !done_h) return fail(CDDT_EINVAL, "cddt_server_times: NULL argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->times.find(id);
+  if (it == s->times.end()) return fail(CDDT_EINVAL, "cddt_server_times: request not finished");
+  *submit_h = it->second.first;
+  *done_h = it->second.second;
+  return CDDT_OK;
+}
+
+cddt_status cddt_server_stats_get(cddt_server s, cddt_server_stats* out_h) {
+  if (!s || !out_h) return fail(CDDT_EINVAL, "cddt_server_stats_get: NULL argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  *out_h = s->stats;
+  if (s->busy_since >= 0) out_h->busy_seconds += s->now() - s->busy_since;
+  return CDDT_OK;
+}
+
+double cddt_server_now(cddt_server s) { return s ? s->now() : 0.0; }
+
+cddt_status cddt_server_destroy(cddt_server s) {
+  if (!s) return CDDT_OK;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
+    for (Request* r : s->queue) {  // never admitted: dropped
+      s->live.erase(r->id);
+      delete r;
+    }
+    s->queue.clear();
+  }
+  s->cv_work.notify_all();
+  if (s->sched.joinable()) s->sched.join();
+  for (auto& kv : s->live) delete kv.second;
+  s->live.clear();
+  destroy_lanes(s);
+  delete s;
+  return CDDT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+"""Serving loop: results are the same alone and in the mix, under budget admission."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1705_01167_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _setup(seed=0, sides=(300, 500, 800), bins=(108, 200, 360), M=300):
+    from paper_1705_01167_amd import cddt
+    rng = wl.rng_for(501, seed)
+    maps, offs, tabs, occs = [], [], [], []
+    for f, (side, n) in enumerate(zip(sides, bins)):
+        occ = wl.building_map(rng, side, side)
+        maps.append(cddt.Map(_dev(occ), n))
+        offs.append(wl.ray_offsets(61))
+        tabs.append(_dev(wl.beam_table(M, wl.beam_params(rng))))
+        occs.append(occ)
+    return rng, maps, offs, tabs, occs, M
+
+
+def _requests(rng, occs, M, k):
+    reqs = []
+    for i in range(k):
+        m = i % len(occs)
+        n = int(round(np.exp(rng.uniform(np.log(17), np.log(1639)))))
+        px, py, pth = wl.free_poses(rng, occs[m], n)
+        obs = rng.integers(0, M + 1, 61).astype(np.int32)
+        reqs.append((m, px, py, pth, obs))
+    return reqs
+
+
+def test_alone_equals_mix_equals_plain():
+    from paper_1705_01167_amd import cddt
+    rng, maps, offs, tabs, occs, M = _setup()
+    reqs = _requests(rng, occs, M, 120)
+    srv = cddt.Server(maps, offs, tabs, [M] * 3, budget_bytes=8 << 20, n_lanes=4, max_batch=32)
+    alone = []
+    for (m, px, py, pth, obs) in reqs:
+        alone.append(srv.wait(srv.submit(m, px, py, pth, obs)))
+    ids = [srv.submit(*r) for r in reqs]          # all at once: batched, several lanes in flight
+    mixed = [srv.wait(i) for i in ids]
+    st = srv.stats()
+    assert st["completed"] == 240 and st["rejected"] == 0
+    assert st["batches"] < 240                     # requests really were batched together
+    assert st["peak_bytes"] <= 8 << 20
+    for a, b, (m, px, py, pth, obs) in zip(alone, mixed, reqs):
+        assert a.tobytes() == b.tobytes()
+        plain = maps[m].weight(_dev(px), _dev(py), _dev(pth), _dev(offs[m]), _dev(obs), tabs[m], M)
+        assert plain.cpu().numpy().tobytes() == a.tobytes()
+    for i in ids:
+        s, d = srv.times(i)
+        assert 0 <= s <= d
+    srv.close()
+
+
+def test_budget_admission_and_reject():
+    from paper_1705_01167_amd import cddt
+    rng, maps, offs, tabs, occs, M = _setup(seed=1, sides=(256,), bins=(108,))
+    # each lane holds about 2 mid-size requests: many small batches, still exact
+    srv = cddt.Server(maps, offs, tabs, [M], budget_bytes=2 * 64 * 1024, n_lanes=2, max_batch=64)
+    reqs = _requests(rng, occs, M, 40)
+    reqs = [r for r in reqs if r[1].size <= 1500]
+    ids = [srv.submit(*r) for r in reqs]
+    outs = [srv.wait(i) for i in ids]
+    st = srv.stats()
+    assert st["peak_bytes"] <= 2 * 64 * 1024 and st["batches"] >= len(reqs) // 8
+    for o, (m, px, py, pth, obs) in zip(outs, reqs):
+        plain = maps[m].weight(_dev(px), _dev(py), _dev(pth), _dev(offs[m]), _dev(obs), tabs[m], M)
+        assert plain.cpu().numpy().tobytes() == o.tobytes()
+    big = wl.free_poses(rng, occs[0], 20000)
+    with pytest.raises(cddt.CddtError) as e:
+        srv.submit(0, *big, reqs[0][4])
+    assert e.value.code == cddt.EBUSY
+    assert srv.stats()["rejected"] == 1
+    srv.close()
+
+
+def test_poll_and_close_with_queue():
+    from paper_1705_01167_amd import cddt
+    rng, maps, offs, tabs, occs, M = _setup(seed=2, sides=(400,), bins=(200,))
+    srv = cddt.Server(maps, offs, tabs, [M], budget_bytes=4 << 20, n_lanes=1, max_batch=4)
+    reqs = _requests(rng, occs, M, 30)
+    ids = [srv.submit(*r) for r in reqs]
+    got = {}
+    while len(got) < len(ids):
+        for i in ids:
+            if i not in got:
+                r = srv.poll(i)
+                if r is not None:
+                    got[i] = r
+    assert all(np.isfinite(v).all() for v in got.values())
+    more = [srv.submit(*r) for r in reqs]   # left queued or in flight: close must still return
+    srv.close()
