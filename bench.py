@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Throughput benchmark of batched CDDT ray casting + beam sensor weights on one GPU.
 
-Default workload (one step = one filter step of every filter): 64 particle
-filters on room/corridor maps of uneven size (sides 512..4000), theta bins in
-{108, 200, 360}, 500..20000 particles each, 61 rays per particle over 270
-degrees, max range 500, fused cast + log-weight in one persistent launch
-replayed from a hipGraph.  The same filters are also run as plain launches
-(one per filter) for comparison.  Inputs are seeded synthetic data resident in
-HBM before timing starts.
+Default workload (`--workload batched`; one step = one filter step of every
+filter): 64 particle filters on room/corridor maps of uneven size (sides
+512..4000), theta bins in {108, 200, 360}, 500..20000 particles each, 61 rays
+per particle over 270 degrees, max range 500, fused cast + log-weight in one
+persistent launch replayed from a hipGraph.  The same filters also run as
+plain launches (one per filter) for comparison.  Inputs are seeded synthetic
+data resident in HBM before timing starts.  The line also carries the gather
+probe, a short serving measurement and the CPU oracle timed on this host.
 
-Prints one JSON line: rays/s (whole job), the roofline of the persistent
-kernel against HBM bandwidth, and the CPU oracle timed on this host.
+Other workloads (each prints its own JSON line): `small` (256^2 rectangle map,
+1000 particles x 61 rays, plain casts), `floor` (2000^2 floor, 2500 particles,
+fused weights), `updates` (4000^2 floor, 1000 toggles + 1M particles x 61
+casts per step), `serving` (8 resident maps, Poisson arrivals swept over load),
+`probe` (random-gather bandwidth only).
 """
 from __future__ import annotations
 
@@ -38,11 +42,17 @@ MAX_RANGE = 500
 # + the second bracketing zero point of each of the 21 pairs 4 + one table
 # entry per ray 4.
 BYTES_PER_PARTICLE = 12 + 1 + 4 + SEARCHES * (8 + 4) + (RAYS - SEARCHES) * 4 + RAYS * 4
+# Algorithmic bytes per plain cast: pose 12 + occupancy 1 + header 8 + zero point 4 + range out 4.
+BYTES_PER_CAST = 12 + 1 + 8 + 4 + 4
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("query_device.h", "batch.hip", "cddt_common.h"):
+    for f in ("query_device.h", "band_layout.h", "batch.hip", "cddt_common.h"):
         with open(os.path.join(ROOT, "paper_1705_01167_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -61,15 +71,42 @@ def measured_traffic(name: str, particles: int):
     return d.get("bytes_per_launch")
 
 
-def build_batched(args):
+def t_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def timed(fn, steps: int, warmup: int, stream):
+    """Run fn(stream) warmup + steps times; (wall seconds, HIP-event ms per step) over the timed steps."""
+    import torch
+    for _ in range(warmup):
+        fn(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        fn(stream)
+    e1.record(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1) / steps
+
+
+# ---------------------------------------------------------------------------
+# Batched filters (default workload)
+# ---------------------------------------------------------------------------
+def build_batched(n_filters: int):
     import torch
     from paper_1705_01167_amd import cddt
     from paper_1705_01167_amd import workloads as wl
 
-    specs = wl.batched_specs(wl.rng_for(wl.BATCHED, wl.S_SPEC), n_filters=args.filters)
+    specs = wl.batched_specs(wl.rng_for(wl.BATCHED, wl.S_SPEC), n_filters=n_filters)
     off_h = wl.ray_offsets(RAYS)
     pair = cddt.pair_offset(off_h)
-    off = torch.from_numpy(off_h).cuda()
+    off = t_dev(off_h)
     filters, keep, host = [], [], []
     t_gen = t_build = 0.0
     for f, sp in enumerate(specs):
@@ -79,13 +116,12 @@ def build_batched(args):
         obs, _ = wl.observations(wl.rng_for(wl.BATCHED, wl.S_OBS, f), occ, off_h, MAX_RANGE)
         table = wl.beam_table(MAX_RANGE, wl.beam_params(wl.rng_for(wl.BATCHED, wl.S_TABLE, f)))
         t1 = time.perf_counter()
-        occ_d = torch.from_numpy(occ).cuda()
+        occ_d = t_dev(occ)
         m = cddt.Map(occ_d, sp["theta_bins"])
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         del occ_d
-        d = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda()
-             for k, v in dict(px=px, py=py, pth=pth, obs=obs, table=table).items()}
+        d = {k: t_dev(v) for k, v in dict(px=px, py=py, pth=pth, obs=obs, table=table).items()}
         lw = torch.zeros(sp["particles"], dtype=torch.float32, device="cuda")
         filters.append(cddt.make_filter(m, d["px"], d["py"], d["pth"], off, d["obs"], d["table"], MAX_RANGE,
                                         lw, pair=pair))
@@ -96,77 +132,45 @@ def build_batched(args):
     return specs, filters, keep, host, off_h, dict(generate_s=t_gen, gpu_build_s=t_build)
 
 
-def cpu_baseline(specs, host, off_h, budget_s: float):
-    """The C++ oracle (plain CDDT, std::thread over particles) on the smallest maps."""
+def cpu_baseline(specs, host, off_h, budget_s: float, max_build_s: float = 40.0):
+    """The C++ oracle (plain CDDT, std::thread over particles) on filters spread over map sizes."""
     from oracle import ref as oref
     threads = max(1, len(os.sched_getaffinity(0)))
-    order = sorted(range(len(specs)), key=lambda f: specs[f]["side"] ** 2 * specs[f]["theta_bins"])
-    rays = 0
-    secs = 0.0
-    used = []
-    for f in order:
+    order = sorted(range(len(specs)), key=lambda f: specs[f]["side"])
+    picks = sorted({order[int(round(q * (len(order) - 1)))] for q in (0.0, 0.25, 0.5, 0.75, 1.0)})
+    built, build_s = [], 0.0
+    for f in picks:
         h = host[f]
-        rm = oref.RefCDDT(h["occ"], h["n"], threads=threads)
         t0 = time.perf_counter()
-        rm.weight(h["px"], h["py"], h["pth"], off_h, h["obs"], h["table"], MAX_RANGE, threads=threads)
-        dt = time.perf_counter() - t0
-        rm.close()
-        rays += h["px"].size * RAYS
-        secs += dt
-        used.append(f"{specs[f]['side']}^2/n{specs[f]['theta_bins']}/{specs[f]['particles']}p")
-        if secs >= budget_s or len(used) >= 6:
+        built.append((f, oref.RefCDDT(h["occ"], h["n"], threads=threads)))
+        build_s += time.perf_counter() - t0
+        if build_s > max_build_s:
             break
+    rays, secs, passes = 0, 0.0, 0
+    while secs < budget_s and passes < 1000:
+        for f, rm in built:
+            h = host[f]
+            t0 = time.perf_counter()
+            rm.weight(h["px"], h["py"], h["pth"], off_h, h["obs"], h["table"], MAX_RANGE, threads=threads)
+            secs += time.perf_counter() - t0
+            rays += h["px"].size * RAYS
+        passes += 1
+    names = [f"{specs[f]['side']}^2/n{specs[f]['theta_bins']}/{specs[f]['particles']}p" for f, _ in built]
+    for _, rm in built:
+        rm.close()
     return {"value": rays / secs, "unit": "rays/s", "cores": threads, "kind": "oracle",
-            "sample": (f"plain C++ CDDT oracle (sorted vectors, std::upper_bound, double log-sum), "
-                       f"{threads} threads, all particles of the {len(used)} smallest of "
-                       f"{len(specs)} filters [{', '.join(used)}], {rays} rays in {secs:.2f} s; "
-                       f"structure build excluded")}
+            "sample": (f"plain C++ CDDT oracle (sorted vectors, std::upper_bound, double log-sum) with "
+                       f"{threads} threads on {len(built)} of {len(specs)} filters spread over map size "
+                       f"[{', '.join(names)}], all their particles, {passes} passes, {rays} rays in "
+                       f"{secs:.1f} s; oracle structure build ({build_s:.1f} s) excluded")}
 
 
-def copy_calibration(mib: int) -> None:
-    """A plain device-to-device copy of known size, to scale the HBM byte counters."""
-    import torch
-    n = mib * (1 << 20)
-    a = torch.ones(n, dtype=torch.uint8, device="cuda")
-    b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}), flush=True)
-
-
-def main():
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--filters", type=int, default=64)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle timing to aim for")
-    ap.add_argument("--no-tune-cache", action="store_true")
-    ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--tuning", type=str, default=None,
-                    help="fixed persistent-kernel tuning 'ppt,waves,blocks' (skips the autotuner)")
-    ap.add_argument("--no-graph", action="store_true", help="launch the plan directly instead of a graph")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="only run a plain device copy of this many MiB (counter calibration) and exit")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        copy_calibration(args.copy_calibration)
-        return
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1).",
-              file=sys.stderr)
-        sys.exit(2)
-
+def run_batched(args) -> dict:
     import torch
     from paper_1705_01167_amd import cddt, tune
 
-    log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    cddt.lib()
     log("bench: generating and building maps")
-    specs, filters, keep, host, off_h, times = build_batched(args)
+    specs, filters, keep, host, off_h, times = build_batched(args.filters)
     particles = sum(s["particles"] for s in specs)
     rays_per_step = particles * RAYS
     stats = [k[0].info() for k in keep]
@@ -175,8 +179,7 @@ def main():
 
     stream = torch.cuda.Stream()
     plan = cddt.Plan(filters, stream=stream, keepalive=keep)
-    sig = tune.signature(len(specs), particles, [s["theta_bins"] for s in specs],
-                         torch.cuda.get_device_name(0))
+    sig = tune.signature(len(specs), particles, [s["theta_bins"] for s in specs], torch.cuda.get_device_name(0))
     t0 = time.perf_counter()
     if args.tuning:
         best = tuple(int(v) for v in args.tuning.split(","))
@@ -186,9 +189,8 @@ def main():
         best, best_ms, _ = tune.autotune(plan, sig, use_cache=not args.no_tune_cache, stream=stream)
     log(f"bench: tuning {best} ({best_ms:.3f} ms) in {time.perf_counter() - t0:.1f} s")
 
-    # reference outputs from plain launches, then the batched graph must match them
-    with torch.cuda.stream(stream):
-        plan.run_plain(stream)
+    # reference outputs from plain launches; the batched graph must reproduce them
+    plan.run_plain(stream)
     stream.synchronize()
     plain_out = [k[2].clone() for k in keep]
     for k in keep:
@@ -197,37 +199,15 @@ def main():
     step = plan.run if args.no_graph else plan.replay
     if not args.no_graph:
         plan.capture(stream)
-
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for _ in range(args.warmup):
-        step(stream)
-    stream.synchronize()
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step(stream)
-    ev1.record(stream)
-    stream.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall
-    batched_ms = ev0.elapsed_time(ev1) / args.steps
+    wall, batched_ms = timed(step, args.steps, args.warmup, stream)
     exact = all(torch.equal(a, k[2]) for a, k in zip(plain_out, keep))
-
-    for _ in range(max(1, args.warmup // 2)):
-        plan.run_plain(stream)
-    stream.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        plan.run_plain(stream)
-    ev1.record(stream)
-    stream.synchronize()
-    plain_ms = ev0.elapsed_time(ev1) / args.steps
+    _, plain_ms = timed(plan.run_plain, args.steps, max(1, args.warmup // 2), stream)
 
     value = rays_per_step / (wall / args.steps)
     algo_bytes = particles * BYTES_PER_PARTICLE
     achieved = algo_bytes / (batched_ms * 1e-3) / 1e9
     traffic = measured_traffic("k_batch", particles)
+    probe = cddt.probe_gather() if not args.no_probe else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -252,6 +232,7 @@ def main():
             "particles": particles,
             "rays_per_step": rays_per_step,
             "zero_points": int(sum(s["zero_points"] for s in stats)),
+            "bands": int(sum(s["rows"] for s in stats)),
             "structure_bytes": int(sum(s["device_bytes"] for s in stats)),
             "tuning": {"particles_per_tile": best[0], "waves_per_block": best[1], "blocks_per_cu": best[2]},
             "parallelism": "single GPU",
@@ -272,13 +253,282 @@ def main():
             "bytes_per_particle": BYTES_PER_PARTICLE,
             "kernel_ms": batched_ms,
         },
+        "gather_probe": probe,
         "cpu_baseline": None,
         "context": "paper: 2500 particles x 61 rays at 40 Hz = 6.1e6 rays/s on one Jetson TX1 CPU thread",
     }
+    if traffic is not None and probe is not None:
+        out["roofline"]["traffic_GBps"] = traffic / (batched_ms * 1e-3) / 1e9
+        out["roofline"]["traffic_frac_of_probe"] = out["roofline"]["traffic_GBps"] / probe["GBps"]
+    plan.close()
+    del keep, filters
+    torch.cuda.empty_cache()
+    if not args.no_serving:
+        log("bench: serving summary")
+        out["serving"] = run_serving(args, summary=True)
     if not args.no_cpu:
         log("bench: timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(specs, host, off_h, args.cpu_budget)
-    plan.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Single-map workloads
+# ---------------------------------------------------------------------------
+def run_small(args) -> dict:
+    import torch
+    from paper_1705_01167_amd import cddt
+    from paper_1705_01167_amd import workloads as wl
+    occ = wl.rect_map(wl.rng_for(wl.SMALL, wl.S_MAP))
+    m = cddt.Map(t_dev(occ), 108)
+    px, py, pth = wl.free_poses(wl.rng_for(wl.SMALL, wl.S_POSES), occ, 1000)
+    off = wl.ray_offsets(RAYS)
+    x = t_dev(np.repeat(px, RAYS))
+    y = t_dev(np.repeat(py, RAYS))
+    th = t_dev((np.repeat(pth, RAYS) + np.tile(off, px.size)).astype(np.float32))
+    out_r = torch.empty(x.numel(), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.Stream()
+    wall, ms = timed(lambda s: m.cast(x, y, th, MAX_RANGE, out=out_r, stream=s), args.steps, args.warmup, stream)
+    n = x.numel()
+    return {"metric": "ray casts/sec (plain cddt_cast)", "value": n / (wall / args.steps), "unit": "rays/s",
+            "ms_per_step": wall / args.steps * 1e3, "kernel_ms": ms, "steps": args.steps,
+            "config": {"workload": "small: 256^2 rectangles map (~10% occupied), 108 bins, 1000 particles x 61 "
+                                   "rays as 61000 plain casts, max range 500",
+                       "occupancy": float(occ.mean()), **{k: v for k, v in m.info().items()
+                                                          if k in ("zero_points", "rows", "edge_cells")}},
+            "roofline": {"bound": "latency (L2-resident structure)", "algorithmic_GBps":
+                         n * BYTES_PER_CAST / (ms * 1e-3) / 1e9}}
+
+
+def run_floor(args) -> dict:
+    import torch
+    from paper_1705_01167_amd import cddt
+    from paper_1705_01167_amd import workloads as wl
+    occ = wl.building_map(wl.rng_for(wl.FLOOR, wl.S_MAP), 2000, 2000)
+    m = cddt.Map(t_dev(occ), 200)
+    off_h = wl.ray_offsets(RAYS)
+    px, py, pth = wl.free_poses(wl.rng_for(wl.FLOOR, wl.S_POSES), occ, 2500)
+    table = t_dev(wl.beam_table(MAX_RANGE, wl.beam_params(wl.rng_for(wl.FLOOR, wl.S_TABLE))))
+    obs, _ = wl.observations(wl.rng_for(wl.FLOOR, wl.S_OBS), occ, off_h, MAX_RANGE)
+    d = [t_dev(a) for a in (px, py, pth, off_h, obs)]
+    lw = torch.empty(2500, dtype=torch.float32, device="cuda")
+    pair = cddt.pair_offset(off_h)
+    stream = torch.cuda.Stream()
+    wall, ms = timed(lambda s: m.weight(*d, table, MAX_RANGE, pair=pair, logw=lw, stream=s), args.steps,
+                     args.warmup, stream)
+    n = 2500 * RAYS
+    return {"metric": "ray casts/sec (fused cddt_weight, one filter)", "value": n / (wall / args.steps),
+            "unit": "rays/s", "ms_per_step": wall / args.steps * 1e3, "kernel_ms": ms, "steps": args.steps,
+            "config": {"workload": "floor: 2000^2 room/corridor map (~4% occupied), 200 bins, 2500 particles x "
+                                   "61 rays, fused beam log-weight (501^2 table), max range 500",
+                       "occupancy": float(occ.mean()), **{k: v for k, v in m.info().items()
+                                                          if k in ("zero_points", "rows", "edge_cells")}},
+            "roofline": {"bound": "latency (MALL-resident structure)",
+                         "algorithmic_GBps": 2500 * BYTES_PER_PARTICLE / (ms * 1e-3) / 1e9}}
+
+
+def run_updates(args) -> dict:
+    import torch
+    from paper_1705_01167_amd import cddt
+    from paper_1705_01167_amd import workloads as wl
+    occ = wl.building_map(wl.rng_for(wl.UPDATES, wl.S_MAP), 4000, 4000)
+    n, P = 200, 1_000_000
+    t0 = time.perf_counter()
+    m = cddt.Map(t_dev(occ), n)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    off = t_dev(wl.ray_offsets(RAYS))
+    px, py, pth = wl.free_poses(wl.rng_for(wl.UPDATES, wl.S_POSES), occ, P)
+    x = t_dev(px).repeat_interleave(RAYS)
+    y = t_dev(py).repeat_interleave(RAYS)
+    th = (t_dev(pth)[:, None] + off[None, :]).reshape(-1).contiguous()
+    out_r = torch.empty(x.numel(), dtype=torch.int32, device="cuda")
+    rng = wl.rng_for(wl.UPDATES, wl.S_OPS)
+    cur = occ.copy()
+    steps = args.steps
+    ops = []
+    for _ in range(steps + args.warmup):
+        xs, ys, vals = wl.toggle_ops(rng, cur, 1000)
+        wl.apply_ops(cur, xs, ys, vals)
+        ops.append((xs, ys, vals))
+    stream = torch.cuda.Stream()
+    upd_s = cast_s = 0.0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for i, (xs, ys, vals) in enumerate(ops):
+        t0 = time.perf_counter()
+        m.update(xs, ys, vals, stream=stream)
+        t1 = time.perf_counter()
+        e0.record(stream)
+        m.cast(x, y, th, MAX_RANGE, out=out_r, stream=stream)
+        e1.record(stream)
+        stream.synchronize()
+        if i >= args.warmup:
+            upd_s += t1 - t0
+            cast_s += e0.elapsed_time(e1) / 1e3
+    fresh = cddt.Map(t_dev(cur), n)
+    same = all((a == b).all() for a, b in zip(m.export(), fresh.export()))
+    rays = x.numel()
+    info = m.info()
+    return {"metric": "ray casts/sec with 1000 cell toggles per step (plain cddt_cast)",
+            "value": rays * steps / (upd_s + cast_s), "unit": "rays/s", "steps": steps,
+            "cast_rays_per_s": rays * steps / cast_s, "update_ms_per_step": upd_s / steps * 1e3,
+            "cast_ms_per_step": cast_s / steps * 1e3, "update_equals_rebuild": bool(same),
+            "build_seconds": build_s, "rebuilds": info["rebuilds"],
+            "config": {"workload": "updates: 4000^2 room/corridor map, 200 bins, each step 1000 random "
+                                   "toggles (incremental update) then 1M particles x 61 rays as plain casts",
+                       **{k: v for k, v in info.items() if k in ("zero_points", "rows", "edge_cells", "capacity")}},
+            "roofline": {"bound": "hbm", "algorithmic_GBps": rays * BYTES_PER_CAST / (cast_s / steps) / 1e9,
+                         "peak": PEAK_HBM_GBS}}
+
+
+# ---------------------------------------------------------------------------
+# Serving
+# ---------------------------------------------------------------------------
+SERVE_SIDES = (1000, 1500, 2000, 2500, 3000, 3500, 4000, 4000)
+
+
+def build_serving():
+    import torch
+    from paper_1705_01167_amd import cddt
+    from paper_1705_01167_amd import workloads as wl
+    rng = wl.rng_for(wl.SERVING, wl.S_SPEC)
+    maps, offs, tabs, pools, obs = [], [], [], [], []
+    off_h = wl.ray_offsets(RAYS)
+    for i, side in enumerate(SERVE_SIDES):
+        n = int(wl.THETA_CHOICES[int(rng.integers(0, 3))])
+        occ = wl.building_map(wl.rng_for(wl.SERVING, wl.S_MAP, i), side, side)
+        maps.append(cddt.Map(t_dev(occ), n))
+        offs.append(off_h)
+        tabs.append(t_dev(wl.beam_table(MAX_RANGE, wl.beam_params(wl.rng_for(wl.SERVING, wl.S_TABLE, i)))))
+        pools.append(wl.free_poses(wl.rng_for(wl.SERVING, wl.S_POSES, i), occ, 20000))
+        obs.append([wl.observations(wl.rng_for(wl.SERVING, wl.S_OBS, 1000 * i + r), occ, off_h, MAX_RANGE)[0]
+                    for r in range(4)])
+    torch.cuda.synchronize()
+    return maps, offs, tabs, pools, obs
+
+
+def make_requests(k: int, seed: int, pools, obs):
+    """Request i: robot i mod 256 on map robot mod 8, log-uniform 17..1639 particles from the map's pool."""
+    from paper_1705_01167_amd import workloads as wl
+    rng = wl.rng_for(wl.SERVING, wl.S_ARRIVALS, seed)
+    out = []
+    for i in range(k):
+        robot = int(rng.integers(0, 256))
+        m = robot % len(pools)
+        n = int(round(math.exp(rng.uniform(math.log(17), math.log(1639)))))
+        s = int(rng.integers(0, 20000 - n))
+        px, py, pth = (a[s:s + n] for a in pools[m])
+        out.append((m, px, py, pth, obs[m][robot % len(obs[m])], n))
+    return out
+
+
+def serve_at(srv, reqs, rate: float | None, seed: int):
+    """Open-loop Poisson arrivals at `rate` requests/s (None: all at once); latency from scheduled arrival."""
+    rng = np.random.default_rng(seed)
+    k = len(reqs)
+    gaps = rng.exponential(1.0 / rate, k) if rate else np.zeros(k)
+    t0 = srv.now() + 0.002
+    arrive = t0 + np.cumsum(gaps)
+    ids = []
+    for i, (m, px, py, pth, ob, n) in enumerate(reqs):
+        while srv.now() < arrive[i]:
+            pass
+        ids.append(srv.submit(m, px, py, pth, ob))
+    done = np.empty(k)
+    for i, rid in enumerate(ids):
+        srv.wait(rid)
+        done[i] = srv.times(rid)[1]
+    lat = done - arrive
+    rays = sum(r[5] for r in reqs) * RAYS
+    span = done.max() - arrive[0]
+    return {"offered_rps": rate, "completed_rps": k / span, "rays_per_s": rays / span,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "requests": k}
+
+
+def run_serving(args, summary: bool = False) -> dict:
+    from paper_1705_01167_amd import cddt
+    maps, offs, tabs, pools, obs = build_serving()
+    srv = cddt.Server(maps, offs, tabs, [MAX_RANGE] * len(maps), budget_bytes=args.serve_budget,
+                      n_lanes=args.serve_lanes, max_batch=args.serve_batch)
+    warm = make_requests(500, 0, pools, obs)
+    serve_at(srv, warm, None, 0)
+    cap_reqs = make_requests(args.serve_requests, 1, pools, obs)
+    cap = serve_at(srv, cap_reqs, None, 1)
+    capacity = cap["completed_rps"]
+    fracs = (0.5, 0.9) if summary else (0.1, 0.25, 0.4, 0.55, 0.7, 0.85, 1.0, 1.2)
+    points = []
+    for j, f in enumerate(fracs):
+        reqs = make_requests(args.serve_requests, 10 + j, pools, obs)
+        points.append(dict(load=f, **serve_at(srv, reqs, f * capacity, 10 + j)))
+        log(f"bench: serving load {f:.2f}: {points[-1]}")
+    st = srv.stats()
+    srv.close()
+    res = {"capacity_rps": capacity, "capacity_rays_per_s": cap["rays_per_s"], "points": points,
+           "stats": st, "config": {"maps": list(SERVE_SIDES), "theta_bins": [m.theta_bins for m in maps],
+                                   "robots": 256, "request_particles": "log-uniform 17..1639",
+                                   "budget_bytes": args.serve_budget, "lanes": args.serve_lanes,
+                                   "max_batch": args.serve_batch}}
+    return res
+
+
+def copy_calibration(mib: int) -> None:
+    """A plain device-to-device copy of known size, to scale the HBM byte counters."""
+    import torch
+    n = mib * (1 << 20)
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="batched",
+                    choices=["batched", "small", "floor", "updates", "serving", "probe"])
+    ap.add_argument("--filters", type=int, default=64)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving summary")
+    ap.add_argument("--no-probe", action="store_true", help="skip the gather-bandwidth probe")
+    ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle timing to aim for")
+    ap.add_argument("--no-tune-cache", action="store_true")
+    ap.add_argument("--tuning", type=str, default=None,
+                    help="fixed persistent-kernel tuning 'ppt,waves,blocks' (skips the autotuner)")
+    ap.add_argument("--no-graph", action="store_true", help="launch the plan directly instead of a graph")
+    ap.add_argument("--serve-requests", type=int, default=3000)
+    ap.add_argument("--serve-budget", type=int, default=256 << 20)
+    ap.add_argument("--serve-lanes", type=int, default=4)
+    ap.add_argument("--serve-batch", type=int, default=512)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (counter calibration) and exit")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1705_01167_amd import cddt
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cddt.lib()
+    if args.workload == "batched":
+        out = run_batched(args)
+    elif args.workload == "small":
+        out = run_small(args)
+    elif args.workload == "floor":
+        out = run_floor(args)
+    elif args.workload == "updates":
+        out = run_updates(args)
+    elif args.workload == "serving":
+        out = {"metric": "serving: completed rays/s and p50/p99 latency vs offered load", **run_serving(args)}
+    else:
+        out = {"gather_probe": [cddt.probe_gather(depth=d) for d in (1, 2, 4, 8)]}
     print(json.dumps(out), flush=True)
 
 

@@ -233,6 +233,18 @@ cddt_status cddt_plan_destroy(cddt_plan p);
 /* Number of compute units of the current device (for tuning spaces). */
 int32_t cddt_device_cus(void);
 
+/* Measurement helper, not part of the method: the band search's memory access
+ * pattern without the search.  Groups of 8 lanes read whole 128-byte lines
+ * (16 bytes per lane) at hashed random line indices of `buf`, keeping `depth`
+ * (1, 2, 4 or 8) independent lines in flight; blocks x 256 threads, each group
+ * reading steps*depth lines.  The achieved line rate x 128 bytes is the
+ * achievable random-gather bandwidth.
+ *   buf   device, `bytes` bytes (a multiple of 128, < 2^39).
+ *   sink  device int32[blocks * 256] (receives a checksum per thread).
+ * Asynchronous.  Errors: EINVAL. */
+cddt_status cddt_probe_gather(const void* buf, int64_t bytes, int32_t blocks, int32_t steps, int32_t depth,
+                              uint32_t seed, int32_t* sink, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching over resident maps.
  * A server keeps maps resident and accepts requests (one robot's particles

@@ -99,6 +99,7 @@ SIGNATURES = {
     "cddt_plan_run_plain": (_i32, [_vp, _vp]),
     "cddt_plan_destroy": (_i32, [_vp]),
     "cddt_device_cus": (_i32, []),
+    "cddt_probe_gather": (_i32, [_vp, _i64, _i32, _i32, _i32, _u32, _vp, _vp]),
     "cddt_server_create": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, C.POINTER(ServerConfig), C.POINTER(_vp)]),
     "cddt_server_submit": (_i32, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, C.POINTER(_i64)]),
     "cddt_server_poll": (_i32, [_vp, _i64, _vp, C.POINTER(_i32)]),
@@ -358,6 +359,31 @@ class Plan:
 
 def device_cus() -> int:
     return int(lib().cddt_device_cus())
+
+
+def probe_gather(gib: float = 4.0, depth: int = 4, steps: int = 64, blocks: int | None = None, reps: int = 3,
+                 stream=None) -> dict:
+    """Achievable random 128-byte-line gather rate (cddt_probe_gather) over a `gib` GiB buffer."""
+    import torch
+    nbytes = int(gib * (1 << 30)) // 128 * 128
+    buf = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    if blocks is None:
+        blocks = device_cus() * 32
+    sink = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    args = (C.c_void_p(buf.data_ptr()), nbytes, int(blocks), int(steps), int(depth))
+    _check(lib().cddt_probe_gather(*args, 1, C.c_void_p(sink.data_ptr()), C.c_void_p(s.cuda_stream)))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for r in range(reps):
+        _check(lib().cddt_probe_gather(*args, 2 + r, C.c_void_p(sink.data_ptr()), C.c_void_p(s.cuda_stream)))
+    e1.record(s)
+    s.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    lines = blocks * 256 // 8 * steps * depth
+    del buf
+    return {"lines_per_s": lines / sec, "GBps": lines * 128 / sec / 1e9, "buffer_GiB": gib, "depth": depth,
+            "blocks": blocks, "steps": steps}
 
 
 class Server:
