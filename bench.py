@@ -234,7 +234,8 @@ def run_batched(args) -> dict:
             "zero_points": int(sum(s["zero_points"] for s in stats)),
             "bands": int(sum(s["rows"] for s in stats)),
             "structure_bytes": int(sum(s["device_bytes"] for s in stats)),
-            "tuning": {"particles_per_tile": best[0], "waves_per_block": best[1], "blocks_per_cu": best[2]},
+            "tuning": {"particles_per_tile": best[0], "waves_per_block": best[1], "blocks_per_cu": best[2],
+                       "group_searches": best[3]},
             "parallelism": "single GPU",
         },
         "batched_rays_per_s_kernel": rays_per_step / (batched_ms * 1e-3),
@@ -498,12 +499,13 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle timing to aim for")
     ap.add_argument("--no-tune-cache", action="store_true")
     ap.add_argument("--tuning", type=str, default=None,
-                    help="fixed persistent-kernel tuning 'ppt,waves,blocks' (skips the autotuner)")
+                    help="fixed persistent-kernel tuning 'ppt,waves,blocks,K' (skips the autotuner)")
     ap.add_argument("--no-graph", action="store_true", help="launch the plan directly instead of a graph")
     ap.add_argument("--serve-requests", type=int, default=3000)
     ap.add_argument("--serve-budget", type=int, default=256 << 20)
     ap.add_argument("--serve-lanes", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=512)
+    ap.add_argument("--probe-gib", type=str, default="4", help="probe buffer sizes in GiB, comma separated")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -528,7 +530,8 @@ def main():
     elif args.workload == "serving":
         out = {"metric": "serving: completed rays/s and p50/p99 latency vs offered load", **run_serving(args)}
     else:
-        out = {"gather_probe": [cddt.probe_gather(depth=d) for d in (1, 2, 4, 8)]}
+        out = {"gather_probe": [cddt.probe_gather(gib=float(g), depth=d) for g in args.probe_gib.split(",")
+                                for d in (1, 4)]}
     print(json.dumps(out), flush=True)
 
 

@@ -46,10 +46,10 @@ class Filter(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("particles_per_tile", C.c_int32), ("waves_per_block", C.c_int32),
-                ("blocks_per_cu", C.c_int32), ("reserved", C.c_int32)]
+                ("blocks_per_cu", C.c_int32), ("group_searches", C.c_int32)]
 
     def as_tuple(self):
-        return (self.particles_per_tile, self.waves_per_block, self.blocks_per_cu)
+        return (self.particles_per_tile, self.waves_per_block, self.blocks_per_cu, self.group_searches)
 
 
 class ServerConfig(C.Structure):
@@ -308,7 +308,7 @@ class Plan:
 
     def __init__(self, filters, tuning: tuple | None = None, stream=None, keepalive=None):
         arr = (Filter * len(filters))(*filters)
-        t = Tuning(*tuning, 0) if tuning is not None else None
+        t = Tuning(*tuning) if tuning is not None else None
         h = C.c_void_p()
         _check(lib().cddt_plan_create(C.cast(arr, C.c_void_p), len(filters),
                                       C.byref(t) if t is not None else None, _stream(stream), C.byref(h)))
@@ -335,7 +335,7 @@ class Plan:
 
     @tuning.setter
     def tuning(self, v):
-        t = Tuning(*v, 0)
+        t = Tuning(*v)
         _check(lib().cddt_plan_set_tuning(self.handle, C.byref(t)))
 
     def run(self, stream=None):
@@ -351,7 +351,7 @@ class Plan:
         _check(lib().cddt_plan_replay(self.handle, _stream(stream)))
 
     def time(self, tuning, reps: int = 5, stream=None) -> float:
-        t = Tuning(*tuning, 0)
+        t = Tuning(*tuning)
         ms = C.c_float()
         _check(lib().cddt_plan_time(self.handle, C.byref(t), int(reps), _stream(stream), C.byref(ms)))
         return float(ms.value)
@@ -390,14 +390,14 @@ class Server:
     """Continuous-batching server over resident maps (cddt_server_*)."""
 
     def __init__(self, maps, offsets, tables, max_ranges, budget_bytes: int = 1 << 30, n_lanes: int = 4,
-                 max_batch: int = 256, tuning=(4, 4, 8)):
+                 max_batch: int = 256, tuning=(4, 4, 8, 5)):
         n = len(maps)
         self._offsets = [np.ascontiguousarray(np.asarray(o, np.float32)) for o in offsets]
         self._tables = list(tables)              # keep device tables alive
         self._maps = list(maps)
         self._n_rays = [o.size for o in self._offsets]
         cfg = ServerConfig(int(budget_bytes), int(n_lanes), int(max_batch), int(max(self._n_rays)), 0,
-                           Tuning(*tuning, 0))
+                           Tuning(*tuning))
         handles = (C.c_void_p * n)(*[m.handle.value for m in maps])
         offp = (C.c_void_p * n)(*[o.ctypes.data for o in self._offsets])
         nr = (C.c_int32 * n)(*self._n_rays)

@@ -42,6 +42,7 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+template <int K>
 __global__ void k_batch(const FilterDev* __restrict__ filters, const int64_t* __restrict__ prefix,
                         int32_t n_filters, int64_t total_tiles, int32_t ppt,
                         unsigned long long* __restrict__ counter) {
@@ -55,18 +56,19 @@ __global__ void k_batch(const FilterDev* __restrict__ filters, const int64_t* __
     int32_t lo = 0, hi = n_filters;  // prefix[lo] <= t < prefix[hi]
     while (hi - lo > 1) {
       int32_t mid = (lo + hi) >> 1;
-      if ((uint64_t)prefix[mid] <= t)
+      if ((uint64_t)ldg(prefix + mid) <= t)
         lo = mid;
       else
         hi = mid;
     }
     const FilterDev f = filters[lo];
-    const int64_t p0 = (int64_t)(t - (uint64_t)prefix[lo]) * ppt;
+    const int64_t p0 = (int64_t)(t - (uint64_t)ldg(prefix + lo)) * ppt;
     const int64_t p1 = p0 + ppt < f.n_particles ? p0 + ppt : f.n_particles;
     for (int64_t p = p0; p < p1; ++p) {
-      float lw = wave_particle_logw(f.map, f.px[p], f.py[p], f.pth[p], f.offsets, f.obs, f.n_rays, f.pair_offset,
+      float lw = wave_particle_logw<K>(f.map, ldg(f.px + p), ldg(f.py + p), ldg(f.pth + p), f.offsets, f.obs,
+                                       f.n_rays, f.pair_offset,
                                     f.table, f.max_range, f.ranges ? f.ranges + p * f.n_rays : nullptr);
-      if (lane == 0) f.logw[p] = lw;
+      if (lane == 0) stg(f.logw + p, lw);
     }
   }
 }
@@ -81,8 +83,22 @@ cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, in
   if (total_tiles > 0) {
     const unsigned blocks = (unsigned)std::max(1, cus * t.blocks_per_cu);
     const unsigned threads = (unsigned)(kWave * t.waves_per_block);
-    hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(threads), 0, st, d_filters, d_prefix, n_filters, total_tiles,
-                       t.particles_per_tile, d_counter);
+    const int32_t ppt = t.particles_per_tile;
+    switch (t.group_searches) {
+#define CDDT_BATCH_K(KK)                                                                                        \
+  case KK:                                                                                                      \
+    hipLaunchKernelGGL(k_batch<KK>, dim3(blocks), dim3(threads), 0, st, d_filters, d_prefix, n_filters,         \
+                       total_tiles, ppt, d_counter);                                                            \
+    break;
+      CDDT_BATCH_K(1)
+      CDDT_BATCH_K(2)
+      CDDT_BATCH_K(3)
+      CDDT_BATCH_K(4)
+      CDDT_BATCH_K(5)
+#undef CDDT_BATCH_K
+      default:
+        return fail(CDDT_EINVAL, "tuning: group_searches must be in 1..5");
+    }
   }
   CDDT_HIP(hipGetLastError());
   return CDDT_OK;
@@ -94,6 +110,8 @@ cddt_status check_tuning(const cddt_tuning& t) {
   if (t.waves_per_block < 1 || t.waves_per_block > 16)
     return fail(CDDT_EINVAL, "tuning: waves_per_block must be in 1..16");
   if (t.blocks_per_cu < 1 || t.blocks_per_cu > 32) return fail(CDDT_EINVAL, "tuning: blocks_per_cu must be in 1..32");
+  const int k = t.group_searches;
+  if (k < 1 || k > 5) return fail(CDDT_EINVAL, "tuning: group_searches must be in 1..5");
   return CDDT_OK;
 }
 
@@ -102,6 +120,7 @@ cddt_tuning default_tuning() {
   t.particles_per_tile = 4;
   t.waves_per_block = 4;
   t.blocks_per_cu = 8;
+  t.group_searches = 5;
   return t;
 }
 

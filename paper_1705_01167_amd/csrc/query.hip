@@ -8,6 +8,8 @@ namespace {
 
 constexpr int kCastThreads = 256;
 constexpr int kWeightThreads = 256;  // 4 particles (waves) per block
+constexpr int kCastK = 4;            // concurrent searches per 8-lane group (see wave_search)
+constexpr int kWeightK = 5;
 
 // One wave takes 64 consecutive rays at a time (lane = ray); the loop bound is
 // the same for every lane of a wave so the cooperative search stays converged.
@@ -21,18 +23,19 @@ __global__ __launch_bounds__(kCastThreads) void k_cast(MapDev m, const float* __
   for (int64_t c = (int64_t)blockIdx.x * (kCastThreads / kWave) + (threadIdx.x >> 6); c < chunks; c += waves) {
     const int64_t i = c * kWave + lane;
     const bool active = i < n;
-    const float xi = active ? x[i] : 0.0f, yi = active ? y[i] : 0.0f, ti = active ? th[i] : 0.0f;
-    const int32_t r = wave_cast(m, active, xi, yi, ti, max_range);
-    if (active) out[i] = r;
+    const float xi = active ? ldg(x + i) : 0.0f, yi = active ? ldg(y + i) : 0.0f, ti = active ? ldg(th + i) : 0.0f;
+    const int32_t r = wave_cast<kCastK>(m, active, xi, yi, ti, max_range);
+    if (active) stg(out + i, r);
   }
 }
 
 __global__ __launch_bounds__(kWeightThreads) void k_weight(FilterDev f) {
   const int64_t p = (int64_t)blockIdx.x * (kWeightThreads / kWave) + (threadIdx.x >> 6);
   if (p >= f.n_particles) return;  // whole wave leaves together
-  float lw = wave_particle_logw(f.map, f.px[p], f.py[p], f.pth[p], f.offsets, f.obs, f.n_rays, f.pair_offset,
+  float lw = wave_particle_logw<kWeightK>(f.map, ldg(f.px + p), ldg(f.py + p), ldg(f.pth + p), f.offsets, f.obs,
+                                          f.n_rays, f.pair_offset,
                                 f.table, f.max_range, f.ranges ? f.ranges + p * f.n_rays : nullptr);
-  if ((threadIdx.x & 63) == 0) f.logw[p] = lw;
+  if ((threadIdx.x & 63) == 0) stg(f.logw + p, lw);
 }
 
 }  // namespace

@@ -26,6 +26,26 @@
 
 namespace cddt {
 
+// Loads and stores through the global address space.  Pointers read from a
+// descriptor table in memory are generic, and generic (flat) loads count
+// against the LDS wait counter too, which would serialise them with the
+// lane shuffles; global loads keep several lines in flight.
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+// 16-byte load as a native vector (int4's copy constructor would take a
+// generic reference and turn the load back into a flat one).
+typedef int32_t cddt_v4i __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int4 ldg4(const int4* p) {
+  const cddt_v4i v = *(const __attribute__((address_space(1))) cddt_v4i*)p;
+  return make_int4(v.x, v.y, v.z, v.w);
+}
+
 // Quantised query position: floor(v * 2^16); v * 2^16 is exact in float32.
 __device__ __forceinline__ int32_t quantize16(float v) {
   return (int32_t)floorf(__fmul_rn(v, 65536.0f));
@@ -40,7 +60,9 @@ __device__ __forceinline__ bool pose_inside(const MapDev& m, float x, float y) {
 __device__ __forceinline__ int32_t theta_bin(float theta, float k_scale, int32_t n) {
   float t = __fmul_rn(theta, k_scale);
   float u = __fadd_rn(t, 0.5f);
-  int32_t k = (int32_t)floorf(u) % n;
+  int32_t k = (int32_t)floorf(u);
+  if (k >= -n && k < 2 * n) return k < 0 ? k + n : (k >= n ? k - n : k);  // angles within one turn of [0, 2pi)
+  k %= n;
   return k < 0 ? k + n : k;
 }
 
@@ -49,7 +71,7 @@ __device__ __forceinline__ int32_t lower_bound_i32(const int32_t* __restrict__ a
   int32_t lo = 0, cnt = len;
   while (cnt > 0) {
     int32_t half = cnt >> 1;
-    int32_t v = a[lo + half];
+    int32_t v = ldg(a + lo + half);
     if (v < key) {
       lo += half + 1;
       cnt -= half + 1;
@@ -73,7 +95,8 @@ struct Landing {
 };
 
 __device__ __forceinline__ Landing land(const MapDev& m, int32_t slice, int32_t xf, int32_t yf) {
-  SliceDev sl = m.slices[slice];
+  const int4 sv = ldg4(reinterpret_cast<const int4*>(m.slices + slice));
+  const SliceDev sl{sv.x, sv.y, sv.z, sv.w};
   int64_t along = (int64_t)xf * sl.c + (int64_t)yf * sl.s;
   int64_t lat = (int64_t)yf * sl.c - (int64_t)xf * sl.s;
   Landing l;
@@ -82,24 +105,62 @@ __device__ __forceinline__ Landing land(const MapDev& m, int32_t slice, int32_t 
   return l;
 }
 
-// Sum / min / max over the 8 lanes of a search group (lanes 8g .. 8g+7).
+// Cross-lane moves inside a row of 16 lanes (DPP; VALU, no LDS traffic).
+// quad_perm patterns swap lanes 1 / 2 apart inside each group of 4; the
+// half-row mirror pairs lane i with 7 - i inside each group of 8; the row
+// mirror pairs lane i with 15 - i.
+constexpr int kDppQuadXor1 = 0xB1;    // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4E;    // quad_perm [2, 3, 0, 1]
+constexpr int kDppQuadBcast0 = 0x00;  // quad_perm [0, 0, 0, 0]
+constexpr int kDppRowMirror = 0x140;
+constexpr int kDppHalfMirror = 0x141;
+
+template <int Ctrl>
+__device__ __forceinline__ int32_t dpp(int32_t v) {
+  return __builtin_amdgcn_update_dpp(0, v, Ctrl, 0xF, 0xF, false);
+}
+template <int Ctrl>
+__device__ __forceinline__ float dppf(float v) {
+  return __builtin_bit_cast(float, dpp<Ctrl>(__builtin_bit_cast(int32_t, v)));
+}
+
+// Sum / min / max over the 8 lanes of a search group (lanes 8g .. 8g+7): two
+// quad exchanges, then the other quad of the group through the half mirror.
 __device__ __forceinline__ int32_t group_sum(int32_t v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 4);
-  return v;
+  v += dpp<kDppQuadXor1>(v);
+  v += dpp<kDppQuadXor2>(v);
+  return v + dpp<kDppHalfMirror>(v);
 }
 __device__ __forceinline__ int32_t group_min(int32_t v) {
-  v = min(v, __shfl_xor(v, 1));
-  v = min(v, __shfl_xor(v, 2));
-  v = min(v, __shfl_xor(v, 4));
-  return v;
+  v = min(v, dpp<kDppQuadXor1>(v));
+  v = min(v, dpp<kDppQuadXor2>(v));
+  return min(v, dpp<kDppHalfMirror>(v));
 }
 __device__ __forceinline__ int32_t group_max(int32_t v) {
-  v = max(v, __shfl_xor(v, 1));
-  v = max(v, __shfl_xor(v, 2));
-  v = max(v, __shfl_xor(v, 4));
-  return v;
+  v = max(v, dpp<kDppQuadXor1>(v));
+  v = max(v, dpp<kDppQuadXor2>(v));
+  return max(v, dpp<kDppHalfMirror>(v));
+}
+// Value of the group's first lane in all 8 lanes.
+__device__ __forceinline__ int32_t group_bcast0(int32_t v, int sub) {
+  const int32_t q = dpp<kDppQuadBcast0>(v);  // first lane of each quad
+  const int32_t o = dpp<kDppHalfMirror>(q);  // the other quad's first lane
+  return sub < 4 ? q : o;
+}
+
+// Float sum over the whole wave in a fixed order: each row of 16 lanes is
+// reduced with DPP (all lanes of a row end with the same bits), then the
+// four row totals are added as (row0 + row1) + (row2 + row3).
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dppf<kDppQuadXor1>(v);
+  v += dppf<kDppQuadXor2>(v);
+  v += dppf<kDppHalfMirror>(v);
+  v += dppf<kDppRowMirror>(v);
+  const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, v), 0));
+  const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, v), 16));
+  const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, v), 32));
+  const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, v), 48));
+  return (r0 + r1) + (r2 + r3);
 }
 
 // Scan this lane's four entries (indices 4*sub .. 4*sub+3 of a 32-entry line,
@@ -129,6 +190,12 @@ __device__ __forceinline__ void scan4(int4 v, int sub, int skip, int32_t valid, 
 // r_succ, the range to the smallest zero point > xq, and r_pred, the range to
 // the largest zero point < xq (max_range when there is none).  Must be called
 // by all 64 lanes together.
+//
+// The eight 8-lane groups each run K searches side by side: the K header
+// lines are requested before any is used, then the searches descend their
+// levels in lock-step, one line request per search per level.  K raises the
+// number of independent lines a wave keeps in flight from 8 to 8K.
+template <int K>
 __device__ __forceinline__ void wave_search(const MapDev& m, bool want, int32_t row, int32_t xq, int32_t max_range,
                                             int32_t& r_succ, int32_t& r_pred) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -141,69 +208,93 @@ __device__ __forceinline__ void wave_search(const MapDev& m, bool want, int32_t 
   const int g = lane >> 3, sub = lane & 7;
   r_succ = max_range;
   r_pred = max_range;
-  for (int base = 0; base < n; base += 8) {
-    const int k = base + g;
-    const bool act = k < n;
-    const int src = __shfl(list, act ? k : 0);
-    const int32_t qrow = __shfl(row, src);
-    const int32_t x = __shfl(xq, src);
-    int32_t gs = max_range, gp = max_range;
-    if (act) {
-      const int4* hn = reinterpret_cast<const int4*>(m.hdr + (int64_t)qrow * kNodeInts);
-      const int4 h = hn[sub];
-      const uint32_t start = (uint32_t)__shfl(h.x, lane & ~7);
-      const int32_t len = __shfl(h.y, lane & ~7);
-      const int32_t cap0 = __shfl(h.z, lane & ~7);
-      // top level T: the smallest level with at most kTopEntries entries
-      int32_t T = 0, nT = len;
+  for (int base = 0; base < n; base += 8 * K) {
+    int32_t x[K], len[K], cap[K], c[K], nxt[K], prv[K], lvl[K];
+    uint32_t start[K];
+    int4 v[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {  // request all K header lines first
+      const int k = base + 8 * j + g;
+      const bool act = k < n;
+      const int src = __shfl(list, act ? k : 0);
+      const int32_t qrow = __shfl(row, src);
+      x[j] = __shfl(xq, src);
+      v[j] = act ? ldg4(reinterpret_cast<const int4*>(m.hdr + (int64_t)qrow * kNodeInts) + sub) : make_int4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {  // top level, held in the header node
+      start[j] = (uint32_t)group_bcast0(v[j].x, sub);
+      len[j] = group_bcast0(v[j].y, sub);
+      cap[j] = group_bcast0(v[j].z, sub);
+      int32_t T = 0, nT = len[j];
       while (nT > kTopEntries) {
         nT = (nT + kLineInts - 1) >> kLineShift;
         ++T;
       }
-      int32_t c, nxt, prv;
-      {
-        int32_t lc, ln, lp;
-        scan4(h, sub, kHeaderWords, nT, x, lc, ln, lp);
-        c = group_sum(lc);
-        nxt = group_min(ln);
-        prv = group_max(lp);
-      }
-      for (int32_t t = T - 1; t >= 0 && c > 0; --t) {
-        const int32_t blk = c - 1;
-        const int32_t nt = level_count(len, t);
-        const int32_t valid = min(kLineInts, nt - blk * kLineInts);
-        const int4* line = reinterpret_cast<const int4*>(m.zeros + level_base(start, cap0, t) + (uint32_t)blk * kLineInts);
-        const int4 v = line[sub];
-        int32_t lc, ln, lp;
-        scan4(v, sub, 0, valid, x, lc, ln, lp);
-        c = blk * kLineInts + group_sum(lc);
-        const int32_t gn = group_min(ln);
-        nxt = gn != INT_MAX ? gn : nxt;  // none in this block: the next block's first entry
-        prv = group_max(lp);
-      }
-      // c = number of keys <= x; nxt = smallest key > x; prv = largest key <= x
-      if (c < len) gs = range_of((int64_t)nxt - x, max_range);
-      if (c > 0) {
-        int32_t pv = prv;
-        if (pv == x) {  // rare: x equals a key; find the last key strictly below it
-          const int32_t lb = lower_bound_i32(m.zeros + start, c, x);
-          pv = lb > 0 ? m.zeros[start + lb - 1] : INT_MIN;
+      int32_t lc, ln, lp;
+      scan4(v[j], sub, kHeaderWords, nT, x[j], lc, ln, lp);
+      c[j] = group_sum(lc);
+      nxt[j] = group_min(ln);
+      prv[j] = group_max(lp);
+      lvl[j] = c[j] > 0 ? T - 1 : -1;
+    }
+    for (;;) {  // one level of every unfinished search per round
+      bool more = false;
+#pragma unroll
+      for (int j = 0; j < K; ++j) more |= lvl[j] >= 0;
+      if (!more) break;
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        if (lvl[j] >= 0) {
+          const uint32_t off = level_base(start[j], (uint32_t)cap[j], lvl[j]) + (uint32_t)(c[j] - 1) * kLineInts;
+          v[j] = ldg4(reinterpret_cast<const int4*>(m.zeros + off) + sub);
         }
-        if (pv != INT_MIN) gp = range_of((int64_t)x - pv, max_range);
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        if (lvl[j] >= 0) {
+          const int32_t blk = c[j] - 1;
+          const int32_t valid = min(kLineInts, level_count(len[j], lvl[j]) - blk * kLineInts);
+          int32_t lc, ln, lp;
+          scan4(v[j], sub, 0, valid, x[j], lc, ln, lp);
+          c[j] = blk * kLineInts + group_sum(lc);
+          const int32_t gn = group_min(ln);
+          nxt[j] = gn != INT_MAX ? gn : nxt[j];  // none in this block: the next block's first entry
+          prv[j] = group_max(lp);
+          --lvl[j];
+        }
+    }
+    // c = number of keys <= x; nxt = smallest key > x; prv = largest key <= x
+    int32_t gs[K], gp[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      gs[j] = c[j] < len[j] ? range_of((int64_t)nxt[j] - x[j], max_range) : max_range;
+      gp[j] = max_range;
+      if (c[j] > 0) {
+        int32_t pv = prv[j];
+        if (pv == x[j]) {  // rare: x equals a key; find the last key strictly below it
+          const int32_t lb = lower_bound_i32(m.zeros + start[j], c[j], x[j]);
+          pv = lb > 0 ? ldg(m.zeros + start[j] + lb - 1) : INT_MIN;
+        }
+        if (pv != INT_MIN) gp[j] = range_of((int64_t)x[j] - pv, max_range);
       }
     }
-    // hand results back: lanes whose rank falls in this pass pull from their group leader
-    const int leader = (rank & 7) << 3;
-    const int32_t ps = __shfl(gs, leader);
-    const int32_t pp = __shfl(gp, leader);
-    if (want && (rank >> 3) == (base >> 3)) {
-      r_succ = ps;
-      r_pred = pp;
+    // hand results back: search k = base + 8j + g sits in slot j of group g;
+    // both ranges (<= 65535) travel packed in one word
+    const int rel = rank - base;
+    const int leader = (rel & 7) << 3;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int32_t pk = __shfl(gs[j] | (gp[j] << 16), leader);
+      if (want && rel >= 0 && (rel >> 3) == j) {
+        r_succ = pk & 0xffff;
+        r_pred = (int32_t)((uint32_t)pk >> 16);
+      }
     }
   }
 }
 
 // Plain casts for up to 64 rays, one per lane (Sec. IV-B).  All lanes call.
+template <int K>
 __device__ __forceinline__ int32_t wave_cast(const MapDev& m, bool active, float x, float y, float theta,
                                              int32_t max_range) {
   bool valid = active && (fabsf(theta) < 1e6f) && pose_inside(m, x, y);
@@ -211,7 +302,7 @@ __device__ __forceinline__ int32_t wave_cast(const MapDev& m, bool active, float
   if (valid) {
     xf = quantize16(x);
     yf = quantize16(y);
-    valid = m.occ[(size_t)(yf >> 16) * (size_t)m.w + (size_t)(xf >> 16)] == 0;
+    valid = ldg(m.occ + (size_t)(yf >> 16) * (size_t)m.w + (size_t)(xf >> 16)) == 0;
   }
   bool fwd = true;
   Landing l{0, 0};
@@ -221,18 +312,19 @@ __device__ __forceinline__ int32_t wave_cast(const MapDev& m, bool active, float
     l = land(m, fwd ? k : k - m.half, xf, yf);
   }
   int32_t rs, rp;
-  wave_search(m, valid, l.row, l.xq, max_range, rs, rp);
+  wave_search<K>(m, valid, l.row, l.xq, max_range, rs, rp);
   return valid ? (fwd ? rs : rp) : 0;
 }
 
 // Log-weight of one particle, computed by all 64 lanes of a wave (lane = ray
 // within a chunk of 64 rays).  Every lane returns the same value.  The sum is
-// float32: each lane accumulates its rays in chunk order, then a fixed xor
-// butterfly adds the lanes, so the bits depend only on n_rays.
+// float32: each lane accumulates its rays in chunk order, then wave_sum adds
+// the lanes in a fixed order, so the bits depend only on n_rays.
 //
 // Radial pairing (Sec. IV-C): if pair_off > 0, lane l + pair_off reuses the
 // search of lane l when both rays land in the same slice (their bins differ by
 // n/2): every search returns both the successor and the predecessor.
+template <int K>
 __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, float py, float pth,
                                                     const float* __restrict__ offsets,
                                                     const int32_t* __restrict__ obs, int32_t n_rays,
@@ -245,13 +337,13 @@ __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, f
   if (xy_ok) {
     xf = quantize16(px);
     yf = quantize16(py);
-    xy_ok = m.occ[(size_t)(yf >> 16) * (size_t)m.w + (size_t)(xf >> 16)] == 0;
+    xy_ok = ldg(m.occ + (size_t)(yf >> 16) * (size_t)m.w + (size_t)(xf >> 16)) == 0;
   }
   float acc = 0.0f;
   for (int32_t base = 0; base < n_rays; base += kWave) {
     const int32_t r = base + lane;
     const bool active = r < n_rays;
-    float th = active ? __fadd_rn(pth, offsets[r]) : 0.0f;
+    float th = active ? __fadd_rn(pth, ldg(offsets + r)) : 0.0f;
     bool valid = active && xy_ok && (fabsf(th) < 1e6f);
     int32_t slice = 0;
     bool fwd = true;
@@ -266,9 +358,8 @@ __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, f
     if (pair_off > 0) {
       const int src = lane - pair_off;
       src_c = src >= 0 ? src : lane;
-      const int32_t ps = __shfl(slice, src_c);
-      const int pv = __shfl(valid ? 1 : 0, src_c);
-      const bool cand = src >= 0 && valid && pv && ps == slice;
+      const int32_t ps = __shfl(valid ? slice : -1, src_c);  // partner's slice, -1 if it casts nothing
+      const bool cand = src >= 0 && valid && ps == slice;
       // a partner that itself reuses a search does not search: no chains
       const int pc = __shfl(cand ? 1 : 0, src_c);
       paired = cand && !pc;
@@ -276,21 +367,18 @@ __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, f
     Landing l{0, 0};
     if (valid && !paired) l = land(m, slice, xf, yf);
     int32_t rs, rp;
-    wave_search(m, valid && !paired, l.row, l.xq, max_range, rs, rp);
-    const int32_t os = __shfl(rs, src_c);
-    const int32_t op = __shfl(rp, src_c);
+    wave_search<K>(m, valid && !paired, l.row, l.xq, max_range, rs, rp);
+    const int32_t opk = __shfl(rs | (rp << 16), src_c);  // partner's (successor, predecessor) ranges
     int32_t range = 0;
-    if (valid) range = paired ? (fwd ? os : op) : (fwd ? rs : rp);
+    if (valid) range = paired ? (fwd ? (opk & 0xffff) : (int32_t)((uint32_t)opk >> 16)) : (fwd ? rs : rp);
     if (active) {
-      int32_t zo = obs[r];
+      int32_t zo = ldg(obs + r);
       zo = zo < 0 ? 0 : (zo > max_range ? max_range : zo);
-      acc += table[(int64_t)zo * m1 + range];
-      if (ranges_row) ranges_row[r] = range;
+      acc += ldg(table + (int64_t)zo * m1 + range);
+      if (ranges_row) stg(ranges_row + r, range);
     }
   }
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  return acc;
+  return wave_sum(acc);
 }
 
 }  // namespace cddt

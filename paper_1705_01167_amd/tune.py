@@ -1,8 +1,8 @@
 """Autotuner for the persistent batched kernel.
 
 Times every tuning in a small grid (particles per tile x waves per block x
-blocks per CU) on the plan itself with HIP events (cddt_plan_time) and keeps
-the fastest.  Results are cached in a JSON file keyed by device and a plan
+blocks per CU x concurrent searches per 8-lane group) on the plan itself with
+HIP events (cddt_plan_time) and keeps the fastest.  Results are cached in a JSON file keyed by device and a plan
 signature (filter count, particle total bucket, theta-bin set), so a later run
 with the same shape skips the sweep.
 """
@@ -15,9 +15,10 @@ import os
 
 from . import cddt
 
-SPACE_PPT = (1, 2, 4, 8, 16, 32)
+SPACE_PPT = (1, 2, 4, 8, 16)
 SPACE_WAVES = (1, 2, 4, 8)
 SPACE_BLOCKS = (2, 4, 8, 16)
+SPACE_K = (1, 2, 3, 4, 5)
 
 
 def cache_path() -> str:
@@ -27,7 +28,7 @@ def cache_path() -> str:
 
 def signature(n_filters: int, total_particles: int, theta_bins, device_name: str) -> str:
     bucket = int(round(math.log2(max(1, total_particles))))
-    return f"{device_name}|f{n_filters}|p2^{bucket}|n{'-'.join(map(str, sorted(set(theta_bins))))}"
+    return f"v2|{device_name}|f{n_filters}|p2^{bucket}|n{'-'.join(map(str, sorted(set(theta_bins))))}"
 
 
 def _load() -> dict:
@@ -58,7 +59,7 @@ def autotune(plan: "cddt.Plan", sig: str, reps: int = 3, use_cache: bool = True,
         plan.tuning = t
         return t, cache[sig]["ms"], []
     results = []
-    for t in itertools.product(SPACE_PPT, SPACE_WAVES, SPACE_BLOCKS):
+    for t in itertools.product(SPACE_PPT, SPACE_WAVES, SPACE_BLOCKS, SPACE_K):
         ms = plan.time(t, reps=reps, stream=stream)
         results.append((ms, t))
     results.sort()
