@@ -204,7 +204,8 @@ typedef struct {
   int32_t particles_per_tile; /* particles a wave takes per queue pop (1..256) */
   int32_t waves_per_block;    /* 1..16 */
   int32_t blocks_per_cu;      /* persistent blocks per compute unit (1..32) */
-  int32_t group_searches;     /* band searches each 8-lane group runs side by side (1..5) */
+  int32_t group_searches;     /* 0: one lane per band search; 1..5: eight lanes per search, this
+                                 many searches per 8-lane group in flight */
 } cddt_tuning;
 
 typedef struct cddt_plan_s* cddt_plan;

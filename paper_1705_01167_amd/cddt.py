@@ -390,7 +390,7 @@ class Server:
     """Continuous-batching server over resident maps (cddt_server_*)."""
 
     def __init__(self, maps, offsets, tables, max_ranges, budget_bytes: int = 1 << 30, n_lanes: int = 4,
-                 max_batch: int = 256, tuning=(4, 4, 8, 5)):
+                 max_batch: int = 256, tuning=(4, 4, 8, 0)):
         n = len(maps)
         self._offsets = [np.ascontiguousarray(np.asarray(o, np.float32)) for o in offsets]
         self._tables = list(tables)              # keep device tables alive

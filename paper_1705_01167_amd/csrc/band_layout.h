@@ -13,7 +13,10 @@
 // Level t holds ceil(len / 32^t) entries, entry j being key j * 32^t.  The top
 // level T is the first one with at most kTopEntries entries; it lives in the
 // header node (T = 0 puts the keys themselves there), so a search reads the
-// header line and then one line at each level T-1, ..., 0.
+// header line and then one line at each level T-1, ..., 0.  Unused slots of the
+// last line of every level and of the header are INT_MAX, which no zero point
+// reaches (|Z| < 2^31 - 2^28 for maps up to 16384 cells a side), so a search can
+// scan whole lines without bounds checks.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -87,10 +90,12 @@ __device__ inline void finalize_band(int32_t* __restrict__ hdr_node, int32_t* __
   const uint32_t cap = (uint32_t)hdr_node[2];
   const int T = top_level(len);
   const int32_t* keys = zeros + start;
+  for (int32_t k = len + lane; k < (int32_t)round_line((uint64_t)len); k += 64) zeros[start + k] = INT_MAX;
   for (int t = 1; t < T; ++t) {
     const int32_t nt = level_count(len, t);
     int32_t* lv = zeros + level_base(start, cap, t);
-    for (int32_t k = lane; k < nt; k += 64) lv[k] = keys[(int64_t)k << (kLineShift * t)];
+    for (int32_t k = lane; k < (int32_t)round_line((uint64_t)nt); k += 64)
+      lv[k] = k < nt ? keys[(int64_t)k << (kLineShift * t)] : INT_MAX;
   }
   const int32_t nT = level_count(len, T);
   if (lane >= kHeaderWords && lane < kNodeInts) {

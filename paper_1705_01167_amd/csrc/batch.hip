@@ -95,9 +95,10 @@ cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, in
       CDDT_BATCH_K(3)
       CDDT_BATCH_K(4)
       CDDT_BATCH_K(5)
+      CDDT_BATCH_K(0)
 #undef CDDT_BATCH_K
       default:
-        return fail(CDDT_EINVAL, "tuning: group_searches must be in 1..5");
+        return fail(CDDT_EINVAL, "tuning: group_searches must be in 0..5");
     }
   }
   CDDT_HIP(hipGetLastError());
@@ -111,7 +112,7 @@ cddt_status check_tuning(const cddt_tuning& t) {
     return fail(CDDT_EINVAL, "tuning: waves_per_block must be in 1..16");
   if (t.blocks_per_cu < 1 || t.blocks_per_cu > 32) return fail(CDDT_EINVAL, "tuning: blocks_per_cu must be in 1..32");
   const int k = t.group_searches;
-  if (k < 1 || k > 5) return fail(CDDT_EINVAL, "tuning: group_searches must be in 1..5");
+  if (k < 0 || k > 5) return fail(CDDT_EINVAL, "tuning: group_searches must be in 0..5");
   return CDDT_OK;
 }
 
@@ -120,7 +121,7 @@ cddt_tuning default_tuning() {
   t.particles_per_tile = 4;
   t.waves_per_block = 4;
   t.blocks_per_cu = 8;
-  t.group_searches = 5;
+  t.group_searches = 0;
   return t;
 }
 

@@ -8,8 +8,8 @@ namespace {
 
 constexpr int kCastThreads = 256;
 constexpr int kWeightThreads = 256;  // 4 particles (waves) per block
-constexpr int kCastK = 4;            // concurrent searches per 8-lane group (see wave_search)
-constexpr int kWeightK = 5;
+constexpr int kCastK = 0;            // search strategy (band_search): one lane per search
+constexpr int kWeightK = 0;
 
 // One wave takes 64 consecutive rays at a time (lane = ray); the loop bound is
 // the same for every lane of a wave so the cooperative search stays converged.

@@ -293,6 +293,85 @@ __device__ __forceinline__ void wave_search(const MapDev& m, bool want, int32_t 
   }
 }
 
+// One 128-byte line of 32 entries, loaded by a single lane (8 x 16 bytes).
+struct Line32 {
+  int32_t e[32];
+};
+
+__device__ __forceinline__ Line32 load_line(const int32_t* p) {
+  Line32 L;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int4 q = ldg4(reinterpret_cast<const int4*>(p) + i);
+    L.e[4 * i] = q.x;
+    L.e[4 * i + 1] = q.y;
+    L.e[4 * i + 2] = q.z;
+    L.e[4 * i + 3] = q.w;
+  }
+  return L;
+}
+
+// Entries First..31 of a sorted line (unused slots hold INT_MAX): c = number
+// of entries <= x, prv = the largest of them (INT_MIN if none), nxt = the
+// smallest entry > x, or `carried` when every entry is <= x.
+template <int First>
+__device__ __forceinline__ void scan_line(const Line32& L, int32_t x, int32_t carried, int32_t& c, int32_t& nxt,
+                                          int32_t& prv) {
+  c = 0;
+  prv = INT_MIN;
+  nxt = L.e[First];
+#pragma unroll
+  for (int i = First; i < 32; ++i) {
+    const bool le = L.e[i] <= x;
+    c = le ? i + 1 - First : c;
+    prv = le ? L.e[i] : prv;
+    nxt = le ? (i + 1 < 32 ? L.e[i + 1] : carried) : nxt;
+  }
+}
+
+// Band search by one lane: the header line, then one line per level below the
+// top.  Same results as wave_search; no cross-lane traffic, and a wave keeps up
+// to 64 independent lines in flight.  Lanes without a query return max_range.
+__device__ __forceinline__ void lane_search(const MapDev& m, bool want, int32_t row, int32_t x, int32_t max_range,
+                                            int32_t& r_succ, int32_t& r_pred) {
+  r_succ = max_range;
+  r_pred = max_range;
+  if (!want) return;
+  Line32 L = load_line(m.hdr + (int64_t)row * kNodeInts);
+  const uint32_t start = (uint32_t)L.e[0];
+  const int32_t len = L.e[1];
+  const uint32_t cap = (uint32_t)L.e[2];
+  int32_t c, nxt, prv;
+  scan_line<kHeaderWords>(L, x, INT_MAX, c, nxt, prv);
+  for (int t = top_level(len) - 1; t >= 0 && c > 0; --t) {
+    const int32_t blk = c - 1;
+    L = load_line(m.zeros + level_base(start, cap, t) + (uint32_t)blk * kLineInts);
+    int32_t lc;
+    scan_line<0>(L, x, nxt, lc, nxt, prv);
+    c = blk * kLineInts + lc;
+  }
+  if (c < len) r_succ = range_of((int64_t)nxt - x, max_range);
+  if (c > 0) {
+    int32_t pv = prv;
+    if (pv == x) {  // rare: x equals a key; find the last key strictly below it
+      const int32_t lb = lower_bound_i32(m.zeros + start, c, x);
+      pv = lb > 0 ? ldg(m.zeros + start + lb - 1) : INT_MIN;
+    }
+    if (pv != INT_MIN) r_pred = range_of((int64_t)x - pv, max_range);
+  }
+}
+
+// Search strategy: K = 0 one lane per search, K >= 1 eight lanes per search
+// with K searches per group in flight.
+template <int K>
+__device__ __forceinline__ void band_search(const MapDev& m, bool want, int32_t row, int32_t xq, int32_t max_range,
+                                            int32_t& r_succ, int32_t& r_pred) {
+  if constexpr (K == 0)
+    lane_search(m, want, row, xq, max_range, r_succ, r_pred);
+  else
+    wave_search<K>(m, want, row, xq, max_range, r_succ, r_pred);
+}
+
 // Plain casts for up to 64 rays, one per lane (Sec. IV-B).  All lanes call.
 template <int K>
 __device__ __forceinline__ int32_t wave_cast(const MapDev& m, bool active, float x, float y, float theta,
@@ -312,7 +391,7 @@ __device__ __forceinline__ int32_t wave_cast(const MapDev& m, bool active, float
     l = land(m, fwd ? k : k - m.half, xf, yf);
   }
   int32_t rs, rp;
-  wave_search<K>(m, valid, l.row, l.xq, max_range, rs, rp);
+  band_search<K>(m, valid, l.row, l.xq, max_range, rs, rp);
   return valid ? (fwd ? rs : rp) : 0;
 }
 
@@ -367,7 +446,7 @@ __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, f
     Landing l{0, 0};
     if (valid && !paired) l = land(m, slice, xf, yf);
     int32_t rs, rp;
-    wave_search<K>(m, valid && !paired, l.row, l.xq, max_range, rs, rp);
+    band_search<K>(m, valid && !paired, l.row, l.xq, max_range, rs, rp);
     const int32_t opk = __shfl(rs | (rp << 16), src_c);  // partner's (successor, predecessor) ranges
     int32_t range = 0;
     if (valid) range = paired ? (fwd ? (opk & 0xffff) : (int32_t)((uint32_t)opk >> 16)) : (fwd ? rs : rp);

@@ -1,7 +1,8 @@
 """Autotuner for the persistent batched kernel.
 
 Times every tuning in a small grid (particles per tile x waves per block x
-blocks per CU x concurrent searches per 8-lane group) on the plan itself with
+blocks per CU x search strategy: one lane per search, or 8 lanes per search
+with 1..3 searches per group in flight) on the plan itself with
 HIP events (cddt_plan_time) and keeps the fastest.  Results are cached in a JSON file keyed by device and a plan
 signature (filter count, particle total bucket, theta-bin set), so a later run
 with the same shape skips the sweep.
@@ -18,7 +19,7 @@ from . import cddt
 SPACE_PPT = (1, 2, 4, 8, 16)
 SPACE_WAVES = (1, 2, 4, 8)
 SPACE_BLOCKS = (2, 4, 8, 16)
-SPACE_K = (1, 2, 3, 4, 5)
+SPACE_K = (0, 1, 2, 3)
 
 
 def cache_path() -> str:
@@ -28,7 +29,7 @@ def cache_path() -> str:
 
 def signature(n_filters: int, total_particles: int, theta_bins, device_name: str) -> str:
     bucket = int(round(math.log2(max(1, total_particles))))
-    return f"v2|{device_name}|f{n_filters}|p2^{bucket}|n{'-'.join(map(str, sorted(set(theta_bins))))}"
+    return f"v3|{device_name}|f{n_filters}|p2^{bucket}|n{'-'.join(map(str, sorted(set(theta_bins))))}"
 
 
 def _load() -> dict:

@@ -270,7 +270,7 @@ def test_batched_plan_equals_plain():
         plain.append((ref_lw, ref_r))
         keep.append((gm, t, lw, rr))
     plan = cddt.Plan(filters, keepalive=keep)
-    for tuning in [(1, 1, 1, 1), (4, 4, 8, 2), (16, 2, 4, 3), (3, 8, 2, 4), (8, 4, 4, 5)]:
+    for tuning in [(1, 1, 1, 1), (4, 4, 8, 2), (16, 2, 4, 3), (3, 8, 2, 4), (8, 4, 4, 5), (8, 8, 4, 0), (1, 2, 3, 0)]:
         for (_, _, lw, rr) in keep:
             lw.fill_(float("nan"))
             rr.fill_(-1)
