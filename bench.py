@@ -235,7 +235,7 @@ def run_batched(args) -> dict:
             "bands": int(sum(s["rows"] for s in stats)),
             "structure_bytes": int(sum(s["device_bytes"] for s in stats)),
             "tuning": {"particles_per_tile": best[0], "waves_per_block": best[1], "blocks_per_cu": best[2],
-                       "group_searches": best[3]},
+                       "search_mode": best[3]},
             "parallelism": "single GPU",
         },
         "batched_rays_per_s_kernel": rays_per_step / (batched_ms * 1e-3),

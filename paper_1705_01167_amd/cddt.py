@@ -46,10 +46,10 @@ class Filter(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("particles_per_tile", C.c_int32), ("waves_per_block", C.c_int32),
-                ("blocks_per_cu", C.c_int32), ("group_searches", C.c_int32)]
+                ("blocks_per_cu", C.c_int32), ("search_mode", C.c_int32)]
 
     def as_tuple(self):
-        return (self.particles_per_tile, self.waves_per_block, self.blocks_per_cu, self.group_searches)
+        return (self.particles_per_tile, self.waves_per_block, self.blocks_per_cu, self.search_mode)
 
 
 class ServerConfig(C.Structure):
@@ -390,7 +390,7 @@ class Server:
     """Continuous-batching server over resident maps (cddt_server_*)."""
 
     def __init__(self, maps, offsets, tables, max_ranges, budget_bytes: int = 1 << 30, n_lanes: int = 4,
-                 max_batch: int = 256, tuning=(4, 4, 8, 0)):
+                 max_batch: int = 256, tuning=(8, 4, 2, 7)):
         n = len(maps)
         self._offsets = [np.ascontiguousarray(np.asarray(o, np.float32)) for o in offsets]
         self._tables = list(tables)              # keep device tables alive

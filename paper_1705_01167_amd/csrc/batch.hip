@@ -42,11 +42,26 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-template <int K>
+// Search modes (the tuning's search_mode): 0 one lane per search, one particle
+// per wave at a time; 1..5 eight lanes per search with that many searches per
+// group in flight; 6 / 7 / 8 one lane per search with the searches of 4 / 8 /
+// 16 particles queued in LDS and drained together (ray layouts of <= 64 rays;
+// longer layouts fall back to mode 0).
+constexpr int kModeTile4 = 6, kModeTile8 = 7, kModeTile16 = 8;
+__host__ __device__ constexpr int tile_q(int mode) {
+  return mode == kModeTile4 ? 4 : (mode == kModeTile8 ? 8 : (mode == kModeTile16 ? 16 : 0));
+}
+
+template <int Mode>
 __global__ void k_batch(const FilterDev* __restrict__ filters, const int64_t* __restrict__ prefix,
                         int32_t n_filters, int64_t total_tiles, int32_t ppt,
                         unsigned long long* __restrict__ counter) {
+  extern __shared__ int2 smem_jobs[];
+  constexpr int Q = tile_q(Mode);
   const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int2* jobs = smem_jobs + wave * Q * kWave;
+  int32_t* res = reinterpret_cast<int32_t*>(smem_jobs + nw * Q * kWave) + wave * Q * kWave;
   for (;;) {
     uint64_t t = 0;
     if (lane == 0) t = atomicAdd(counter, 1ull);
@@ -64,10 +79,17 @@ __global__ void k_batch(const FilterDev* __restrict__ filters, const int64_t* __
     const FilterDev f = filters[lo];
     const int64_t p0 = (int64_t)(t - (uint64_t)ldg(prefix + lo)) * ppt;
     const int64_t p1 = p0 + ppt < f.n_particles ? p0 + ppt : f.n_particles;
+    if constexpr (Q > 0) {
+      if (f.n_rays <= kWave) {
+        for (int64_t p = p0; p < p1; p += Q) wave_tile_logw<Q>(f, p, (int32_t)min((int64_t)Q, p1 - p), jobs, res);
+        continue;
+      }
+    }
+    constexpr int K = Q > 0 ? 0 : Mode;
     for (int64_t p = p0; p < p1; ++p) {
       float lw = wave_particle_logw<K>(f.map, ldg(f.px + p), ldg(f.py + p), ldg(f.pth + p), f.offsets, f.obs,
-                                       f.n_rays, f.pair_offset,
-                                    f.table, f.max_range, f.ranges ? f.ranges + p * f.n_rays : nullptr);
+                                       f.n_rays, f.pair_offset, f.table, f.max_range,
+                                       f.ranges ? f.ranges + p * f.n_rays : nullptr);
       if (lane == 0) stg(f.logw + p, lw);
     }
   }
@@ -84,10 +106,11 @@ cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, in
     const unsigned blocks = (unsigned)std::max(1, cus * t.blocks_per_cu);
     const unsigned threads = (unsigned)(kWave * t.waves_per_block);
     const int32_t ppt = t.particles_per_tile;
-    switch (t.group_searches) {
+    const size_t lds = (size_t)t.waves_per_block * tile_q(t.search_mode) * kWave * (sizeof(int2) + sizeof(int32_t));
+    switch (t.search_mode) {
 #define CDDT_BATCH_K(KK)                                                                                        \
   case KK:                                                                                                      \
-    hipLaunchKernelGGL(k_batch<KK>, dim3(blocks), dim3(threads), 0, st, d_filters, d_prefix, n_filters,         \
+    hipLaunchKernelGGL(k_batch<KK>, dim3(blocks), dim3(threads), lds, st, d_filters, d_prefix, n_filters,       \
                        total_tiles, ppt, d_counter);                                                            \
     break;
       CDDT_BATCH_K(1)
@@ -96,9 +119,12 @@ cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, in
       CDDT_BATCH_K(4)
       CDDT_BATCH_K(5)
       CDDT_BATCH_K(0)
+      CDDT_BATCH_K(6)
+      CDDT_BATCH_K(7)
+      CDDT_BATCH_K(8)
 #undef CDDT_BATCH_K
       default:
-        return fail(CDDT_EINVAL, "tuning: group_searches must be in 0..5");
+        return fail(CDDT_EINVAL, "tuning: search_mode must be in 0..8");
     }
   }
   CDDT_HIP(hipGetLastError());
@@ -111,8 +137,9 @@ cddt_status check_tuning(const cddt_tuning& t) {
   if (t.waves_per_block < 1 || t.waves_per_block > 16)
     return fail(CDDT_EINVAL, "tuning: waves_per_block must be in 1..16");
   if (t.blocks_per_cu < 1 || t.blocks_per_cu > 32) return fail(CDDT_EINVAL, "tuning: blocks_per_cu must be in 1..32");
-  const int k = t.group_searches;
-  if (k < 0 || k > 5) return fail(CDDT_EINVAL, "tuning: group_searches must be in 0..5");
+  if (t.search_mode < 0 || t.search_mode > 8) return fail(CDDT_EINVAL, "tuning: search_mode must be in 0..8");
+  if ((size_t)t.waves_per_block * tile_q(t.search_mode) * kWave * (sizeof(int2) + sizeof(int32_t)) > 65536)
+    return fail(CDDT_EINVAL, "tuning: the search queue of this mode and block size exceeds 64 KiB of LDS");
   return CDDT_OK;
 }
 
@@ -121,7 +148,7 @@ cddt_tuning default_tuning() {
   t.particles_per_tile = 4;
   t.waves_per_block = 4;
   t.blocks_per_cu = 8;
-  t.group_searches = 0;
+  t.search_mode = kModeTile8;
   return t;
 }
 

@@ -29,6 +29,19 @@ __global__ __launch_bounds__(kCastThreads) void k_cast(MapDev m, const float* __
   }
 }
 
+// Q particles per wave through the phased tile routine (ray layouts of <= 64 rays).
+constexpr int kWeightQ = 4;
+constexpr int64_t kTileMinParticles = 1 << 17;
+__global__ __launch_bounds__(kWeightThreads) void k_weight_tiles(FilterDev f) {
+  __shared__ int2 jobs[kWeightThreads / kWave][kWeightQ * kWave];
+  __shared__ int32_t res[kWeightThreads / kWave][kWeightQ * kWave];
+  const int wave = threadIdx.x >> 6;
+  const int64_t p0 = ((int64_t)blockIdx.x * (kWeightThreads / kWave) + wave) * kWeightQ;
+  if (p0 >= f.n_particles) return;  // whole wave leaves together
+  const int32_t cnt = (int32_t)min((int64_t)kWeightQ, f.n_particles - p0);
+  wave_tile_logw<kWeightQ>(f, p0, cnt, jobs[wave], res[wave]);
+}
+
 __global__ __launch_bounds__(kWeightThreads) void k_weight(FilterDev f) {
   const int64_t p = (int64_t)blockIdx.x * (kWeightThreads / kWave) + (threadIdx.x >> 6);
   if (p >= f.n_particles) return;  // whole wave leaves together
@@ -53,9 +66,16 @@ cddt_status launch_cast(const MapDev& m, const float* x, const float* y, const f
 cddt_status launch_weight(const FilterDev& f, hipStream_t st) {
   if (f.n_particles == 0) return CDDT_OK;
   const int per_block = kWeightThreads / kWave;
-  int64_t blocks = (f.n_particles + per_block - 1) / per_block;
-  if (blocks > 0x7fffffffLL) return fail(CDDT_EINVAL, "too many particles for one launch");
-  hipLaunchKernelGGL(k_weight, dim3((unsigned)blocks), dim3(kWeightThreads), 0, st, f);
+  // tiles of Q particles per wave only when there are enough particles to fill the chip
+  if (f.n_rays <= kWave && f.n_particles >= kTileMinParticles) {
+    const int64_t blocks = (f.n_particles + per_block * kWeightQ - 1) / (per_block * kWeightQ);
+    if (blocks > 0x7fffffffLL) return fail(CDDT_EINVAL, "too many particles for one launch");
+    hipLaunchKernelGGL(k_weight_tiles, dim3((unsigned)blocks), dim3(kWeightThreads), 0, st, f);
+  } else {
+    const int64_t blocks = (f.n_particles + per_block - 1) / per_block;
+    if (blocks > 0x7fffffffLL) return fail(CDDT_EINVAL, "too many particles for one launch");
+    hipLaunchKernelGGL(k_weight, dim3((unsigned)blocks), dim3(kWeightThreads), 0, st, f);
+  }
   CDDT_HIP(hipGetLastError());
   return CDDT_OK;
 }

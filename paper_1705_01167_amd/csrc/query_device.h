@@ -460,4 +460,115 @@ __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, f
   return wave_sum(acc);
 }
 
+// Log-weights of `cnt` (<= Q) consecutive particles by one wave, for ray
+// layouts of at most 64 rays.  Same results as wave_particle_logw for each
+// particle, computed in three phases so that one particle's chain of
+// dependent reads (occupancy byte, header line, key line, table entry) does not
+// serialise the wave:
+//   A  lane q loads particle q's pose and occupancy byte (all Q at once);
+//   B  each particle's rays (lane = ray) are binned and paired, and the rays
+//      that search append (band, Xq) jobs to this wave's LDS queue; the queue
+//      is then drained 64 jobs per round, one lane per search;
+//   C  every ray reads its (or its partner's) result, the Q table gathers are
+//      issued together, and each particle's sum is reduced in the fixed order.
+// jobs / res: this wave's LDS slices of Q * 64 entries.
+template <int Q>
+__device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, int32_t cnt, int2* jobs,
+                                               int32_t* res) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const MapDev& m = f.map;
+  const int32_t M = f.max_range, m1 = M + 1;
+  // A: poses and the overlap check
+  float qt = 0.0f;
+  int32_t qxf = 0, qyf = 0, qok = 0;
+  if (lane < cnt) {
+    const float x = ldg(f.px + p0 + lane), y = ldg(f.py + p0 + lane);
+    qt = ldg(f.pth + p0 + lane);
+    if (pose_inside(m, x, y)) {
+      qxf = quantize16(x);
+      qyf = quantize16(y);
+      qok = ldg(m.occ + (size_t)(qyf >> 16) * (size_t)m.w + (size_t)(qxf >> 16)) == 0;
+    }
+  }
+  const bool active = lane < f.n_rays;
+  const float off = active ? ldg(f.offsets + lane) : 0.0f;
+  int32_t zo = active ? ldg(f.obs + lane) : 0;
+  zo = zo < 0 ? 0 : (zo > M ? M : zo);
+  const int P = f.pair_offset;
+  // B: bins, pairing and the search queue
+  int32_t code[Q];  // -1: no cast (range 0); else (result slot << 1) | forward
+  int32_t njobs = 0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    code[q] = -1;
+    if (q < cnt) {
+      const float pth = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, qt), q));
+      const int32_t xf = __builtin_amdgcn_readlane(qxf, q), yf = __builtin_amdgcn_readlane(qyf, q);
+      const bool ok = __builtin_amdgcn_readlane(qok, q) != 0;
+      const float th = active ? __fadd_rn(pth, off) : 0.0f;
+      const bool valid = active && ok && (fabsf(th) < 1e6f);
+      int32_t slice = 0;
+      bool fwd = true;
+      if (valid) {
+        const int32_t k = theta_bin(th, m.k_scale, m.n);
+        fwd = k < m.half;
+        slice = fwd ? k : k - m.half;
+      }
+      bool paired = false;
+      int src_c = lane;
+      if (P > 0) {
+        const int src = lane - P;
+        src_c = src >= 0 ? src : lane;
+        const int32_t ps = __shfl(valid ? slice : -1, src_c);
+        const bool cand = src >= 0 && valid && ps == slice;
+        const int pc = __shfl(cand ? 1 : 0, src_c);
+        paired = cand && !pc;
+      }
+      const bool want = valid && !paired;
+      const uint64_t mask = __ballot(want);
+      const int32_t slot = njobs + __popcll(mask & ((1ull << lane) - 1ull));
+      if (want) {
+        const Landing l = land(m, slice, xf, yf);
+        jobs[slot] = make_int2(l.row, l.xq);
+      }
+      const int32_t pslot = __shfl(slot, src_c);
+      if (valid) code[q] = ((paired ? pslot : slot) << 1) | (fwd ? 1 : 0);
+      njobs += __popcll(mask);
+    }
+  }
+  __threadfence_block();
+  for (int32_t b = 0; b < njobs; b += kWave) {
+    const int32_t j = b + lane;
+    const bool w = j < njobs;
+    const int2 jb = w ? jobs[j] : make_int2(0, 0);
+    int32_t rs, rp;
+    lane_search(m, w, jb.x, jb.y, M, rs, rp);
+    if (w) res[j] = rs | (rp << 16);
+  }
+  __threadfence_block();
+  // C: table gathers, then one fixed-order sum per particle
+  float tv[Q];
+  int32_t rg[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    tv[q] = 0.0f;
+    rg[q] = 0;
+    if (q < cnt && active) {
+      if (code[q] >= 0) {
+        const int32_t pk = res[code[q] >> 1];
+        rg[q] = (code[q] & 1) ? (pk & 0xffff) : (int32_t)((uint32_t)pk >> 16);
+      }
+      tv[q] = ldg(f.table + (int64_t)zo * m1 + rg[q]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    if (q < cnt) {
+      if (f.ranges && active) stg(f.ranges + (p0 + q) * f.n_rays + lane, rg[q]);
+      const float lw = wave_sum(tv[q]);
+      if (lane == 0) stg(f.logw + p0 + q, lw);
+    }
+  }
+}
+
 }  // namespace cddt

@@ -1,8 +1,9 @@
 """Autotuner for the persistent batched kernel.
 
 Times every tuning in a small grid (particles per tile x waves per block x
-blocks per CU x search strategy: one lane per search, or 8 lanes per search
-with 1..3 searches per group in flight) on the plan itself with
+blocks per CU x search mode: one lane per search, 8 lanes per search with 2
+searches per group in flight, or searches of 4 / 8 / 16 particles queued and
+drained together) on the plan itself with
 HIP events (cddt_plan_time) and keeps the fastest.  Results are cached in a JSON file keyed by device and a plan
 signature (filter count, particle total bucket, theta-bin set), so a later run
 with the same shape skips the sweep.
@@ -18,8 +19,8 @@ from . import cddt
 
 SPACE_PPT = (1, 2, 4, 8, 16)
 SPACE_WAVES = (1, 2, 4, 8)
-SPACE_BLOCKS = (2, 4, 8, 16)
-SPACE_K = (0, 1, 2, 3)
+SPACE_BLOCKS = (1, 2, 4, 8, 16)
+SPACE_K = (0, 2, 6, 7, 8)
 
 
 def cache_path() -> str:
@@ -29,7 +30,7 @@ def cache_path() -> str:
 
 def signature(n_filters: int, total_particles: int, theta_bins, device_name: str) -> str:
     bucket = int(round(math.log2(max(1, total_particles))))
-    return f"v3|{device_name}|f{n_filters}|p2^{bucket}|n{'-'.join(map(str, sorted(set(theta_bins))))}"
+    return f"v5|{device_name}|f{n_filters}|p2^{bucket}|n{'-'.join(map(str, sorted(set(theta_bins))))}"
 
 
 def _load() -> dict:
@@ -61,7 +62,12 @@ def autotune(plan: "cddt.Plan", sig: str, reps: int = 3, use_cache: bool = True,
         return t, cache[sig]["ms"], []
     results = []
     for t in itertools.product(SPACE_PPT, SPACE_WAVES, SPACE_BLOCKS, SPACE_K):
-        ms = plan.time(t, reps=reps, stream=stream)
+        try:
+            ms = plan.time(t, reps=reps, stream=stream)
+        except cddt.CddtError as e:
+            if e.code != cddt.EINVAL:
+                raise
+            continue  # tuning outside the kernel's limits
         results.append((ms, t))
     results.sort()
     best_ms, best = results[0]

@@ -270,7 +270,8 @@ def test_batched_plan_equals_plain():
         plain.append((ref_lw, ref_r))
         keep.append((gm, t, lw, rr))
     plan = cddt.Plan(filters, keepalive=keep)
-    for tuning in [(1, 1, 1, 1), (4, 4, 8, 2), (16, 2, 4, 3), (3, 8, 2, 4), (8, 4, 4, 5), (8, 8, 4, 0), (1, 2, 3, 0)]:
+    for tuning in [(1, 1, 1, 1), (4, 4, 8, 2), (16, 2, 4, 3), (3, 8, 2, 4), (8, 4, 4, 5), (8, 8, 4, 0), (1, 2, 3, 0),
+                   (8, 4, 8, 6), (3, 2, 4, 7), (1, 1, 1, 6), (16, 4, 2, 8), (5, 1, 3, 8)]:
         for (_, _, lw, rr) in keep:
             lw.fill_(float("nan"))
             rr.fill_(-1)
@@ -291,3 +292,25 @@ def test_batched_plan_equals_plain():
         for (_, _, lw, rr), (ref_lw, ref_r) in zip(keep, plain):
             assert torch.equal(lw, ref_lw)
     plan.close()
+
+
+def test_weight_many_particles_tiled():
+    """Plain weights over >= 2^17 particles take the queued-search path: same results."""
+    torch = _torch()
+    rng = wl.rng_for(306, 0)
+    occ = wl.building_map(rng, 700, 500)
+    n, M = 200, 400
+    rm = oref.RefCDDT(occ, n)
+    gm = _gpu_map(occ, n)
+    P = (1 << 17) + 77
+    px, py, pth = wl.free_poses(rng, occ, P)
+    off = wl.ray_offsets(61)
+    obs = rng.integers(0, M + 1, 61).astype(np.int32)
+    table = wl.beam_table(M, wl.beam_params(rng))
+    ref_lw, ref_r = rm.weight(px, py, pth, off, obs, table, M, threads=16, want_ranges=True)
+    lw, rr = _gpu_map_weight(gm, px, py, pth, off, obs, table, M)
+    assert (rr == ref_r).all()
+    assert (np.abs(lw - ref_lw) <= RTOL * np.maximum(1.0, np.abs(ref_lw))).all()
+    # the first particles alone (one-particle-per-wave path) give the same bits
+    lw_small, _ = _gpu_map_weight(gm, px[:1000], py[:1000], pth[:1000], off, obs, table, M)
+    assert (lw_small == lw[:1000]).all()
