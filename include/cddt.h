@@ -202,12 +202,13 @@ typedef struct {
 
 typedef struct {
   int32_t particles_per_tile; /* particles a wave takes per queue pop (1..256) */
-  int32_t waves_per_block;    /* 1..16 */
+  int32_t waves_per_block;    /* 1..8 */
   int32_t blocks_per_cu;      /* persistent blocks per compute unit (1..32) */
   int32_t search_mode;        /* 0: one lane per band search, one particle per wave at a time;
                                  1..5: eight lanes per search, this many searches per 8-lane
                                  group in flight; 6 / 7 / 8: one lane per search, the searches
-                                 of 4 / 8 / 16 particles queued in LDS and drained together */
+                                 of 4 / 8 / 16 particles queued in LDS and drained together;
+                                 9 / 10: as 7 / 8 with two searches per lane per round */
 } cddt_tuning;
 
 typedef struct cddt_plan_s* cddt_plan;

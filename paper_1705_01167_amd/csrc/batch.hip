@@ -45,15 +45,22 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
 // Search modes (the tuning's search_mode): 0 one lane per search, one particle
 // per wave at a time; 1..5 eight lanes per search with that many searches per
 // group in flight; 6 / 7 / 8 one lane per search with the searches of 4 / 8 /
-// 16 particles queued in LDS and drained together (ray layouts of <= 64 rays;
-// longer layouts fall back to mode 0).
-constexpr int kModeTile4 = 6, kModeTile8 = 7, kModeTile16 = 8;
+// 16 particles queued in LDS and drained together, one search per lane per
+// round; 9 / 10 the same with 8 / 16 particles and two searches per lane per
+// round (ray layouts of <= 64 rays; longer layouts fall back to mode 0).
+constexpr int kModeTile4 = 6, kModeTile8 = 7, kModeTile16 = 8, kModeTile8x2 = 9, kModeTile16x2 = 10;
 __host__ __device__ constexpr int tile_q(int mode) {
-  return mode == kModeTile4 ? 4 : (mode == kModeTile8 ? 8 : (mode == kModeTile16 ? 16 : 0));
+  return (mode == kModeTile4) ? 4
+         : (mode == kModeTile8 || mode == kModeTile8x2) ? 8
+         : (mode == kModeTile16 || mode == kModeTile16x2) ? 16
+                                                          : 0;
 }
+__host__ __device__ constexpr bool tile_x2(int mode) { return mode == kModeTile8x2 || mode == kModeTile16x2; }
+
+constexpr int kMaxBatchThreads = 512;
 
 template <int Mode>
-__global__ void k_batch(const FilterDev* __restrict__ filters, const int64_t* __restrict__ prefix,
+__global__ __launch_bounds__(kMaxBatchThreads) void k_batch(const FilterDev* __restrict__ filters, const int64_t* __restrict__ prefix,
                         int32_t n_filters, int64_t total_tiles, int32_t ppt,
                         unsigned long long* __restrict__ counter) {
   extern __shared__ int2 smem_jobs[];
@@ -81,7 +88,8 @@ __global__ void k_batch(const FilterDev* __restrict__ filters, const int64_t* __
     const int64_t p1 = p0 + ppt < f.n_particles ? p0 + ppt : f.n_particles;
     if constexpr (Q > 0) {
       if (f.n_rays <= kWave) {
-        for (int64_t p = p0; p < p1; p += Q) wave_tile_logw<Q>(f, p, (int32_t)min((int64_t)Q, p1 - p), jobs, res);
+        for (int64_t p = p0; p < p1; p += Q)
+          wave_tile_logw<Q, tile_x2(Mode)>(f, p, (int32_t)min((int64_t)Q, p1 - p), jobs, res);
         continue;
       }
     }
@@ -122,9 +130,11 @@ cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, in
       CDDT_BATCH_K(6)
       CDDT_BATCH_K(7)
       CDDT_BATCH_K(8)
+      CDDT_BATCH_K(9)
+      CDDT_BATCH_K(10)
 #undef CDDT_BATCH_K
       default:
-        return fail(CDDT_EINVAL, "tuning: search_mode must be in 0..8");
+        return fail(CDDT_EINVAL, "tuning: search_mode must be in 0..10");
     }
   }
   CDDT_HIP(hipGetLastError());
@@ -134,10 +144,10 @@ cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, in
 cddt_status check_tuning(const cddt_tuning& t) {
   if (t.particles_per_tile < 1 || t.particles_per_tile > 256)
     return fail(CDDT_EINVAL, "tuning: particles_per_tile must be in 1..256");
-  if (t.waves_per_block < 1 || t.waves_per_block > 16)
-    return fail(CDDT_EINVAL, "tuning: waves_per_block must be in 1..16");
+  if (t.waves_per_block < 1 || t.waves_per_block * kWave > kMaxBatchThreads)
+    return fail(CDDT_EINVAL, "tuning: waves_per_block must be in 1..8");
   if (t.blocks_per_cu < 1 || t.blocks_per_cu > 32) return fail(CDDT_EINVAL, "tuning: blocks_per_cu must be in 1..32");
-  if (t.search_mode < 0 || t.search_mode > 8) return fail(CDDT_EINVAL, "tuning: search_mode must be in 0..8");
+  if (t.search_mode < 0 || t.search_mode > 10) return fail(CDDT_EINVAL, "tuning: search_mode must be in 0..10");
   if ((size_t)t.waves_per_block * tile_q(t.search_mode) * kWave * (sizeof(int2) + sizeof(int32_t)) > 65536)
     return fail(CDDT_EINVAL, "tuning: the search queue of this mode and block size exceeds 64 KiB of LDS");
   return CDDT_OK;
@@ -148,7 +158,7 @@ cddt_tuning default_tuning() {
   t.particles_per_tile = 4;
   t.waves_per_block = 4;
   t.blocks_per_cu = 8;
-  t.search_mode = kModeTile8;
+  t.search_mode = kModeTile16;
   return t;
 }
 

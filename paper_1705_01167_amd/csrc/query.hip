@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kWeightThreads) void k_weight_tiles(FilterDev f) {
   const int64_t p0 = ((int64_t)blockIdx.x * (kWeightThreads / kWave) + wave) * kWeightQ;
   if (p0 >= f.n_particles) return;  // whole wave leaves together
   const int32_t cnt = (int32_t)min((int64_t)kWeightQ, f.n_particles - p0);
-  wave_tile_logw<kWeightQ>(f, p0, cnt, jobs[wave], res[wave]);
+  wave_tile_logw<kWeightQ, false>(f, p0, cnt, jobs[wave], res[wave]);
 }
 
 __global__ __launch_bounds__(kWeightThreads) void k_weight(FilterDev f) {

@@ -361,6 +361,66 @@ __device__ __forceinline__ void lane_search(const MapDev& m, bool want, int32_t 
   }
 }
 
+// Two independent band searches by one lane, their line requests issued side
+// by side (the second search's lines are in flight while the first's are
+// scanned).  Same results as two lane_search calls.
+__device__ __forceinline__ void lane_search2(const MapDev& m, bool wa, int32_t ra, int32_t xa, bool wb, int32_t rb,
+                                             int32_t xb, int32_t max_range, int32_t& sa, int32_t& pa, int32_t& sb,
+                                             int32_t& pb) {
+  sa = pa = sb = pb = max_range;
+  if (!wa && !wb) return;
+  Line32 A, B;
+  if (wa) A = load_line(m.hdr + (int64_t)ra * kNodeInts);
+  if (wb) B = load_line(m.hdr + (int64_t)rb * kNodeInts);
+  uint32_t st_a = 0, st_b = 0, cp_a = 0, cp_b = 0;
+  int32_t ln_a = 0, ln_b = 0, ca = 0, cb = 0, na = INT_MAX, nb = INT_MAX, va = INT_MIN, vb = INT_MIN, ta = -1, tb = -1;
+  if (wa) {
+    st_a = (uint32_t)A.e[0];
+    ln_a = A.e[1];
+    cp_a = (uint32_t)A.e[2];
+    scan_line<kHeaderWords>(A, xa, INT_MAX, ca, na, va);
+    ta = ca > 0 ? top_level(ln_a) - 1 : -1;
+  }
+  if (wb) {
+    st_b = (uint32_t)B.e[0];
+    ln_b = B.e[1];
+    cp_b = (uint32_t)B.e[2];
+    scan_line<kHeaderWords>(B, xb, INT_MAX, cb, nb, vb);
+    tb = cb > 0 ? top_level(ln_b) - 1 : -1;
+  }
+  while (ta >= 0 || tb >= 0) {
+    const int32_t ka = ca - 1, kb = cb - 1;
+    if (ta >= 0) A = load_line(m.zeros + level_base(st_a, cp_a, ta) + (uint32_t)ka * kLineInts);
+    if (tb >= 0) B = load_line(m.zeros + level_base(st_b, cp_b, tb) + (uint32_t)kb * kLineInts);
+    if (ta >= 0) {
+      int32_t lc;
+      scan_line<0>(A, xa, na, lc, na, va);
+      ca = ka * kLineInts + lc;
+      --ta;
+    }
+    if (tb >= 0) {
+      int32_t lc;
+      scan_line<0>(B, xb, nb, lc, nb, vb);
+      cb = kb * kLineInts + lc;
+      --tb;
+    }
+  }
+  auto finish = [&](bool w, uint32_t st, int32_t ln, int32_t c, int32_t nx, int32_t pv, int32_t x, int32_t& rs,
+                    int32_t& rp) {
+    if (!w) return;
+    if (c < ln) rs = range_of((int64_t)nx - x, max_range);
+    if (c > 0) {
+      if (pv == x) {  // rare: x equals a key; find the last key strictly below it
+        const int32_t lb = lower_bound_i32(m.zeros + st, c, x);
+        pv = lb > 0 ? ldg(m.zeros + st + lb - 1) : INT_MIN;
+      }
+      if (pv != INT_MIN) rp = range_of((int64_t)x - pv, max_range);
+    }
+  };
+  finish(wa, st_a, ln_a, ca, na, va, xa, sa, pa);
+  finish(wb, st_b, ln_b, cb, nb, vb, xb, sb, pb);
+}
+
 // Search strategy: K = 0 one lane per search, K >= 1 eight lanes per search
 // with K searches per group in flight.
 template <int K>
@@ -471,8 +531,9 @@ __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, f
 //      is then drained 64 jobs per round, one lane per search;
 //   C  every ray reads its (or its partner's) result, the Q table gathers are
 //      issued together, and each particle's sum is reduced in the fixed order.
-// jobs / res: this wave's LDS slices of Q * 64 entries.
-template <int Q>
+// jobs / res: this wave's LDS slices of Q * 64 entries.  With Lanes2 each lane
+// runs two searches of a round side by side (128 searches per round).
+template <int Q, int Lanes2>
 __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, int32_t cnt, int2* jobs,
                                                int32_t* res) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -537,13 +598,26 @@ __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, i
     }
   }
   __threadfence_block();
-  for (int32_t b = 0; b < njobs; b += kWave) {
-    const int32_t j = b + lane;
-    const bool w = j < njobs;
-    const int2 jb = w ? jobs[j] : make_int2(0, 0);
-    int32_t rs, rp;
-    lane_search(m, w, jb.x, jb.y, M, rs, rp);
-    if (w) res[j] = rs | (rp << 16);
+  if constexpr (Lanes2) {  // two searches per lane per round
+    for (int32_t b = 0; b < njobs; b += 2 * kWave) {
+      const int32_t ja = b + lane, jb = b + kWave + lane;
+      const bool wa = ja < njobs, wb = jb < njobs;
+      const int2 qa = wa ? jobs[ja] : make_int2(0, 0);
+      const int2 qb = wb ? jobs[jb] : make_int2(0, 0);
+      int32_t sa, pa, sb, pb;
+      lane_search2(m, wa, qa.x, qa.y, wb, qb.x, qb.y, M, sa, pa, sb, pb);
+      if (wa) res[ja] = sa | (pa << 16);
+      if (wb) res[jb] = sb | (pb << 16);
+    }
+  } else {
+    for (int32_t b = 0; b < njobs; b += kWave) {
+      const int32_t j = b + lane;
+      const bool w = j < njobs;
+      const int2 jb = w ? jobs[j] : make_int2(0, 0);
+      int32_t rs, rp;
+      lane_search(m, w, jb.x, jb.y, M, rs, rp);
+      if (w) res[j] = rs | (rp << 16);
+    }
   }
   __threadfence_block();
   // C: table gathers, then one fixed-order sum per particle

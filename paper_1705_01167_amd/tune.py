@@ -2,8 +2,8 @@
 
 Times every tuning in a small grid (particles per tile x waves per block x
 blocks per CU x search mode: one lane per search, 8 lanes per search with 2
-searches per group in flight, or searches of 4 / 8 / 16 particles queued and
-drained together) on the plan itself with
+searches per group in flight, or searches of 8 / 16 particles queued and
+drained with one or two searches per lane per round) on the plan itself with
 HIP events (cddt_plan_time) and keeps the fastest.  Results are cached in a JSON file keyed by device and a plan
 signature (filter count, particle total bucket, theta-bin set), so a later run
 with the same shape skips the sweep.
@@ -20,7 +20,7 @@ from . import cddt
 SPACE_PPT = (1, 2, 4, 8, 16)
 SPACE_WAVES = (1, 2, 4, 8)
 SPACE_BLOCKS = (1, 2, 4, 8, 16)
-SPACE_K = (0, 2, 6, 7, 8)
+SPACE_K = (0, 2, 7, 8, 9, 10)
 
 
 def cache_path() -> str:
@@ -30,7 +30,7 @@ def cache_path() -> str:
 
 def signature(n_filters: int, total_particles: int, theta_bins, device_name: str) -> str:
     bucket = int(round(math.log2(max(1, total_particles))))
-    return f"v5|{device_name}|f{n_filters}|p2^{bucket}|n{'-'.join(map(str, sorted(set(theta_bins))))}"
+    return f"v6|{device_name}|f{n_filters}|p2^{bucket}|n{'-'.join(map(str, sorted(set(theta_bins))))}"
 
 
 def _load() -> dict:

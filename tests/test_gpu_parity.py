@@ -271,7 +271,8 @@ def test_batched_plan_equals_plain():
         keep.append((gm, t, lw, rr))
     plan = cddt.Plan(filters, keepalive=keep)
     for tuning in [(1, 1, 1, 1), (4, 4, 8, 2), (16, 2, 4, 3), (3, 8, 2, 4), (8, 4, 4, 5), (8, 8, 4, 0), (1, 2, 3, 0),
-                   (8, 4, 8, 6), (3, 2, 4, 7), (1, 1, 1, 6), (16, 4, 2, 8), (5, 1, 3, 8)]:
+                   (8, 4, 8, 6), (3, 2, 4, 7), (1, 1, 1, 6), (16, 4, 2, 8), (5, 1, 3, 8),
+                   (8, 2, 2, 9), (16, 1, 8, 10), (7, 3, 1, 10)]:
         for (_, _, lw, rr) in keep:
             lw.fill_(float("nan"))
             rr.fill_(-1)
