@@ -264,7 +264,8 @@ typedef struct cddt_server_s* cddt_server;
 
 typedef struct {
   int64_t budget_bytes;     /* device staging budget for request inputs/outputs */
-  int32_t n_lanes;          /* batches in flight (streams), 1..8 */
+  int32_t n_lanes;          /* batches in flight (streams), 1..8; 1 gave the lowest latency
+                               measured, since one persistent launch already fills the device */
   int32_t max_batch;        /* requests per batch, 1..4096 */
   int32_t max_rays;         /* rays per request, 1..1024 */
   int32_t reserved;
@@ -277,6 +278,8 @@ typedef struct {
   int64_t rays;
   int64_t peak_bytes;       /* highest staging bytes in use */
   double busy_seconds;      /* wall time with at least one batch in flight */
+  double device_seconds;    /* sum over batches of device time, input copy start to output copy end */
+  double max_batch_seconds; /* the slowest batch's device time */
 } cddt_server_stats;
 
 /* maps_h: host array of n_maps resident maps (not owned).  Per map: its ray
@@ -293,13 +296,27 @@ cddt_status cddt_server_create(const cddt_map* maps_h, int32_t n_maps,
 cddt_status cddt_server_submit(cddt_server s, int32_t map_index, const float* px_h,
                                const float* py_h, const float* ptheta_h, int32_t n_particles,
                                const int32_t* obs_h, int64_t* id_h);
+/* Measurement helper (an open-loop load generator), not part of the method:
+ * submits request i at_h[i] seconds after the call starts (offsets not
+ * decreasing) from the calling thread, exactly as cddt_server_submit would,
+ * and records that scheduled arrival as its submit time, so latency is
+ * measured from the arrival even when a submission runs late.  Arrays are host arrays of n entries; request i reads
+ * px_h[i], py_h[i], ptheta_h[i] (count_h[i] floats each) and obs_h[i].  Blocks
+ * until the last request is submitted; ids_h[i] receives the id, or -1 if the
+ * request was refused (EBUSY).  Errors: EINVAL (nothing submitted). */
+cddt_status cddt_server_replay(cddt_server s, int32_t n, const int32_t* map_h, const int32_t* count_h,
+                               const float* const* px_h, const float* const* py_h,
+                               const float* const* ptheta_h, const int32_t* const* obs_h,
+                               const double* at_h, int64_t* ids_h);
 /* Non-blocking: 1 if the request finished (logw copied to logw_h, which must
  * hold n_particles floats, and the request released), 0 if not yet. */
 cddt_status cddt_server_poll(cddt_server s, int64_t id, float* logw_h, int32_t* done_h);
 /* Blocking form of poll. */
 cddt_status cddt_server_wait(cddt_server s, int64_t id, float* logw_h);
 /* Completion time of a finished request, seconds since server creation
- * (result visible on the host), and its submit time. */
+ * (result visible on the host), and its submit time.  Kept for the 65536 most
+ * recent completions (a fixed ring, so a long-running server holds bounded
+ * memory); EINVAL for a request not finished or completed longer ago. */
 cddt_status cddt_server_times(cddt_server s, int64_t id, double* submit_h, double* done_h);
 cddt_status cddt_server_stats_get(cddt_server s, cddt_server_stats* out_h);
 /* Seconds since server creation on the server's clock. */

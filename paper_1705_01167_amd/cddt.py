@@ -60,7 +60,8 @@ class ServerConfig(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
                 ("batches", C.c_int64), ("rays", C.c_int64), ("peak_bytes", C.c_int64),
-                ("busy_seconds", C.c_double)]
+                ("busy_seconds", C.c_double), ("device_seconds", C.c_double),
+                ("max_batch_seconds", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -102,6 +103,7 @@ SIGNATURES = {
     "cddt_probe_gather": (_i32, [_vp, _i64, _i32, _i32, _i32, _u32, _vp, _vp]),
     "cddt_server_create": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, C.POINTER(ServerConfig), C.POINTER(_vp)]),
     "cddt_server_submit": (_i32, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, C.POINTER(_i64)]),
+    "cddt_server_replay": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cddt_server_poll": (_i32, [_vp, _i64, _vp, C.POINTER(_i32)]),
     "cddt_server_wait": (_i32, [_vp, _i64, _vp]),
     "cddt_server_times": (_i32, [_vp, _i64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -389,7 +391,7 @@ def probe_gather(gib: float = 4.0, depth: int = 4, steps: int = 64, blocks: int 
 class Server:
     """Continuous-batching server over resident maps (cddt_server_*)."""
 
-    def __init__(self, maps, offsets, tables, max_ranges, budget_bytes: int = 1 << 30, n_lanes: int = 4,
+    def __init__(self, maps, offsets, tables, max_ranges, budget_bytes: int = 1 << 30, n_lanes: int = 1,
                  max_batch: int = 256, tuning=(8, 4, 2, 7)):
         n = len(maps)
         self._offsets = [np.ascontiguousarray(np.asarray(o, np.float32)) for o in offsets]
@@ -423,6 +425,36 @@ class Server:
                                         obs.ctypes.data_as(C.c_void_p), C.byref(rid)))
         self._sizes[rid.value] = px.size
         return rid.value
+
+    def replay(self, reqs, at):
+        """Open-loop replay: request i = (map, px, py, pth, obs) submitted at[i] s after the call starts.
+
+        Returns the request ids (-1 where refused); srv.times(id)[0] is the scheduled arrival."""
+        n = len(reqs)
+        keep = []
+        arr = {k: (C.c_void_p * n)() for k in ("px", "py", "pth", "obs")}
+        maps = np.zeros(n, np.int32)
+        counts = np.zeros(n, np.int32)
+        for i, (m, px, py, pth, obs) in enumerate(reqs):
+            a = [np.ascontiguousarray(px, np.float32), np.ascontiguousarray(py, np.float32),
+                 np.ascontiguousarray(pth, np.float32), np.ascontiguousarray(obs, np.int32)]
+            if a[3].size != self._n_rays[m]:
+                raise ValueError("obs must hold one range per ray of the map")
+            keep.append(a)
+            maps[i], counts[i] = m, a[0].size
+            for k, v in zip(("px", "py", "pth", "obs"), a):
+                arr[k][i] = v.ctypes.data
+        at = np.ascontiguousarray(at, np.float64)
+        ids = np.full(n, -1, np.int64)
+        _check(lib().cddt_server_replay(self.handle, n, maps.ctypes.data_as(C.c_void_p),
+                                        counts.ctypes.data_as(C.c_void_p), C.cast(arr["px"], C.c_void_p),
+                                        C.cast(arr["py"], C.c_void_p), C.cast(arr["pth"], C.c_void_p),
+                                        C.cast(arr["obs"], C.c_void_p), at.ctypes.data_as(C.c_void_p),
+                                        ids.ctypes.data_as(C.c_void_p)))
+        for i, rid in enumerate(ids.tolist()):
+            if rid >= 0:
+                self._sizes[rid] = int(counts[i])
+        return ids
 
     def poll(self, rid: int):
         out = np.empty(self._sizes[rid], np.float32)

@@ -13,7 +13,7 @@
 // nothing else, so a run can be captured into a hipGraph and replayed.
 #include <algorithm>
 
-#include "query_device.h"
+#include "batch_kernel.h"
 
 struct cddt_plan_s {
   std::vector<cddt_filter> filters;
@@ -30,86 +30,12 @@ struct cddt_plan_s {
 };
 
 namespace cddt {
-namespace {
-
-__global__ void k_reset_counter(unsigned long long* counter) {
-  if (threadIdx.x == 0) *counter = 0ull;
-}
-
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
-  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// Search modes (the tuning's search_mode): 0 one lane per search, one particle
-// per wave at a time; 1..5 eight lanes per search with that many searches per
-// group in flight; 6 / 7 / 8 one lane per search with the searches of 4 / 8 /
-// 16 particles queued in LDS and drained together, one search per lane per
-// round; 9 / 10 the same with 8 / 16 particles and two searches per lane per
-// round (ray layouts of <= 64 rays; longer layouts fall back to mode 0).
-constexpr int kModeTile4 = 6, kModeTile8 = 7, kModeTile16 = 8, kModeTile8x2 = 9, kModeTile16x2 = 10;
-__host__ __device__ constexpr int tile_q(int mode) {
-  return (mode == kModeTile4) ? 4
-         : (mode == kModeTile8 || mode == kModeTile8x2) ? 8
-         : (mode == kModeTile16 || mode == kModeTile16x2) ? 16
-                                                          : 0;
-}
-__host__ __device__ constexpr bool tile_x2(int mode) { return mode == kModeTile8x2 || mode == kModeTile16x2; }
-
-constexpr int kMaxBatchThreads = 512;
-
-template <int Mode>
-__global__ __launch_bounds__(kMaxBatchThreads) void k_batch(const FilterDev* __restrict__ filters, const int64_t* __restrict__ prefix,
-                        int32_t n_filters, int64_t total_tiles, int32_t ppt,
-                        unsigned long long* __restrict__ counter) {
-  extern __shared__ int2 smem_jobs[];
-  constexpr int Q = tile_q(Mode);
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  int2* jobs = smem_jobs + wave * Q * kWave;
-  int32_t* res = reinterpret_cast<int32_t*>(smem_jobs + nw * Q * kWave) + wave * Q * kWave;
-  for (;;) {
-    uint64_t t = 0;
-    if (lane == 0) t = atomicAdd(counter, 1ull);
-    t = __shfl((unsigned long long)t, 0);
-    t = uniform_u64(t);
-    if (t >= (uint64_t)total_tiles) break;
-    int32_t lo = 0, hi = n_filters;  // prefix[lo] <= t < prefix[hi]
-    while (hi - lo > 1) {
-      int32_t mid = (lo + hi) >> 1;
-      if ((uint64_t)ldg(prefix + mid) <= t)
-        lo = mid;
-      else
-        hi = mid;
-    }
-    const FilterDev f = filters[lo];
-    const int64_t p0 = (int64_t)(t - (uint64_t)ldg(prefix + lo)) * ppt;
-    const int64_t p1 = p0 + ppt < f.n_particles ? p0 + ppt : f.n_particles;
-    if constexpr (Q > 0) {
-      if (f.n_rays <= kWave) {
-        for (int64_t p = p0; p < p1; p += Q)
-          wave_tile_logw<Q, tile_x2(Mode)>(f, p, (int32_t)min((int64_t)Q, p1 - p), jobs, res);
-        continue;
-      }
-    }
-    constexpr int K = Q > 0 ? 0 : Mode;
-    for (int64_t p = p0; p < p1; ++p) {
-      float lw = wave_particle_logw<K>(f.map, ldg(f.px + p), ldg(f.py + p), ldg(f.pth + p), f.offsets, f.obs,
-                                       f.n_rays, f.pair_offset, f.table, f.max_range,
-                                       f.ranges ? f.ranges + p * f.n_rays : nullptr);
-      if (lane == 0) stg(f.logw + p, lw);
-    }
-  }
-}
-
-}  // namespace
 
 // Counter reset plus one persistent launch over the tiles of n_filters filters.
 cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, int32_t n_filters,
                          int64_t total_tiles, const cddt_tuning& t, unsigned long long* d_counter, int32_t cus,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, d_counter);
+                         hipStream_t st, bool counter_zeroed) {
+  if (!counter_zeroed) hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, d_counter);
   if (total_tiles > 0) {
     const unsigned blocks = (unsigned)std::max(1, cus * t.blocks_per_cu);
     const unsigned threads = (unsigned)(kWave * t.waves_per_block);

@@ -1,0 +1,65 @@
+// Device-side types and helpers of libcddt: the per-map and per-filter
+// descriptors that kernels take by value, and the edge-cell test.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cddt {
+
+// One stored slice: direction (2^30 fixed point), lowest band index, and the
+// index of its first band in the global band arrays.
+struct SliceDev {
+  int32_t c, s, row_min, row_base;
+};
+
+// Everything a query needs about one map, passed by value to kernels.
+struct MapDev {
+  const uint8_t* occ;        // W*H grid, row-major, nonzero = occupied
+  const SliceDev* slices;    // n/2 entries
+  const int32_t* hdr;        // per band: a 128-byte header node (band_layout.h)
+  const int32_t* zeros;      // band regions: keys (Q16, ascending) and sample levels
+  int32_t w, h, n, half;
+  float k_scale;             // (float)(n / (2 pi))
+  int32_t pad;
+};
+
+// One filter of a batched step (device copy of cddt_filter plus its map).
+struct FilterDev {
+  MapDev map;
+  const float* px;
+  const float* py;
+  const float* pth;
+  const float* offsets;
+  const int32_t* obs;
+  const float* table;
+  float* logw;
+  int32_t* ranges;
+  int64_t n_particles;
+  int32_t n_rays, pair_offset, max_range, pad;
+};
+
+constexpr int kWave = 64;
+
+// Edge-map test of cell (i, j) (Sec. IV-C): occupied, and at least one of its
+// 8 neighbours is free or off the map.  With `full` every occupied cell counts.
+__device__ __forceinline__ bool edge_cell(const uint8_t* __restrict__ occ, int w, int h, int i, int j, int full) {
+  if (occ[(size_t)j * w + i] == 0) return false;
+  if (full) return true;
+  for (int dj = -1; dj <= 1; ++dj) {
+    const int b = j + dj;
+    if (b < 0 || b >= h) return true;  // off-map neighbour counts as free
+    for (int di = -1; di <= 1; ++di) {
+      const int a = i + di;
+      if (a < 0 || a >= w) return true;
+      if (occ[(size_t)b * w + a] == 0) return true;
+    }
+  }
+  return false;
+}
+constexpr int kMaxSide = 16384;
+constexpr int kMaxBins = 8192;
+constexpr int kMaxRays = 1024;
+
+}  // namespace cddt

@@ -5,9 +5,10 @@
 // has its own stream, a device arena of budget_bytes / n_lanes and pinned host
 // staging.  Whenever a lane is idle, the scheduler admits queued requests in
 // arrival order while the lane's arena and batch size allow, packs their
-// inputs and filter descriptors into the staging buffer, and issues one
-// upload, one persistent batched launch (the same kernel as cddt_plan_run) and
-// one download on the lane's stream, followed by an event.  Up to n_lanes
+// inputs and filter descriptors into the staging buffer, and issues a staging
+// kernel that pulls them into the arena, one persistent batched launch (the
+// same kernel as cddt_plan_run) and one download on the lane's stream,
+// followed by an event.  Up to n_lanes
 // batches are in flight at once, so requests that arrive while others run are
 // admitted as lanes and memory free up and their work overlaps on the device.
 // A batch's requests complete when its event has fired: their log-weights are
@@ -54,18 +55,34 @@ struct Request {
   bool done = false;
 };
 
+struct TimesSlot {
+  int64_t id = -1;
+  double submit = 0, done = 0;
+};
+constexpr size_t kTimesRing = 1 << 16;
+constexpr double kSpinSeconds = 200e-6;  // idle polling before the scheduler blocks
+
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
+// Copy a lane's packed inputs from pinned host memory into its device arena.
+__global__ void k_stage_in(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n16) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 struct Lane {
   hipStream_t stream = nullptr;
-  hipEvent_t done = nullptr;
+  hipEvent_t start = nullptr;  // before the input copy
+  hipEvent_t done = nullptr;   // after the output copy
   char* d_arena = nullptr;   // device: [descriptors][prefix][counter][inputs...][outputs...]
   char* h_in = nullptr;      // pinned staging of the same layout (inputs part)
+  const char* h_in_dev = nullptr;  // h_in as the device addresses it
   float* h_out = nullptr;    // pinned log-weights
   size_t arena = 0;
   std::vector<Request*> batch;
   std::vector<size_t> out_off;  // per request: float offset of its log-weights in h_out
+  size_t out_floats = 0;
   size_t bytes = 0;
   bool busy = false;
 };
@@ -83,7 +100,8 @@ struct cddt_server_s {
   std::condition_variable cv_work, cv_done;
   std::deque<cddt::Request*> queue;
   std::unordered_map<int64_t, cddt::Request*> live;
-  std::unordered_map<int64_t, std::pair<double, double>> times;
+  // submit/done times of the most recent completions, slot id % kTimesRing
+  std::vector<cddt::TimesSlot> times = std::vector<cddt::TimesSlot>(cddt::kTimesRing);
   std::thread sched;
   bool stop = false;
   int64_t next_id = 0;
@@ -105,25 +123,28 @@ size_t request_bytes(const cddt_server_s* s, int32_t map, int32_t n) {
          sizeof(int64_t);
 }
 
-// Pack a lane's admitted batch into its staging buffer and launch it.  Called
-// with the lock held; HIP calls only enqueue work.
-cddt_status launch_lane(cddt_server_s* s, Lane& L) {
+// Pack a lane's admitted batch into its staging buffer and launch it.  Runs
+// on the scheduler thread without the lock: the lane and the requests in its
+// batch belong to the scheduler until they are marked done.  The kernel's tile
+// counter is cleared by the same host-to-device copy that carries the inputs.
+cddt_status launch_lane(const cddt_server_s* s, Lane& L) {
   const size_t nb = L.batch.size();
   const size_t desc_bytes = align_up(sizeof(FilterDev) * nb);
   const size_t prefix_bytes = align_up(sizeof(int64_t) * (nb + 1));
   const size_t counter_off = desc_bytes + prefix_bytes;
   size_t off = counter_off + kAlign;
-  std::vector<FilterDev> fd(nb);
-  std::vector<int64_t> prefix(nb + 1, 0);
+  FilterDev* fd = (FilterDev*)L.h_in;
+  int64_t* prefix = (int64_t*)(L.h_in + desc_bytes);
+  *(unsigned long long*)(L.h_in + counter_off) = 0ull;
+  prefix[0] = 0;
   L.out_off.assign(nb, 0);
   size_t out_floats = 0;
   const int64_t ppt = s->cfg.tuning.particles_per_tile;
   for (size_t k = 0; k < nb; ++k) {
-    Request* r = L.batch[k];
+    const Request* r = L.batch[k];
     const ServedMap& m = s->maps[r->map];
     const size_t n = (size_t)r->n;
-    float* hp = (float*)(L.h_in + off);
-    std::memcpy(hp, r->poses.data(), n * 12);
+    std::memcpy(L.h_in + off, r->poses.data(), n * 12);
     const char* dp = L.d_arena + off;
     off += align_up(n * 12);
     std::memcpy(L.h_in + off, r->obs.data(), (size_t)m.n_rays * 4);
@@ -149,111 +170,167 @@ cddt_status launch_lane(cddt_server_s* s, Lane& L) {
   }
   const size_t in_bytes = off;
   for (size_t k = 0; k < nb; ++k) fd[k].logw = (float*)(L.d_arena + in_bytes) + L.out_off[k];
-  std::memcpy(L.h_in, fd.data(), sizeof(FilterDev) * nb);
-  std::memcpy(L.h_in + desc_bytes, prefix.data(), sizeof(int64_t) * (nb + 1));
-  CDDT_HIP(hipMemcpyAsync(L.d_arena, L.h_in, in_bytes, hipMemcpyHostToDevice, L.stream));
+  L.out_floats = out_floats;
+  CDDT_HIP(hipEventRecord(L.start, L.stream));
+  // the inputs are pulled from pinned memory by a kernel, so that all of a
+  // batch's device work runs on the lane's one queue
+  const size_t n16 = in_bytes / 16;  // in_bytes is a multiple of kAlign
+  const unsigned blocks = (unsigned)std::min<size_t>((n16 + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_stage_in, dim3(blocks), dim3(256), 0, L.stream, (const uint4*)L.h_in_dev, (uint4*)L.d_arena,
+                     n16);
   CDDT_TRY(launch_batch((const FilterDev*)L.d_arena, (const int64_t*)(L.d_arena + desc_bytes), (int32_t)nb,
                         prefix[nb], s->cfg.tuning, (unsigned long long*)(L.d_arena + counter_off), s->cus,
-                        L.stream));
+                        L.stream, /*counter_zeroed=*/true));
   CDDT_HIP(hipMemcpyAsync(L.h_out, L.d_arena + in_bytes, out_floats * 4, hipMemcpyDeviceToHost, L.stream));
   CDDT_HIP(hipEventRecord(L.done, L.stream));
   return CDDT_OK;
 }
 
+// Lock held.  Report NaN weights for a batch that could not run.
 void fail_batch(cddt_server_s* s, Lane& L) {
   const double t = s->now();
-  for (Request* r : L.batch) {  // report NaN weights for a batch that could not run
+  for (Request* r : L.batch) {
     r->logw.assign((size_t)r->n, __builtin_nanf(""));
     r->done = true;
     r->done_t = t;
-    s->times[r->id] = {r->submit_t, t};
+    s->times[(size_t)r->id % kTimesRing] = {r->id, r->submit_t, t};
   }
   L.batch.clear();
   s->cv_done.notify_all();
 }
 
+// The scheduler alternates between work done without the lock (event polls,
+// copying results out of pinned memory, packing and enqueueing batches) and
+// short critical sections that publish completions and take queued requests,
+// so submitters are never held up by HIP calls.
 void scheduler(cddt_server_s* s) {
   (void)hipSetDevice(s->device);
-  std::unique_lock<std::mutex> lk(s->mu);
+  std::vector<char> finished(s->lanes.size()), failed(s->lanes.size()), launched(s->lanes.size());
+  std::vector<hipError_t> status(s->lanes.size());
+  std::vector<double> device_s(s->lanes.size());
+  bool any_busy = false;
+  double idle_since = -1.0;
   for (;;) {
-    bool any_busy = false;
-    // retire finished batches
-    for (Lane& L : s->lanes) {
+    // 1. unlocked: poll in-flight lanes, copy finished results into their requests
+    for (size_t l = 0; l < s->lanes.size(); ++l) {
+      Lane& L = s->lanes[l];
+      finished[l] = 0;
       if (!L.busy) continue;
-      const hipError_t q = hipEventQuery(L.done);
-      if (q == hipErrorNotReady) {
-        any_busy = true;
-        continue;
+      status[l] = hipEventQuery(L.done);
+      if (status[l] == hipErrorNotReady) continue;
+      finished[l] = 1;
+      if (status[l] != hipSuccess) continue;
+      float ms = 0.f;
+      device_s[l] = hipEventElapsedTime(&ms, L.start, L.done) == hipSuccess ? 1e-3 * ms : 0.0;
+      for (size_t k = 0; k < L.batch.size(); ++k) {
+        Request* r = L.batch[k];
+        r->logw.assign(L.h_out + L.out_off[k], L.h_out + L.out_off[k] + r->n);
+        r->poses.clear();
+        r->poses.shrink_to_fit();
       }
-      if (q != hipSuccess) {
-        s->error = hipGetErrorString(q);
+    }
+    // 2. locked: publish completions, admit queued requests into idle lanes
+    bool any_new = false;
+    {
+      std::lock_guard<std::mutex> g(s->mu);
+      const double t = s->now();
+      bool notify = false;
+      for (size_t l = 0; l < s->lanes.size(); ++l) {
+        Lane& L = s->lanes[l];
+        if (!finished[l]) continue;
+        s->bytes_in_flight -= (int64_t)L.bytes;
+        L.bytes = 0;
+        L.busy = false;
+        if (status[l] != hipSuccess) {
+          s->error = hipGetErrorString(status[l]);
+          fail_batch(s, L);
+          continue;
+        }
+        s->stats.device_seconds += device_s[l];
+        s->stats.max_batch_seconds = std::max(s->stats.max_batch_seconds, device_s[l]);
+        for (Request* r : L.batch) {
+          r->done_t = t;
+          r->done = true;
+          s->times[(size_t)r->id % kTimesRing] = {r->id, r->submit_t, t};
+          s->stats.completed++;
+          s->stats.rays += (int64_t)r->n * s->maps[r->map].n_rays;
+        }
+        L.batch.clear();
+        notify = true;
+      }
+      if (notify) s->cv_done.notify_all();
+      for (size_t l = 0; l < s->lanes.size(); ++l) {
+        Lane& L = s->lanes[l];
+        launched[l] = 0;
+        if (L.busy || s->queue.empty()) continue;
+        size_t used = 0;
+        while (!s->queue.empty() && (int32_t)L.batch.size() < s->cfg.max_batch) {
+          Request* r = s->queue.front();
+          if (used + r->bytes > L.arena) break;
+          used += r->bytes;
+          L.batch.push_back(r);
+          s->queue.pop_front();
+        }
+        if (L.batch.empty()) continue;
+        L.bytes = used;
+        L.busy = true;
+        launched[l] = 1;
+        any_new = true;
+        s->stats.batches++;
+        s->bytes_in_flight += (int64_t)used;
+        s->stats.peak_bytes = std::max<int64_t>(s->stats.peak_bytes, s->bytes_in_flight);
+      }
+      any_busy = false;
+      for (const Lane& L : s->lanes) any_busy |= L.busy;
+      if (any_busy && s->busy_since < 0) s->busy_since = t;
+      if (!any_busy && s->busy_since >= 0) {
+        s->stats.busy_seconds += t - s->busy_since;
+        s->busy_since = -1.0;
+      }
+    }
+    // 3. unlocked: pack and enqueue the new batches
+    if (any_new) {
+      for (size_t l = 0; l < s->lanes.size(); ++l) {
+        if (!launched[l]) continue;
+        Lane& L = s->lanes[l];
+        if (launch_lane(s, L) == CDDT_OK) continue;
+        const std::string err = cddt_last_error();
+        std::lock_guard<std::mutex> g(s->mu);
+        s->error = err;
         s->bytes_in_flight -= (int64_t)L.bytes;
         L.bytes = 0;
         L.busy = false;
         fail_batch(s, L);
-        continue;
       }
-      const double t = s->now();
-      for (size_t k = 0; k < L.batch.size(); ++k) {
-        Request* r = L.batch[k];
-        r->logw.assign(L.h_out + L.out_off[k], L.h_out + L.out_off[k] + r->n);
-        r->done_t = t;
-        r->done = true;
-        s->times[r->id] = {r->submit_t, t};
-        s->stats.completed++;
-        s->stats.rays += (int64_t)r->n * s->maps[r->map].n_rays;
-        r->poses.clear();
-        r->poses.shrink_to_fit();
-      }
-      s->bytes_in_flight -= (int64_t)L.bytes;
-      L.batch.clear();
-      L.bytes = 0;
-      L.busy = false;
-      s->cv_done.notify_all();
+      continue;  // poll again at once: completions may already be waiting
     }
-    // admit queued requests into idle lanes
-    for (Lane& L : s->lanes) {
-      if (L.busy || s->queue.empty()) continue;
-      size_t used = 0;
-      while (!s->queue.empty() && (int32_t)L.batch.size() < s->cfg.max_batch) {
-        Request* r = s->queue.front();
-        if (used + r->bytes > L.arena) break;
-        used += r->bytes;
-        L.batch.push_back(r);
-        s->queue.pop_front();
-      }
-      if (L.batch.empty()) continue;
-      L.bytes = used;
-      if (launch_lane(s, L) != CDDT_OK) {
-        s->error = cddt_last_error();
-        L.bytes = 0;
-        fail_batch(s, L);
-        continue;
-      }
-      L.busy = true;
-      any_busy = true;
-      s->stats.batches++;
-      s->bytes_in_flight += (int64_t)used;
-      s->stats.peak_bytes = std::max<int64_t>(s->stats.peak_bytes, s->bytes_in_flight);
-    }
-    const double t = s->now();
-    if (any_busy && s->busy_since < 0) s->busy_since = t;
-    if (!any_busy && s->busy_since >= 0) {
-      s->stats.busy_seconds += t - s->busy_since;
-      s->busy_since = -1.0;
-    }
-    if (s->stop && !any_busy) break;
+    // 4. wait for arrivals or for in-flight batches to finish.  While work is in
+    // flight, or shortly after it, the thread polls (yielding the core between
+    // polls) rather than sleeping, since a timed sleep or a wake-up costs tens
+    // of microseconds of latency; an idle server blocks on the condition.
     if (any_busy) {
-      // batches in flight: poll their events again shortly (new arrivals wake us too)
-      s->cv_work.wait_for(lk, std::chrono::microseconds(20));
-    } else if (s->queue.empty()) {
-      s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+      idle_since = -1.0;
+      std::this_thread::yield();
+      continue;
     }
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->stop) break;
+    if (!s->queue.empty()) continue;
+    const double t = s->now();
+    if (idle_since < 0) idle_since = t;
+    if (t - idle_since < kSpinSeconds) {
+      lk.unlock();
+      std::this_thread::yield();
+      continue;
+    }
+    s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+    idle_since = -1.0;
   }
 }
 
 void destroy_lanes(cddt_server_s* s) {
   for (Lane& L : s->lanes) {
+    if (L.start) (void)hipEventDestroy(L.start);
     if (L.done) (void)hipEventDestroy(L.done);
     if (L.stream) (void)hipStreamDestroy(L.stream);
     if (L.d_arena) (void)hipFree(L.d_arena);
@@ -266,6 +343,14 @@ void destroy_lanes(cddt_server_s* s) {
   s->maps.clear();
 }
 
+}  // namespace
+}  // namespace cddt
+
+namespace cddt {
+namespace {
+cddt_status submit_one(cddt_server_s* s, int32_t map_index, const float* px_h, const float* py_h,
+                       const float* ptheta_h, int32_t n_particles, const int32_t* obs_h, double arrival,
+                       int64_t* id_h);
 }  // namespace
 }  // namespace cddt
 
@@ -320,10 +405,11 @@ cddt_status cddt_server_create(const cddt_map* maps_h, int32_t n_maps, const flo
     const size_t fixed = align_up(sizeof(FilterDev) * c.max_batch) + align_up(sizeof(int64_t) * (c.max_batch + 1)) +
                          kAlign;
     if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&L.start) != hipSuccess || hipEventCreate(&L.done) != hipSuccess ||
         hipMalloc(&L.d_arena, fixed + arena) != hipSuccess ||
         hipHostMalloc((void**)&L.h_in, fixed + arena, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&L.h_out, arena, hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc((void**)&L.h_out, arena, hipHostMallocDefault) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&L.h_in_dev, L.h_in, 0) != hipSuccess)
       return bail("cddt_server_create: lane allocation failed");
   }
   s->sched = std::thread(scheduler, s);
@@ -337,6 +423,39 @@ cddt_status cddt_server_submit(cddt_server s, int32_t map_index, const float* px
   if (map_index < 0 || map_index >= (int32_t)s->maps.size()) return fail(CDDT_EINVAL, "cddt_server_submit: bad map");
   if (n_particles < 0 || (n_particles > 0 && (!px_h || !py_h || !ptheta_h)) || !obs_h)
     return fail(CDDT_EINVAL, "cddt_server_submit: bad particle or observation arrays");
+  return submit_one(s, map_index, px_h, py_h, ptheta_h, n_particles, obs_h, -1.0, id_h);
+}
+
+cddt_status cddt_server_replay(cddt_server s, int32_t n, const int32_t* map_h, const int32_t* count_h,
+                               const float* const* px_h, const float* const* py_h, const float* const* ptheta_h,
+                               const int32_t* const* obs_h, const double* at_h, int64_t* ids_h) {
+  if (!s || n < 0 || (n > 0 && (!map_h || !count_h || !px_h || !py_h || !ptheta_h || !obs_h || !at_h || !ids_h)))
+    return fail(CDDT_EINVAL, "cddt_server_replay: NULL argument");
+  for (int32_t i = 0; i < n; ++i) {  // validate everything before the first submission
+    if (map_h[i] < 0 || map_h[i] >= (int32_t)s->maps.size()) return fail(CDDT_EINVAL, "cddt_server_replay: bad map");
+    if (count_h[i] < 0 || (count_h[i] > 0 && (!px_h[i] || !py_h[i] || !ptheta_h[i])) || !obs_h[i])
+      return fail(CDDT_EINVAL, "cddt_server_replay: bad particle or observation arrays");
+    if (at_h[i] < 0.0 || (i > 0 && at_h[i] < at_h[i - 1]))
+      return fail(CDDT_EINVAL, "cddt_server_replay: offsets must be non-negative and not decrease");
+  }
+  const double t0 = s->now();
+  for (int32_t i = 0; i < n; ++i) {
+    const double at = t0 + at_h[i];
+    while (s->now() < at) {
+    }
+    ids_h[i] = -1;
+    submit_one(s, map_h[i], px_h[i], py_h[i], ptheta_h[i], count_h[i], obs_h[i], at, &ids_h[i]);
+  }
+  return CDDT_OK;
+}
+
+}  // extern "C"
+
+namespace cddt {
+namespace {
+cddt_status submit_one(cddt_server_s* s, int32_t map_index, const float* px_h, const float* py_h,
+                       const float* ptheta_h, int32_t n_particles, const int32_t* obs_h, double arrival,
+                       int64_t* id_h) {
   const size_t bytes = request_bytes(s, map_index, n_particles);
   Request* r = new Request();
   r->map = map_index;
@@ -352,10 +471,10 @@ cddt_status cddt_server_submit(cddt_server s, int32_t map_index, const float* px
     if (bytes > s->lanes[0].arena || s->stop) {
       s->stats.rejected++;
       delete r;
-      return fail(CDDT_EBUSY, "cddt_server_submit: request larger than a lane's share of the budget");
+      return fail(CDDT_EBUSY, "server: request larger than a lane's share of the budget");
     }
     r->id = s->next_id++;
-    r->submit_t = s->now();
+    r->submit_t = arrival >= 0.0 ? arrival : s->now();
     s->live[r->id] = r;
     s->queue.push_back(r);
     s->stats.submitted++;
@@ -364,6 +483,10 @@ cddt_status cddt_server_submit(cddt_server s, int32_t map_index, const float* px
   s->cv_work.notify_one();
   return CDDT_OK;
 }
+}  // namespace
+}  // namespace cddt
+
+extern "C" {
 
 cddt_status cddt_server_poll(cddt_server s, int64_t id, float* logw_h, int32_t* done_h) {
   if (!s || !done_h) return fail(CDDT_EINVAL, "cddt_server_poll: NULL argument");
@@ -396,10 +519,11 @@ cddt_status cddt_server_wait(cddt_server s, int64_t id, float* logw_h) {
 cddt_status cddt_server_times(cddt_server s, int64_t id, double* submit_h, double* done_h) {
   if (!s || !submit_h || !done_h) return fail(CDDT_EINVAL, "cddt_server_times: NULL argument");
   std::lock_guard<std::mutex> g(s->mu);
-  auto it = s->times.find(id);
-  if (it == s->times.end()) return fail(CDDT_EINVAL, "cddt_server_times: request not finished");
-  *submit_h = it->second.first;
-  *done_h = it->second.second;
+  const cddt::TimesSlot& t = s->times[(size_t)(id < 0 ? 0 : id) % cddt::kTimesRing];
+  if (id < 0 || t.id != id)
+    return fail(CDDT_EINVAL, "cddt_server_times: request not finished, or one of the oldest completions");
+  *submit_h = t.submit;
+  *done_h = t.done;
   return CDDT_OK;
 }
 

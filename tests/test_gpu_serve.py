@@ -63,6 +63,30 @@ def test_alone_equals_mix_equals_plain():
     srv.close()
 
 
+def test_replay_equals_submit():
+    """Open-loop replay from the native thread gives the same results as submit; times are the schedule."""
+    from paper_1705_01167_amd import cddt
+    rng, maps, offs, tabs, occs, M = _setup(seed=3)
+    reqs = _requests(rng, occs, M, 60)
+    srv = cddt.Server(maps, offs, tabs, [M] * 3, budget_bytes=8 << 20, n_lanes=2, max_batch=16)
+    ref = [srv.wait(srv.submit(*r)) for r in reqs]
+    at = np.cumsum(np.full(len(reqs), 2e-4))
+    ids = srv.replay(reqs, at)
+    assert (ids >= 0).all()
+    arrive = []
+    for rid, r in zip(ids.tolist(), ref):
+        assert srv.wait(rid).tobytes() == r.tobytes()
+        s, d = srv.times(rid)
+        assert s <= d
+        arrive.append(s)
+    gaps = np.diff(arrive)
+    assert np.allclose(gaps, 2e-4, atol=1e-9)      # submit time is the scheduled arrival
+    with pytest.raises(cddt.CddtError):
+        srv.replay(reqs[:2], [1e-3, 0.0])           # decreasing offsets: refused, nothing submitted
+    assert srv.stats()["submitted"] == 120
+    srv.close()
+
+
 def test_budget_admission_and_reject():
     from paper_1705_01167_amd import cddt
     rng, maps, offs, tabs, occs, M = _setup(seed=1, sides=(256,), bins=(108,))
