@@ -3,11 +3,12 @@
 // A plan holds a device table of filter descriptors (map, particles, rays,
 // observations, table, outputs) and the prefix sums of their tile counts.
 // The persistent grid has blocks_per_cu blocks per compute unit; every wave
-// repeatedly takes the next tile index from a 64-bit device counter, finds
+// repeatedly takes the next tile index from one of eight 64-bit device
+// counters (one per contiguous part of the tiles), finds
 // its filter by binary search over the prefix sums and computes the tile's
 // particle weights with the same per-particle routine as the plain kernel, so
-// the results are identical bit for bit.  A wave leaves when the counter
-// passes the last tile, so the grid always drains.
+// the results are identical bit for bit.  A wave leaves when every part's
+// counter has passed the part's last tile, so the grid always drains.
 //
 // Each run is two kernel launches (counter reset, persistent kernel) and
 // nothing else, so a run can be captured into a hipGraph and replayed.
@@ -40,7 +41,7 @@ cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, in
     const unsigned blocks = (unsigned)std::max(1, cus * t.blocks_per_cu);
     const unsigned threads = (unsigned)(kWave * t.waves_per_block);
     const int32_t ppt = t.particles_per_tile;
-    const size_t lds = (size_t)t.waves_per_block * tile_q(t.search_mode) * kWave * (sizeof(int2) + sizeof(int32_t));
+    const size_t lds = tile_lds_bytes(t.search_mode, t.waves_per_block);
     switch (t.search_mode) {
 #define CDDT_BATCH_K(KK)                                                                                        \
   case KK:                                                                                                      \
@@ -74,7 +75,7 @@ cddt_status check_tuning(const cddt_tuning& t) {
     return fail(CDDT_EINVAL, "tuning: waves_per_block must be in 1..8");
   if (t.blocks_per_cu < 1 || t.blocks_per_cu > 32) return fail(CDDT_EINVAL, "tuning: blocks_per_cu must be in 1..32");
   if (t.search_mode < 0 || t.search_mode > 10) return fail(CDDT_EINVAL, "tuning: search_mode must be in 0..10");
-  if ((size_t)t.waves_per_block * tile_q(t.search_mode) * kWave * (sizeof(int2) + sizeof(int32_t)) > 65536)
+  if (tile_lds_bytes(t.search_mode, t.waves_per_block) > 65536)
     return fail(CDDT_EINVAL, "tuning: the search queue of this mode and block size exceeds 64 KiB of LDS");
   return CDDT_OK;
 }
@@ -151,7 +152,7 @@ cddt_status cddt_plan_create(const cddt_filter* filters_h, int32_t n_filters, co
   };
   if (hipMalloc(&p->d_filters, sizeof(FilterDev) * n_filters) != hipSuccess ||
       hipMalloc(&p->d_prefix, sizeof(int64_t) * (n_filters + 1)) != hipSuccess ||
-      hipMalloc(&p->d_counter, sizeof(unsigned long long)) != hipSuccess)
+      hipMalloc(&p->d_counter, kBatchCounterBytes) != hipSuccess)
     return bail("cddt_plan_create: hipMalloc failed");
   if (hipMemcpyAsync(p->d_filters, p->fdev.data(), sizeof(FilterDev) * n_filters, hipMemcpyHostToDevice, st) !=
       hipSuccess)

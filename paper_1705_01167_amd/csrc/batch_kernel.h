@@ -1,7 +1,8 @@
 // The persistent batched kernel: every wave repeatedly takes the next tile
-// index from a 64-bit device counter, finds its filter by binary search over
-// the prefix sums of tile counts and computes the tile's particle weights
-// with the same per-particle routine as the plain kernel.
+// index from the 64-bit device counter of its part of the tiles, finds its
+// filter by binary search over the prefix sums of tile counts and computes
+// the tile's particle weights with the same per-particle routine as the plain
+// kernel.
 #pragma once
 
 #include "query_device.h"
@@ -9,8 +10,17 @@
 namespace cddt {
 namespace {
 
+// Tiles are split into kTileParts contiguous parts, one counter each, 256
+// bytes apart: blocks are dispatched to the 8 XCDs in turn, so block b starts
+// on part b % 8, and the device-scope increments of one launch spread over
+// eight addresses instead of queueing on one.  A wave whose part is used up
+// moves on to the next part; it leaves after finding all of them used up.
+constexpr int kTileParts = 8;
+constexpr int kCounterStride = 32;  // 64-bit words between counters
+static_assert(kTileParts * kCounterStride * sizeof(unsigned long long) == kBatchCounterBytes, "counter block size");
+
 __global__ void k_reset_counter(unsigned long long* counter) {
-  if (threadIdx.x == 0) *counter = 0ull;
+  if (threadIdx.x < kTileParts) counter[threadIdx.x * kCounterStride] = 0ull;
 }
 
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
@@ -36,6 +46,13 @@ __host__ __device__ constexpr bool tile_x2(int mode) { return mode == kModeTile8
 
 constexpr int kMaxBatchThreads = 512;
 
+// Dynamic LDS of one block: per wave and queued particle slot, a search job
+// (int2, whose first word later holds the packed result) and the lane's
+// result code (int32).
+__host__ __device__ constexpr size_t tile_lds_bytes(int mode, int waves) {
+  return (size_t)waves * tile_q(mode) * kWave * (sizeof(int2) + sizeof(int32_t));
+}
+
 template <int Mode>
 __global__ __launch_bounds__(kMaxBatchThreads) void k_batch(const FilterDev* __restrict__ filters, const int64_t* __restrict__ prefix,
                         int32_t n_filters, int64_t total_tiles, int32_t ppt,
@@ -45,13 +62,20 @@ __global__ __launch_bounds__(kMaxBatchThreads) void k_batch(const FilterDev* __r
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   int2* jobs = smem_jobs + wave * Q * kWave;
-  int32_t* res = reinterpret_cast<int32_t*>(smem_jobs + nw * Q * kWave) + wave * Q * kWave;
+  int32_t* codes = reinterpret_cast<int32_t*>(smem_jobs + nw * Q * kWave) + wave * Q * kWave;
+  int part = (int)(blockIdx.x % kTileParts), exhausted = 0;
   for (;;) {
+    const uint64_t part_lo = (uint64_t)total_tiles * part / kTileParts;
+    const uint64_t part_hi = (uint64_t)total_tiles * (part + 1) / kTileParts;
     uint64_t t = 0;
-    if (lane == 0) t = atomicAdd(counter, 1ull);
+    if (lane == 0) t = atomicAdd(counter + part * kCounterStride, 1ull);
     t = __shfl((unsigned long long)t, 0);
-    t = uniform_u64(t);
-    if (t >= (uint64_t)total_tiles) break;
+    t = uniform_u64(t) + part_lo;
+    if (t >= part_hi) {
+      if (++exhausted == kTileParts) break;
+      part = (part + 1) % kTileParts;
+      continue;
+    }
     int32_t lo = 0, hi = n_filters;  // prefix[lo] <= t < prefix[hi]
     while (hi - lo > 1) {
       int32_t mid = (lo + hi) >> 1;
@@ -66,7 +90,7 @@ __global__ __launch_bounds__(kMaxBatchThreads) void k_batch(const FilterDev* __r
     if constexpr (Q > 0) {
       if (f.n_rays <= kWave) {
         for (int64_t p = p0; p < p1; p += Q)
-          wave_tile_logw<Q, tile_x2(Mode)>(f, p, (int32_t)min((int64_t)Q, p1 - p), jobs, res);
+          wave_tile_logw<Q, tile_x2(Mode)>(f, p, (int32_t)min((int64_t)Q, p1 - p), jobs, codes);
         continue;
       }
     }

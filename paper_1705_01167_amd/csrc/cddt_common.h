@@ -94,7 +94,9 @@ cddt_status refresh_stats(cddt_map_s* m, hipStream_t st);
 cddt_status launch_cast(const MapDev& m, const float* x, const float* y, const float* th, int64_t n,
                         int32_t max_range, int32_t* out, hipStream_t st);
 cddt_status launch_weight(const FilterDev& f, hipStream_t st);
-// batch.hip; counter_zeroed: the caller has already cleared *d_counter in stream order
+// batch.hip.  d_counter: kBatchCounterBytes of device memory (the per-part
+// tile counters); counter_zeroed: the caller has already cleared all of it in
+// stream order.
 cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, int32_t n_filters,
                          int64_t total_tiles, const cddt_tuning& t, unsigned long long* d_counter, int32_t cus,
                          hipStream_t st, bool counter_zeroed = false);

@@ -61,5 +61,7 @@ __device__ __forceinline__ bool edge_cell(const uint8_t* __restrict__ occ, int w
 constexpr int kMaxSide = 16384;
 constexpr int kMaxBins = 8192;
 constexpr int kMaxRays = 1024;
+// Bytes of device memory holding the persistent batched kernel's tile counters.
+constexpr size_t kBatchCounterBytes = 2048;
 
 }  // namespace cddt

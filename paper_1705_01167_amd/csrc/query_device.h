@@ -531,11 +531,12 @@ __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, f
 //      is then drained 64 jobs per round, one lane per search;
 //   C  every ray reads its (or its partner's) result, the Q table gathers are
 //      issued together, and each particle's sum is reduced in the fixed order.
-// jobs / res: this wave's LDS slices of Q * 64 entries.  With Lanes2 each lane
-// runs two searches of a round side by side (128 searches per round).
+// jobs / codes: this wave's LDS slices of Q * 64 entries (a job's first word
+// is overwritten by its packed result).  With Lanes2 each lane runs two
+// searches of a round side by side (128 searches per round).
 template <int Q, int Lanes2>
 __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, int32_t cnt, int2* jobs,
-                                               int32_t* res) {
+                                               int32_t* codes) {
   const int lane = threadIdx.x & (kWave - 1);
   const MapDev& m = f.map;
   const int32_t M = f.max_range, m1 = M + 1;
@@ -557,11 +558,12 @@ __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, i
   zo = zo < 0 ? 0 : (zo > M ? M : zo);
   const int P = f.pair_offset;
   // B: bins, pairing and the search queue
-  int32_t code[Q];  // -1: no cast (range 0); else (result slot << 1) | forward
+  // codes[q][lane]: -1 no cast (range 0); else (result slot << 1) | forward.
+  // Kept in LDS rather than registers while the searches run.
   int32_t njobs = 0;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    code[q] = -1;
+    int32_t code = -1;
     if (q < cnt) {
       const float pth = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, qt), q));
       const int32_t xf = __builtin_amdgcn_readlane(qxf, q), yf = __builtin_amdgcn_readlane(qyf, q);
@@ -593,9 +595,10 @@ __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, i
         jobs[slot] = make_int2(l.row, l.xq);
       }
       const int32_t pslot = __shfl(slot, src_c);
-      if (valid) code[q] = ((paired ? pslot : slot) << 1) | (fwd ? 1 : 0);
+      if (valid) code = ((paired ? pslot : slot) << 1) | (fwd ? 1 : 0);
       njobs += __popcll(mask);
     }
+    codes[q * kWave + lane] = code;
   }
   __threadfence_block();
   if constexpr (Lanes2) {  // two searches per lane per round
@@ -606,8 +609,8 @@ __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, i
       const int2 qb = wb ? jobs[jb] : make_int2(0, 0);
       int32_t sa, pa, sb, pb;
       lane_search2(m, wa, qa.x, qa.y, wb, qb.x, qb.y, M, sa, pa, sb, pb);
-      if (wa) res[ja] = sa | (pa << 16);
-      if (wb) res[jb] = sb | (pb << 16);
+      if (wa) jobs[ja].x = sa | (pa << 16);  // the result replaces its job
+      if (wb) jobs[jb].x = sb | (pb << 16);
     }
   } else {
     for (int32_t b = 0; b < njobs; b += kWave) {
@@ -616,7 +619,7 @@ __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, i
       const int2 jb = w ? jobs[j] : make_int2(0, 0);
       int32_t rs, rp;
       lane_search(m, w, jb.x, jb.y, M, rs, rp);
-      if (w) res[j] = rs | (rp << 16);
+      if (w) jobs[j].x = rs | (rp << 16);
     }
   }
   __threadfence_block();
@@ -628,9 +631,10 @@ __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, i
     tv[q] = 0.0f;
     rg[q] = 0;
     if (q < cnt && active) {
-      if (code[q] >= 0) {
-        const int32_t pk = res[code[q] >> 1];
-        rg[q] = (code[q] & 1) ? (pk & 0xffff) : (int32_t)((uint32_t)pk >> 16);
+      const int32_t code = codes[q * kWave + lane];
+      if (code >= 0) {
+        const int32_t pk = jobs[code >> 1].x;
+        rg[q] = (code & 1) ? (pk & 0xffff) : (int32_t)((uint32_t)pk >> 16);
       }
       tv[q] = ldg(f.table + (int64_t)zo * m1 + rg[q]);
     }

@@ -132,10 +132,10 @@ cddt_status launch_lane(const cddt_server_s* s, Lane& L) {
   const size_t desc_bytes = align_up(sizeof(FilterDev) * nb);
   const size_t prefix_bytes = align_up(sizeof(int64_t) * (nb + 1));
   const size_t counter_off = desc_bytes + prefix_bytes;
-  size_t off = counter_off + kAlign;
+  size_t off = counter_off + kBatchCounterBytes;
   FilterDev* fd = (FilterDev*)L.h_in;
   int64_t* prefix = (int64_t*)(L.h_in + desc_bytes);
-  *(unsigned long long*)(L.h_in + counter_off) = 0ull;
+  std::memset(L.h_in + counter_off, 0, kBatchCounterBytes);
   prefix[0] = 0;
   L.out_off.assign(nb, 0);
   size_t out_floats = 0;
@@ -403,7 +403,7 @@ cddt_status cddt_server_create(const cddt_map* maps_h, int32_t n_maps, const flo
   for (Lane& L : s->lanes) {
     L.arena = arena;
     const size_t fixed = align_up(sizeof(FilterDev) * c.max_batch) + align_up(sizeof(int64_t) * (c.max_batch + 1)) +
-                         kAlign;
+                         kBatchCounterBytes;
     if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&L.start) != hipSuccess || hipEventCreate(&L.done) != hipSuccess ||
         hipMalloc(&L.d_arena, fixed + arena) != hipSuccess ||
