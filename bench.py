@@ -36,11 +36,14 @@ PEAK_HBM_GBS = 8000.0
 RAYS = 61
 SEARCHES = 40         # 61 rays with radial pairing of rays r and r + 40 (21 pairs)
 MAX_RANGE = 500
+BUCKETS: int | None = 7  # log2 bucket width of the maps' bucket index (None: no index); set by --buckets
 
-# Algorithmic bytes per particle of the fused step: pose 12 + occupancy byte 1
-# + log-weight out 4 + per search (band header 8 + bracketing zero point 4)
-# + the second bracketing zero point of each of the 21 pairs 4 + one table
-# entry per ray 4.
+# Algorithmic bytes per particle of the fused step, as the method defines it
+# (a bin is a sorted array reached through its offset and length): pose 12 +
+# occupancy byte 1 + log-weight out 4 + per search (band offset and length 8 +
+# bracketing zero point 4) + the second bracketing zero point of each of the
+# 21 pairs 4 + one table entry per ray 4.  The same figure is used with the
+# bucket index, which reads no band header.
 BYTES_PER_PARTICLE = 12 + 1 + 4 + SEARCHES * (8 + 4) + (RAYS - SEARCHES) * 4 + RAYS * 4
 # Algorithmic bytes per plain cast: pose 12 + occupancy 1 + header 8 + zero point 4 + range out 4.
 BYTES_PER_CAST = 12 + 1 + 8 + 4 + 4
@@ -118,7 +121,7 @@ def build_batched(n_filters: int):
         table = wl.beam_table(MAX_RANGE, wl.beam_params(wl.rng_for(wl.BATCHED, wl.S_TABLE, f)))
         t1 = time.perf_counter()
         occ_d = t_dev(occ)
-        m = cddt.Map(occ_d, sp["theta_bins"])
+        m = cddt.Map(occ_d, sp["theta_bins"], buckets=BUCKETS)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         del occ_d
@@ -180,7 +183,8 @@ def run_batched(args) -> dict:
 
     stream = torch.cuda.Stream()
     plan = cddt.Plan(filters, stream=stream, keepalive=keep)
-    sig = tune.signature(len(specs), particles, [s["theta_bins"] for s in specs], torch.cuda.get_device_name(0))
+    sig = tune.signature(len(specs), particles, [s["theta_bins"] for s in specs], torch.cuda.get_device_name(0),
+                         BUCKETS)
     t0 = time.perf_counter()
     if args.tuning:
         best = tuple(int(v) for v in args.tuning.split(","))
@@ -235,6 +239,10 @@ def run_batched(args) -> dict:
             "zero_points": int(sum(s["zero_points"] for s in stats)),
             "bands": int(sum(s["rows"] for s in stats)),
             "structure_bytes": int(sum(s["device_bytes"] for s in stats)),
+            "bucket_index": ({"log2_width_cells": BUCKETS or 7,
+                              "lines": int(sum(s["bucket_lines"] for s in stats)),
+                              "overflow_buckets": int(sum(s["bucket_overflow"] for s in stats))}
+                             if BUCKETS is not None else None),
             "tuning": {"particles_per_tile": best[0], "waves_per_block": best[1], "blocks_per_cu": best[2],
                        "search_mode": best[3]},
             "parallelism": "single GPU",
@@ -282,7 +290,7 @@ def run_small(args) -> dict:
     from paper_1705_01167_amd import cddt
     from paper_1705_01167_amd import workloads as wl
     occ = wl.rect_map(wl.rng_for(wl.SMALL, wl.S_MAP))
-    m = cddt.Map(t_dev(occ), 108)
+    m = cddt.Map(t_dev(occ), 108, buckets=BUCKETS)
     px, py, pth = wl.free_poses(wl.rng_for(wl.SMALL, wl.S_POSES), occ, 1000)
     off = wl.ray_offsets(RAYS)
     x = t_dev(np.repeat(px, RAYS))
@@ -307,7 +315,7 @@ def run_floor(args) -> dict:
     from paper_1705_01167_amd import cddt
     from paper_1705_01167_amd import workloads as wl
     occ = wl.building_map(wl.rng_for(wl.FLOOR, wl.S_MAP), 2000, 2000)
-    m = cddt.Map(t_dev(occ), 200)
+    m = cddt.Map(t_dev(occ), 200, buckets=BUCKETS)
     off_h = wl.ray_offsets(RAYS)
     px, py, pth = wl.free_poses(wl.rng_for(wl.FLOOR, wl.S_POSES), occ, 2500)
     table = t_dev(wl.beam_table(MAX_RANGE, wl.beam_params(wl.rng_for(wl.FLOOR, wl.S_TABLE))))
@@ -336,7 +344,7 @@ def run_updates(args) -> dict:
     occ = wl.building_map(wl.rng_for(wl.UPDATES, wl.S_MAP), 4000, 4000)
     n, P = 200, 1_000_000
     t0 = time.perf_counter()
-    m = cddt.Map(t_dev(occ), n)
+    m = cddt.Map(t_dev(occ), n, buckets=BUCKETS)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     off = t_dev(wl.ray_offsets(RAYS))
@@ -367,7 +375,7 @@ def run_updates(args) -> dict:
         if i >= args.warmup:
             upd_s += t1 - t0
             cast_s += e0.elapsed_time(e1) / 1e3
-    fresh = cddt.Map(t_dev(cur), n)
+    fresh = cddt.Map(t_dev(cur), n, buckets=BUCKETS)
     same = all((a == b).all() for a, b in zip(m.export(), fresh.export()))
     rays = x.numel()
     info = m.info()
@@ -401,7 +409,7 @@ def build_serving():
     for i, side in enumerate(SERVE_SIDES):
         n = int(wl.THETA_CHOICES[int(rng.integers(0, 3))])
         occ = wl.building_map(wl.rng_for(wl.SERVING, wl.S_MAP, i), side, side)
-        maps.append(cddt.Map(t_dev(occ), n))
+        maps.append(cddt.Map(t_dev(occ), n, buckets=BUCKETS))
         offs.append(off_h)
         tabs.append(t_dev(wl.beam_table(MAX_RANGE, wl.beam_params(wl.rng_for(wl.SERVING, wl.S_TABLE, i)))))
         pools.append(wl.free_poses(wl.rng_for(wl.SERVING, wl.S_POSES, i), occ, 20000))
@@ -496,6 +504,8 @@ def main():
     ap.add_argument("--workload", default="batched",
                     choices=["batched", "small", "floor", "updates", "serving", "probe"])
     ap.add_argument("--filters", type=int, default=64)
+    ap.add_argument("--buckets", type=str, default="7",
+                    help="log2 bucket width in cells of the maps' bucket index, or 'none' for no index")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving summary")
     ap.add_argument("--no-probe", action="store_true", help="skip the gather-bandwidth probe")
@@ -512,6 +522,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
+    global BUCKETS
+    BUCKETS = None if args.buckets.lower() == "none" else int(args.buckets)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return

@@ -72,8 +72,21 @@ enum {
 /* Construction flags. */
 enum {
   CDDT_FLAG_FULL_MAP = 1u << 0, /* project every occupied cell, not only the edge map */
-  CDDT_FLAG_STATIC = 1u << 1    /* no per-row slack: smallest structure, updates rebuild */
+  CDDT_FLAG_STATIC = 1u << 1,   /* no per-row slack: smallest structure, updates rebuild */
+  CDDT_FLAG_BUCKETS = 1u << 2   /* add the bucket index described below */
 };
+/* Bucket index (an addition to Sec. IV-A's bins, same results): every band
+ * of every stored slice is cut into fixed-width buckets along the slice
+ * direction, 2^k cells wide, starting at the lowest projection of the map
+ * rectangle onto that slice.  Each bucket is one 128-byte line holding its
+ * zero points, the last zero point before it and the first one after it, so
+ * a band search reads one line, addressed from the band and the query's
+ * projection alone (no header read).  A bucket with more than 30 zero points
+ * sends its searches to the band's sorted search lines instead.  Costs
+ * rows * buckets-per-band * 128 bytes, about 1.8 * (theta_bins / 2) *
+ * width * height * 128 / 2^k bytes for a square map; kept current by
+ * cddt_update.  k (4..10) goes in bits 8..11 of flags; 0 selects k = 7. */
+#define CDDT_BUCKET_LOG2(k) ((uint32_t)(k) << 8)
 
 /* Device memory for the structure.  alloc returns a device pointer of at
  * least `bytes` bytes (NULL on failure); free releases it.  Both are called
@@ -94,8 +107,12 @@ typedef struct {
   int64_t zero_points;   /* stored zero points (sum of row lengths) */
   int64_t capacity;      /* allocated zero-point slots (>= zero_points; slack for updates) */
   int64_t max_row_len;
-  int64_t device_bytes;  /* bytes the map holds on the device */
+  int64_t device_bytes;  /* bytes the map holds on the device (bucket index included) */
   int64_t rebuilds;      /* updates that overflowed a row and re-laid the structure */
+  int64_t bucket_lines;  /* lines of the bucket index (0 without CDDT_FLAG_BUCKETS) */
+  int64_t bucket_overflow; /* buckets whose searches use the band's search lines */
+  int32_t bucket_log2;   /* bucket width 2^k cells (0 without the index) */
+  int32_t reserved2;
 } cddt_stats;
 
 /* Build a CDDT from an occupancy grid (Sec. IV-A: erosion to the edge map,

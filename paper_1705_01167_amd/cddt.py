@@ -17,6 +17,14 @@ LIB_PATH = os.path.join(HERE, "libcddt.so")
 OK, EINVAL, ENOMEM, EDEVICE, EBUSY, EINTERNAL = 0, -1, -2, -3, -4, -5
 FLAG_FULL_MAP = 1
 FLAG_STATIC = 2
+FLAG_BUCKETS = 4
+
+
+def bucket_flags(log2_width: int | None) -> int:
+    """Flag bits for a bucket index of 2^log2_width cells (None: no index, 0: the default width)."""
+    if log2_width is None:
+        return 0
+    return FLAG_BUCKETS | (int(log2_width) << 8)
 
 
 class CddtError(RuntimeError):
@@ -30,10 +38,11 @@ class Stats(C.Structure):
                 ("slices", C.c_int32), ("flags", C.c_uint32), ("reserved", C.c_uint32),
                 ("rows", C.c_int64), ("edge_cells", C.c_int64), ("zero_points", C.c_int64),
                 ("capacity", C.c_int64), ("max_row_len", C.c_int64), ("device_bytes", C.c_int64),
-                ("rebuilds", C.c_int64)]
+                ("rebuilds", C.c_int64), ("bucket_lines", C.c_int64), ("bucket_overflow", C.c_int64),
+                ("bucket_log2", C.c_int32), ("reserved2", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
 
 
 class Filter(C.Structure):
@@ -182,7 +191,8 @@ class Map:
     """A CDDT resident on the GPU (cddt_create / cddt_destroy)."""
 
     def __init__(self, occ, theta_bins: int, full_map: bool = False, static: bool = False,
-                 allocator: Allocator | None = None, stream=None):
+                 allocator: Allocator | None = None, stream=None, buckets: int | None = None):
+        """buckets: None for no bucket index, else log2 of the bucket width in cells (0: default 7)."""
         import torch
         _need(occ, torch.uint8, "occ")
         if occ.dim() != 2:
@@ -190,7 +200,7 @@ class Map:
         self.height, self.width = int(occ.shape[0]), int(occ.shape[1])
         self.theta_bins = int(theta_bins)
         self._alloc = allocator       # keep callbacks alive
-        flags = (FLAG_FULL_MAP if full_map else 0) | (FLAG_STATIC if static else 0)
+        flags = (FLAG_FULL_MAP if full_map else 0) | (FLAG_STATIC if static else 0) | bucket_flags(buckets)
         h = C.c_void_p()
         _check(lib().cddt_create(_ptr(occ), self.width, self.height, self.theta_bins, flags,
                                  C.byref(allocator) if allocator is not None else None,

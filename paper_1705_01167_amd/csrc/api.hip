@@ -75,8 +75,14 @@ void release_all(cddt_map_s* m) {
   release_scratch(m);
   if (m->d_occ) m->alloc.release(m->d_occ);
   if (m->d_slices) m->alloc.release(m->d_slices);
+  if (m->d_bk) m->alloc.release(m->d_bk);
+  if (m->d_row_start) m->alloc.release(m->d_row_start);
+  if (m->d_bk_over) m->alloc.release(m->d_bk_over);
   m->d_occ = nullptr;
   m->d_slices = nullptr;
+  m->d_bk = nullptr;
+  m->d_row_start = nullptr;
+  m->d_bk_over = nullptr;
 }
 
 // Direction table, band ranges and band offsets of every stored slice.
@@ -87,7 +93,8 @@ void slice_tables(cddt_map_s* m) {
   m->row_min.assign(half, 0);
   m->nrows.assign(half, 0);
   m->row_base.assign(half, 0);
-  int64_t base = 0;
+  m->zlo.assign(half, 0);
+  int64_t base = 0, nbk = 1;
   for (int k = 0; k < half; ++k) {
     const double a = 2.0 * M_PI * k / m->n;
     const int64_t c = std::llround(std::cos(a) * 1073741824.0);
@@ -106,8 +113,15 @@ void slice_tables(cddt_map_s* m) {
     m->nrows[k] = (int32_t)(hi - lo + 1);
     m->row_base[k] = (int32_t)base;
     base += hi - lo + 1;
+    // along-slice range of the map rectangle in Q16, with the query's rounding
+    const int64_t wc = ((int64_t)m->w << 16) * c, hs = ((int64_t)m->h << 16) * s;
+    const int64_t zlo = (std::min<int64_t>(0, wc) + std::min<int64_t>(0, hs)) >> 30;
+    const int64_t zhi = (std::max<int64_t>(0, wc) + std::max<int64_t>(0, hs)) >> 30;
+    m->zlo[k] = (int32_t)zlo;
+    if (m->blog2) nbk = std::max<int64_t>(nbk, ((zhi - zlo) >> (16 + m->blog2)) + 1);
   }
   m->rows = base;
+  m->nbk = m->blog2 ? (int32_t)nbk : 0;
   m->k_scale = (float)((double)m->n / (2.0 * M_PI));
 }
 
@@ -172,8 +186,15 @@ cddt_status cddt_create(const uint8_t* occ, int32_t width, int32_t height, int32
     return fail(CDDT_EINVAL, "cddt_create: width and height must be in 1..16384");
   if (theta_bins < 2 || theta_bins > kMaxBins || (theta_bins & 1))
     return fail(CDDT_EINVAL, "cddt_create: theta_bins must be even and in 2..8192");
-  if (flags & ~(uint32_t)(CDDT_FLAG_FULL_MAP | CDDT_FLAG_STATIC))
+  if (flags & ~(uint32_t)(CDDT_FLAG_FULL_MAP | CDDT_FLAG_STATIC | CDDT_FLAG_BUCKETS | CDDT_BUCKET_LOG2(15)))
     return fail(CDDT_EINVAL, "cddt_create: unknown flag bits");
+  int32_t blog2 = (int32_t)((flags >> 8) & 15u);
+  if (!(flags & CDDT_FLAG_BUCKETS) && blog2)
+    return fail(CDDT_EINVAL, "cddt_create: a bucket width needs CDDT_FLAG_BUCKETS");
+  if (flags & CDDT_FLAG_BUCKETS) {
+    if (blog2 == 0) blog2 = kBucketLog2Default;
+    if (blog2 < 4 || blog2 > 10) return fail(CDDT_EINVAL, "cddt_create: bucket width must be 2^4..2^10 cells");
+  }
   if (alloc && (!alloc->alloc || !alloc->free))
     return fail(CDDT_EINVAL, "cddt_create: allocator needs both alloc and free");
   hipStream_t st = (hipStream_t)stream;
@@ -183,6 +204,7 @@ cddt_status cddt_create(const uint8_t* occ, int32_t width, int32_t height, int32
   m->n = theta_bins;
   m->half = theta_bins / 2;
   m->flags = flags;
+  m->blog2 = blog2;
   if (alloc) {
     m->alloc.cb = *alloc;
     m->alloc.custom = true;
@@ -202,10 +224,22 @@ cddt_status cddt_create(const uint8_t* occ, int32_t width, int32_t height, int32
   if ((s = m->alloc.alloc((void**)&m->d_slices, sizeof(SliceDev) * m->half, "slice table")) != CDDT_OK)
     return bail(s);
   std::vector<SliceDev> sl(m->half);
-  for (int k = 0; k < m->half; ++k) sl[k] = SliceDev{m->c[k], m->s[k], m->row_min[k], m->row_base[k]};
+  for (int k = 0; k < m->half; ++k) sl[k] = SliceDev{m->c[k], m->s[k], m->row_base[k] - m->row_min[k], m->zlo[k]};
+  std::vector<int32_t> row_start(m->half + 1);
+  for (int k = 0; k < m->half; ++k) row_start[k] = m->row_base[k];
+  row_start[m->half] = (int32_t)m->rows;
+  if (m->blog2) {
+    const size_t lines = (size_t)m->rows * (size_t)m->nbk;
+    if ((s = m->alloc.alloc((void**)&m->d_bk, lines * 128, "bucket index")) != CDDT_OK) return bail(s);
+    if ((s = m->alloc.alloc((void**)&m->d_row_start, 4 * row_start.size(), "slice band offsets")) != CDDT_OK)
+      return bail(s);
+    if ((s = m->alloc.alloc((void**)&m->d_bk_over, 8, "bucket counter")) != CDDT_OK) return bail(s);
+  }
   hipError_t e = hipMemcpyAsync(m->d_occ, occ, cells, hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(m->d_slices, sl.data(), sizeof(SliceDev) * m->half, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && m->d_row_start)
+    e = hipMemcpyAsync(m->d_row_start, row_start.data(), 4 * row_start.size(), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return bail(fail(CDDT_EDEVICE, std::string("cddt_create: copy failed: ") + hipGetErrorString(e)));
   if ((s = build_structure(m, st)) != CDDT_OK) return bail(s);
   *out_h = m;
@@ -281,8 +315,11 @@ cddt_status cddt_info(cddt_map m, cddt_stats* out_h) {
   s.zero_points = m->zero_points;
   s.capacity = m->capacity;
   s.max_row_len = m->max_row_len;
+  s.bucket_lines = m->d_bk ? m->rows * m->nbk : 0;
+  s.bucket_overflow = m->d_bk ? m->bucket_overflow : 0;
+  s.bucket_log2 = m->d_bk ? m->blog2 : 0;
   s.device_bytes = (int64_t)m->w * m->h + (int64_t)sizeof(SliceDev) * m->half + m->rows * kNodeInts * 4 +
-                   m->capacity * 4;
+                   m->capacity * 4 + s.bucket_lines * 128 + (m->d_bk ? 4 * (m->half + 1) + 8 : 0);
   s.rebuilds = m->rebuilds;
   *out_h = s;
   return CDDT_OK;

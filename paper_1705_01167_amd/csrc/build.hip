@@ -80,13 +80,77 @@ __global__ void k_project(const SliceDev* __restrict__ slices, const uint32_t* _
   const int32_t hi = (int32_t)((yc + hs - 1) >> 31);
   const int32_t z = (int32_t)((i2 * sl.c + j2 * sl.s) >> 15);
   for (int32_t r = lo; r <= hi; ++r) {
-    const int32_t row = sl.row_base + (r - sl.row_min);
+    const int32_t row = sl.row_off + r;
     if (!fill) {
       atomicAdd(&cnt[row], 1u);
     } else {
       uint32_t pos = atomicAdd(&cnt[row], 1u);
       zeros[(uint32_t)hdr[(int64_t)row * kNodeInts] + pos] = z;
     }
+  }
+}
+
+// Bucket index fill: half a wave per bucket line (lane j writes word j).  Line
+// k of the list is bucket k % nbk of band rows_list[k / nbk] (band k / nbk
+// when rows_list is null).  With `partial` the old line is read first so that
+// the overflow counter stays exact.
+__device__ __forceinline__ int32_t first_at_least(const int32_t* __restrict__ keys, int32_t len, int64_t v) {
+  int32_t lo = 0, cnt = len;
+  while (cnt > 0) {
+    const int32_t half = cnt >> 1;
+    if ((int64_t)keys[lo + half] < v) {
+      lo += half + 1;
+      cnt -= half + 1;
+    } else {
+      cnt = half;
+    }
+  }
+  return lo;
+}
+
+__global__ void k_bucket_fill(const int32_t* __restrict__ hdr, const int32_t* __restrict__ zeros,
+                              const SliceDev* __restrict__ slices, const int32_t* __restrict__ row_start,
+                              int32_t half, int32_t shift, int32_t nbk, int32_t* __restrict__ bk,
+                              const uint32_t* __restrict__ rows_list, uint64_t n_lines,
+                              unsigned long long* __restrict__ over, int partial) {
+  const int sub = threadIdx.x & 31;
+  const uint64_t stride = ((uint64_t)gridDim.x * blockDim.x) >> 5;
+  for (uint64_t k = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5; k < n_lines; k += stride) {
+    const uint64_t r = k / (uint64_t)nbk;
+    const int32_t b = (int32_t)(k - r * (uint64_t)nbk);
+    const uint32_t band = rows_list ? rows_list[r] : (uint32_t)r;
+    int32_t lo = 0, cnt = half;  // slice: last row_start <= band
+    while (cnt > 1) {
+      const int32_t h2 = cnt >> 1;
+      if ((uint32_t)row_start[lo + h2] <= band) {
+        lo += h2;
+        cnt -= h2;
+      } else {
+        cnt = h2;
+      }
+    }
+    const int32_t zlo = slices[lo].zlo;
+    const int32_t* node = hdr + (int64_t)band * kNodeInts;
+    const int32_t* keys = zeros + (uint32_t)node[0];
+    const int32_t len = node[1];
+    const int64_t a0 = (int64_t)zlo + ((int64_t)b << shift), a1 = a0 + ((int64_t)1 << shift);
+    const int32_t i0 = first_at_least(keys, len, a0), i1 = first_at_least(keys, len, a1);
+    const int32_t n_in = i1 - i0;
+    int32_t* line = bk + ((int64_t)band * nbk + b) * kLineInts;
+    const int old_over = partial ? (line[0] == kBucketOverflow) : 0;
+    int32_t v;
+    if (n_in > kBucketKeys) {
+      v = sub == 0 ? kBucketOverflow : (sub == 1 ? zlo : 0);
+    } else if (sub == 0) {
+      v = i0 > 0 ? keys[i0 - 1] - zlo : INT_MIN;
+    } else if (sub == 1) {
+      v = i1 < len ? keys[i1] - zlo : INT_MAX;
+    } else {
+      v = sub - 2 < n_in ? keys[i0 + sub - 2] - zlo : INT_MAX;
+    }
+    line[sub] = v;
+    const int now_over = n_in > kBucketKeys ? 1 : 0;
+    if (sub == 0 && now_over != old_over) atomicAdd(over, (unsigned long long)(long long)(now_over - old_over));
   }
 }
 
@@ -425,6 +489,25 @@ cddt_status build_structure(cddt_map_s* m, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(grid_for(R, 4)), dim3(256), 0, st, m->d_hdr, m->d_zeros, R);
   CDDT_HIP(hipGetLastError());
   CDDT_HIP(hipStreamSynchronize(st));
+  if (m->d_bk) return fill_buckets(m, nullptr, R, st);
+  return CDDT_OK;
+}
+
+cddt_status fill_buckets(cddt_map_s* m, const uint32_t* rows_list, int64_t n_rows, hipStream_t st) {
+  if (!m->d_bk || n_rows <= 0) return CDDT_OK;
+  const int partial = rows_list ? 1 : 0;
+  if (!partial) CDDT_HIP(hipMemsetAsync(m->d_bk_over, 0, 8, st));
+  const uint64_t lines = (uint64_t)n_rows * (uint64_t)m->nbk;
+  const uint64_t blocks = std::min<uint64_t>((lines + 7) / 8, 1u << 20);  // 8 lines per 256-thread block
+  hipLaunchKernelGGL(k_bucket_fill, dim3((unsigned)std::max<uint64_t>(blocks, 1)), dim3(256), 0, st,
+                     (const int32_t*)m->d_hdr, (const int32_t*)m->d_zeros, (const SliceDev*)m->d_slices,
+                     (const int32_t*)m->d_row_start, m->half, 16 + m->blog2, m->nbk, m->d_bk, rows_list, lines,
+                     m->d_bk_over, partial);
+  CDDT_HIP(hipGetLastError());
+  unsigned long long over = 0;
+  CDDT_HIP(hipMemcpyAsync(&over, m->d_bk_over, 8, hipMemcpyDeviceToHost, st));
+  CDDT_HIP(hipStreamSynchronize(st));
+  m->bucket_overflow = (int64_t)over;
   return CDDT_OK;
 }
 

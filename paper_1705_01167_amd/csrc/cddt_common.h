@@ -57,7 +57,7 @@ struct cddt_map_s {
   uint32_t flags = 0;
   cddt::Allocator alloc;
   float k_scale = 0.f;
-  std::vector<int32_t> c, s, row_min, nrows, row_base;
+  std::vector<int32_t> c, s, row_min, nrows, row_base, zlo;
   int64_t rows = 0;
   uint8_t* d_occ = nullptr;
   cddt::SliceDev* d_slices = nullptr;
@@ -65,6 +65,12 @@ struct cddt_map_s {
   int32_t* d_zeros = nullptr;    // band regions
   int64_t capacity = 0, zero_points = 0, edge_cells = 0, max_row_len = 0, rebuilds = 0;
   int64_t device_bytes = 0;
+  // bucket index (CDDT_FLAG_BUCKETS): rows * nbk lines of 128 bytes
+  int32_t blog2 = 0, nbk = 0;
+  int32_t* d_bk = nullptr;
+  int32_t* d_row_start = nullptr;          // half + 1 global band offsets
+  unsigned long long* d_bk_over = nullptr;  // overflowing buckets (device counter)
+  int64_t bucket_overflow = 0;
   // update scratch (grown on demand, released with the map)
   cddt::Scratch upd_ops, upd_changed, upd_cand, upd_edits, upd_rec, upd_rowcnt, upd_misc;
   cddt::Scratch upd_slot, upd_touched, upd_grp, upd_tiles;
@@ -75,19 +81,25 @@ struct cddt_map_s {
     m.slices = d_slices;
     m.hdr = d_hdr;
     m.zeros = d_zeros;
+    m.bk = d_bk;
     m.w = w;
     m.h = h;
     m.n = n;
     m.half = half;
     m.k_scale = k_scale;
+    m.bshift = d_bk ? 16 + blog2 : 0;
+    m.nbk = nbk;
     m.pad = 0;
     return m;
   }
 };
 
 namespace cddt {
-// build.hip
+// build.hip.  build_structure also fills the bucket index when the map has
+// one; fill_buckets refreshes the buckets of the listed bands (all bands when
+// rows_list is null) and blocks.
 cddt_status build_structure(cddt_map_s* m, hipStream_t st);
+cddt_status fill_buckets(cddt_map_s* m, const uint32_t* rows_list, int64_t n_rows, hipStream_t st);
 void free_structure(cddt_map_s* m);
 cddt_status refresh_stats(cddt_map_s* m, hipStream_t st);
 // query.hip

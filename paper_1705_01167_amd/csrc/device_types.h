@@ -4,14 +4,18 @@
 
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
 
 namespace cddt {
 
-// One stored slice: direction (2^30 fixed point), lowest band index, and the
-// index of its first band in the global band arrays.
+// One stored slice: direction (2^30 fixed point), the offset that turns a
+// lateral band number into a global band index, and the bucket origin (the
+// lowest along-slice projection of the map rectangle, Q16).
 struct SliceDev {
-  int32_t c, s, row_min, row_base;
+  int32_t c, s;
+  int32_t row_off;  // global band = row_off + (lateral projection >> 46)
+  int32_t zlo;
 };
 
 // Everything a query needs about one map, passed by value to kernels.
@@ -20,8 +24,11 @@ struct MapDev {
   const SliceDev* slices;    // n/2 entries
   const int32_t* hdr;        // per band: a 128-byte header node (band_layout.h)
   const int32_t* zeros;      // band regions: keys (Q16, ascending) and sample levels
+  const int32_t* bk;         // bucket index lines (nullptr: no bucket index)
   int32_t w, h, n, half;
   float k_scale;             // (float)(n / (2 pi))
+  int32_t bshift;            // bucket width 2^bshift in Q16 units
+  int32_t nbk;               // buckets per band
   int32_t pad;
 };
 
@@ -61,6 +68,13 @@ __device__ __forceinline__ bool edge_cell(const uint8_t* __restrict__ occ, int w
 constexpr int kMaxSide = 16384;
 constexpr int kMaxBins = 8192;
 constexpr int kMaxRays = 1024;
+// Bucket index line: [0] last key before the bucket (INT_MIN: none), [1] first
+// key after it (INT_MAX: none), [2..31] its keys ascending, INT_MAX padded; all
+// relative to the slice's zlo.  An overflowing bucket holds kBucketOverflow
+// in [0] and zlo in [1].
+constexpr int kBucketKeys = 30;
+constexpr int32_t kBucketOverflow = INT_MIN + 1;
+constexpr int kBucketLog2Default = 7;
 // Bytes of device memory holding the persistent batched kernel's tile counters.
 constexpr size_t kBatchCounterBytes = 2048;
 

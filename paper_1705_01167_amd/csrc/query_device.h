@@ -89,6 +89,8 @@ __device__ __forceinline__ int32_t range_of(int64_t d, int32_t max_range) {
 }
 
 // Where a valid query lands: along-ray coordinate and global band index.
+// With a bucket index the coordinate is taken relative to the slice's bucket
+// origin (the keys of the bucket lines are stored the same way).
 struct Landing {
   int32_t xq;
   int32_t row;
@@ -96,12 +98,11 @@ struct Landing {
 
 __device__ __forceinline__ Landing land(const MapDev& m, int32_t slice, int32_t xf, int32_t yf) {
   const int4 sv = ldg4(reinterpret_cast<const int4*>(m.slices + slice));
-  const SliceDev sl{sv.x, sv.y, sv.z, sv.w};
-  int64_t along = (int64_t)xf * sl.c + (int64_t)yf * sl.s;
-  int64_t lat = (int64_t)yf * sl.c - (int64_t)xf * sl.s;
+  int64_t along = (int64_t)xf * sv.x + (int64_t)yf * sv.y;
+  int64_t lat = (int64_t)yf * sv.x - (int64_t)xf * sv.y;
   Landing l;
-  l.xq = (int32_t)(along >> 30);
-  l.row = sl.row_base + ((int32_t)(lat >> 46) - sl.row_min);
+  l.xq = (int32_t)(along >> 30) - (m.bk ? sv.w : 0);
+  l.row = sv.z + (int32_t)(lat >> 46);
   return l;
 }
 
@@ -332,7 +333,7 @@ __device__ __forceinline__ void scan_line(const Line32& L, int32_t x, int32_t ca
 // Band search by one lane: the header line, then one line per level below the
 // top.  Same results as wave_search; no cross-lane traffic, and a wave keeps up
 // to 64 independent lines in flight.  Lanes without a query return max_range.
-__device__ __forceinline__ void lane_search(const MapDev& m, bool want, int32_t row, int32_t x, int32_t max_range,
+__device__ __forceinline__ void tree_search(const MapDev& m, bool want, int32_t row, int32_t x, int32_t max_range,
                                             int32_t& r_succ, int32_t& r_pred) {
   r_succ = max_range;
   r_pred = max_range;
@@ -361,12 +362,84 @@ __device__ __forceinline__ void lane_search(const MapDev& m, bool want, int32_t 
   }
 }
 
+// Bucket-index search by one lane: the bucket line of (band, x) gives the
+// nearest key above x (within the bucket, else the carried next key) and the
+// nearest key below x (within the bucket, else the carried previous key);
+// keys equal to x count on neither side, as in tree_search.  x is relative to
+// the slice's bucket origin.  An overflowing bucket defers to tree_search.
+__device__ __forceinline__ int32_t bucket_of(const MapDev& m, int32_t x) {
+  const int32_t b = x >> m.bshift;
+  return b < 0 ? 0 : (b >= m.nbk ? m.nbk - 1 : b);
+}
+
+__device__ __forceinline__ void scan_bucket(const Line32& L, int32_t x, int32_t max_range, int32_t& r_succ,
+                                            int32_t& r_pred) {
+  int32_t prv = L.e[0], nxt = INT_MAX;
+#pragma unroll
+  for (int i = 2; i < 32; ++i) prv = L.e[i] < x ? L.e[i] : prv;   // ascending: the last one below x
+#pragma unroll
+  for (int i = 31; i >= 2; --i) nxt = L.e[i] > x ? L.e[i] : nxt;  // descending: the first one above x
+  nxt = nxt < L.e[1] ? nxt : L.e[1];
+  r_succ = nxt != INT_MAX ? range_of((int64_t)nxt - x, max_range) : max_range;
+  r_pred = prv != INT_MIN ? range_of((int64_t)x - prv, max_range) : max_range;
+}
+
+__device__ __forceinline__ void bucket_search(const MapDev& m, bool want, int32_t row, int32_t x, int32_t max_range,
+                                              int32_t& r_succ, int32_t& r_pred) {
+  r_succ = max_range;
+  r_pred = max_range;
+  if (!want) return;
+  const Line32 L = load_line(m.bk + ((int64_t)row * m.nbk + bucket_of(m, x)) * kLineInts);
+  if (L.e[0] == kBucketOverflow) {
+    tree_search(m, true, row, x + L.e[1], max_range, r_succ, r_pred);
+    return;
+  }
+  scan_bucket(L, x, max_range, r_succ, r_pred);
+}
+
+// Band search by one lane (bucket index when the map has one, else the
+// band's search lines).
+__device__ __forceinline__ void lane_search(const MapDev& m, bool want, int32_t row, int32_t x, int32_t max_range,
+                                            int32_t& r_succ, int32_t& r_pred) {
+  if (m.bk)
+    bucket_search(m, want, row, x, max_range, r_succ, r_pred);
+  else
+    tree_search(m, want, row, x, max_range, r_succ, r_pred);
+}
+
+// Two bucket searches by one lane, both lines in flight together.
+__device__ __forceinline__ void bucket_search2(const MapDev& m, bool wa, int32_t ra, int32_t xa, bool wb, int32_t rb,
+                                               int32_t xb, int32_t max_range, int32_t& sa, int32_t& pa, int32_t& sb,
+                                               int32_t& pb) {
+  sa = pa = sb = pb = max_range;
+  if (!wa && !wb) return;
+  Line32 A, B;
+  if (wa) A = load_line(m.bk + ((int64_t)ra * m.nbk + bucket_of(m, xa)) * kLineInts);
+  if (wb) B = load_line(m.bk + ((int64_t)rb * m.nbk + bucket_of(m, xb)) * kLineInts);
+  if (wa) {
+    if (A.e[0] == kBucketOverflow)
+      tree_search(m, true, ra, xa + A.e[1], max_range, sa, pa);
+    else
+      scan_bucket(A, xa, max_range, sa, pa);
+  }
+  if (wb) {
+    if (B.e[0] == kBucketOverflow)
+      tree_search(m, true, rb, xb + B.e[1], max_range, sb, pb);
+    else
+      scan_bucket(B, xb, max_range, sb, pb);
+  }
+}
+
 // Two independent band searches by one lane, their line requests issued side
 // by side (the second search's lines are in flight while the first's are
 // scanned).  Same results as two lane_search calls.
 __device__ __forceinline__ void lane_search2(const MapDev& m, bool wa, int32_t ra, int32_t xa, bool wb, int32_t rb,
                                              int32_t xb, int32_t max_range, int32_t& sa, int32_t& pa, int32_t& sb,
                                              int32_t& pb) {
+  if (m.bk) {
+    bucket_search2(m, wa, ra, xa, wb, rb, xb, max_range, sa, pa, sb, pb);
+    return;
+  }
   sa = pa = sb = pb = max_range;
   if (!wa && !wb) return;
   Line32 A, B;
@@ -422,14 +495,19 @@ __device__ __forceinline__ void lane_search2(const MapDev& m, bool wa, int32_t r
 }
 
 // Search strategy: K = 0 one lane per search, K >= 1 eight lanes per search
-// with K searches per group in flight.
+// with K searches per group in flight (maps with a bucket index always search
+// one lane per bucket line).
 template <int K>
 __device__ __forceinline__ void band_search(const MapDev& m, bool want, int32_t row, int32_t xq, int32_t max_range,
                                             int32_t& r_succ, int32_t& r_pred) {
-  if constexpr (K == 0)
+  if constexpr (K == 0) {
     lane_search(m, want, row, xq, max_range, r_succ, r_pred);
-  else
-    wave_search<K>(m, want, row, xq, max_range, r_succ, r_pred);
+  } else {
+    if (m.bk)
+      bucket_search(m, want, row, xq, max_range, r_succ, r_pred);
+    else
+      wave_search<K>(m, want, row, xq, max_range, r_succ, r_pred);
+  }
 }
 
 // Plain casts for up to 64 rays, one per lane (Sec. IV-B).  All lanes call.

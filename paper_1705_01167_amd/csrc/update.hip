@@ -128,7 +128,7 @@ __global__ void k_records(const SliceDev* __restrict__ slices, const int2* __res
   const uint32_t base = atomicAdd(&ctr->records, (uint32_t)(hi - lo + 1));
   for (int32_t r = lo; r <= hi; ++r) {
     Rec q;
-    q.row = (uint32_t)(sl.row_base + (r - sl.row_min)) | rm;
+    q.row = (uint32_t)(sl.row_off + r) | rm;
     q.z = z;
     rec[base + (uint32_t)(r - lo)] = q;
   }
@@ -432,6 +432,8 @@ cddt_status apply_update(cddt_map_s* m, const int32_t* xs_h, const int32_t* ys_h
     if (hc.overflow) {  // some band ran out of slack: re-lay the structure from the new grid
       CDDT_TRY(build_structure(m, st));
       ++m->rebuilds;
+    } else {
+      CDDT_TRY(fill_buckets(m, touched, (int64_t)hc.touched, st));  // buckets of the edited bands
     }
   }
   return refresh_stats(m, st);

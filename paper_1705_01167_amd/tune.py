@@ -28,9 +28,10 @@ def cache_path() -> str:
                           os.path.join(os.path.expanduser("~"), ".cache", "cddt", "tuning.json"))
 
 
-def signature(n_filters: int, total_particles: int, theta_bins, device_name: str) -> str:
+def signature(n_filters: int, total_particles: int, theta_bins, device_name: str, buckets=None) -> str:
     bucket = int(round(math.log2(max(1, total_particles))))
-    return f"v6|{device_name}|f{n_filters}|p2^{bucket}|n{'-'.join(map(str, sorted(set(theta_bins))))}"
+    bk = "none" if buckets is None else str(buckets)
+    return f"v7|{device_name}|f{n_filters}|p2^{bucket}|n{'-'.join(map(str, sorted(set(theta_bins))))}|b{bk}"
 
 
 def _load() -> dict:

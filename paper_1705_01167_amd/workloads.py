@@ -154,11 +154,13 @@ def ray_offsets(n_rays: int = 61, fov: float = 1.5 * math.pi) -> np.ndarray:
 
 
 def beam_params(rng: np.random.Generator) -> dict:
+    """Mixture weights (hit, short, max, random) summing to 1 with a random floor of at least 0.02."""
     w_hit = rng.uniform(0.6, 0.8)
     w_short = rng.uniform(0.05, 0.15)
     w_max = rng.uniform(0.02, 0.08)
-    w_rand = 1.0 - w_hit - w_short - w_max
-    return dict(w_hit=w_hit, w_short=w_short, w_max=w_max, w_rand=w_rand,
+    w_rand = max(1.0 - w_hit - w_short - w_max, 0.02)
+    tot = w_hit + w_short + w_max + w_rand
+    return dict(w_hit=w_hit / tot, w_short=w_short / tot, w_max=w_max / tot, w_rand=w_rand / tot,
                 sigma=rng.uniform(4.0, 10.0), lam=rng.uniform(0.005, 0.05))
 
 

@@ -49,6 +49,11 @@ def test_validation_needs_no_gpu():
     assert L.cddt_create(occ, 5, 5, 8192 + 2, 0, None, None, C.byref(out)) == cddt.EINVAL
     assert L.cddt_create(occ, 5, 16385, 8, 0, None, None, C.byref(out)) == cddt.EINVAL
     assert L.cddt_create(occ, 5, 5, 8, 1 << 7, None, None, C.byref(out)) == cddt.EINVAL
+    # bucket width without the bucket flag, and widths outside 2^4..2^10 cells
+    assert L.cddt_create(occ, 5, 5, 8, cddt.bucket_flags(7) & ~cddt.FLAG_BUCKETS, None, None,
+                         C.byref(out)) == cddt.EINVAL
+    assert L.cddt_create(occ, 5, 5, 8, cddt.bucket_flags(3), None, None, C.byref(out)) == cddt.EINVAL
+    assert L.cddt_create(occ, 5, 5, 8, cddt.bucket_flags(11), None, None, C.byref(out)) == cddt.EINVAL
     assert L.cddt_create(None, 5, 5, 8, 0, None, None, C.byref(out)) == cddt.EINVAL
     assert not out.value
     assert L.cddt_cast(None, None, None, None, 1, 5, None, None) == cddt.EINVAL

@@ -94,6 +94,14 @@ def test_update_noop_and_same_value(oracle_ref):
 # ---------------------------------------------------------------------------
 # Sensor model
 # ---------------------------------------------------------------------------
+def test_beam_params_are_a_mixture():
+    """Every draw is a proper mixture (the random floor never goes negative)."""
+    for seed in range(500):
+        p = wl.beam_params(wl.rng_for(204, seed))
+        w = [p["w_hit"], p["w_short"], p["w_max"], p["w_rand"]]
+        assert min(w) > 0 and abs(sum(w) - 1.0) < 1e-12 and p["w_rand"] >= 0.019
+
+
 @pytest.mark.parametrize("seed", range(3))
 def test_beam_table_is_a_distribution(seed):
     p = wl.beam_params(wl.rng_for(203, seed))
