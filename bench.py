@@ -399,7 +399,7 @@ SERVE_RATES = (10000, 25000, 50000, 100000, 200000, 300000, 400000, 500000)   # 
 SERVE_RATES_SUMMARY = (50000, 200000)
 
 
-def build_serving():
+def build_serving(buckets):
     import torch
     from paper_1705_01167_amd import cddt
     from paper_1705_01167_amd import workloads as wl
@@ -409,7 +409,7 @@ def build_serving():
     for i, side in enumerate(SERVE_SIDES):
         n = int(wl.THETA_CHOICES[int(rng.integers(0, 3))])
         occ = wl.building_map(wl.rng_for(wl.SERVING, wl.S_MAP, i), side, side)
-        maps.append(cddt.Map(t_dev(occ), n, buckets=BUCKETS))
+        maps.append(cddt.Map(t_dev(occ), n, buckets=buckets))
         offs.append(off_h)
         tabs.append(t_dev(wl.beam_table(MAX_RANGE, wl.beam_params(wl.rng_for(wl.SERVING, wl.S_TABLE, i)))))
         pools.append(wl.free_poses(wl.rng_for(wl.SERVING, wl.S_POSES, i), occ, 20000))
@@ -457,7 +457,9 @@ def serve_at(srv, reqs, rate: float | None, seed: int):
 
 def run_serving(args, summary: bool = False) -> dict:
     from paper_1705_01167_amd import cddt
-    maps, offs, tabs, pools, obs = build_serving()
+    # the serving maps have no bucket index unless one is asked for explicitly
+    buckets = None if args.buckets.lower() == "auto" else BUCKETS
+    maps, offs, tabs, pools, obs = build_serving(buckets)
     srv = cddt.Server(maps, offs, tabs, [MAX_RANGE] * len(maps), budget_bytes=args.serve_budget,
                       n_lanes=args.serve_lanes, max_batch=args.serve_batch)
     warm = make_requests(500, 0, pools, obs)
@@ -479,6 +481,7 @@ def run_serving(args, summary: bool = False) -> dict:
     res = {"burst_capacity_rps": capacity, "burst_capacity_rays_per_s": cap["rays_per_s"], "points": points,
            "stats": st, "config": {"maps": list(SERVE_SIDES), "theta_bins": [m.theta_bins for m in maps],
                                    "robots": 256, "request_particles": "log-uniform 17..1639",
+                                   "bucket_log2": buckets,
                                    "budget_bytes": args.serve_budget, "lanes": args.serve_lanes,
                                    "max_batch": args.serve_batch}}
     return res
@@ -504,8 +507,10 @@ def main():
     ap.add_argument("--workload", default="batched",
                     choices=["batched", "small", "floor", "updates", "serving", "probe"])
     ap.add_argument("--filters", type=int, default=64)
-    ap.add_argument("--buckets", type=str, default="7",
-                    help="log2 bucket width in cells of the maps' bucket index, or 'none' for no index")
+    ap.add_argument("--buckets", type=str, default="auto",
+                    help="log2 bucket width in cells of the maps' bucket index, 'none' for no index, or 'auto': "
+                         "7 for the batched and floor workloads, none for small, updates and serving (measured "
+                         "faster there: their band headers stay in cache, or the index costs more to update)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving summary")
     ap.add_argument("--no-probe", action="store_true", help="skip the gather-bandwidth probe")
@@ -523,7 +528,10 @@ def main():
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
     global BUCKETS
-    BUCKETS = None if args.buckets.lower() == "none" else int(args.buckets)
+    if args.buckets.lower() == "auto":
+        BUCKETS = None if args.workload in ("small", "updates", "serving") else 7
+    else:
+        BUCKETS = None if args.buckets.lower() == "none" else int(args.buckets)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return

@@ -90,10 +90,11 @@ __global__ void k_project(const SliceDev* __restrict__ slices, const uint32_t* _
   }
 }
 
-// Bucket index fill: half a wave per bucket line (lane j writes word j).  Line
-// k of the list is bucket k % nbk of band rows_list[k / nbk] (band k / nbk
-// when rows_list is null).  With `partial` the old line is read first so that
-// the overflow counter stays exact.
+// Bucket index fill: one wave per band, one lane per bucket (64 buckets per
+// pass), each lane finding its bucket's key range by two binary searches over
+// the band's sorted keys and writing its whole line.  Band t of the list is
+// rows_list[t] (band t when rows_list is null).  With `partial` the old line
+// is read first so that the overflow counter stays exact.
 __device__ __forceinline__ int32_t first_at_least(const int32_t* __restrict__ keys, int32_t len, int64_t v) {
   int32_t lo = 0, cnt = len;
   while (cnt > 0) {
@@ -111,14 +112,12 @@ __device__ __forceinline__ int32_t first_at_least(const int32_t* __restrict__ ke
 __global__ void k_bucket_fill(const int32_t* __restrict__ hdr, const int32_t* __restrict__ zeros,
                               const SliceDev* __restrict__ slices, const int32_t* __restrict__ row_start,
                               int32_t half, int32_t shift, int32_t nbk, int32_t* __restrict__ bk,
-                              const uint32_t* __restrict__ rows_list, uint64_t n_lines,
+                              const uint32_t* __restrict__ rows_list, uint64_t n_bands,
                               unsigned long long* __restrict__ over, int partial) {
-  const int sub = threadIdx.x & 31;
-  const uint64_t stride = ((uint64_t)gridDim.x * blockDim.x) >> 5;
-  for (uint64_t k = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5; k < n_lines; k += stride) {
-    const uint64_t r = k / (uint64_t)nbk;
-    const int32_t b = (int32_t)(k - r * (uint64_t)nbk);
-    const uint32_t band = rows_list ? rows_list[r] : (uint32_t)r;
+  const int lane = threadIdx.x & 63;
+  const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t t = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < n_bands; t += n_waves) {
+    const uint32_t band = rows_list ? rows_list[t] : (uint32_t)t;
     int32_t lo = 0, cnt = half;  // slice: last row_start <= band
     while (cnt > 1) {
       const int32_t h2 = cnt >> 1;
@@ -133,24 +132,31 @@ __global__ void k_bucket_fill(const int32_t* __restrict__ hdr, const int32_t* __
     const int32_t* node = hdr + (int64_t)band * kNodeInts;
     const int32_t* keys = zeros + (uint32_t)node[0];
     const int32_t len = node[1];
-    const int64_t a0 = (int64_t)zlo + ((int64_t)b << shift), a1 = a0 + ((int64_t)1 << shift);
-    const int32_t i0 = first_at_least(keys, len, a0), i1 = first_at_least(keys, len, a1);
-    const int32_t n_in = i1 - i0;
-    int32_t* line = bk + ((int64_t)band * nbk + b) * kLineInts;
-    const int old_over = partial ? (line[0] == kBucketOverflow) : 0;
-    int32_t v;
-    if (n_in > kBucketKeys) {
-      v = sub == 0 ? kBucketOverflow : (sub == 1 ? zlo : 0);
-    } else if (sub == 0) {
-      v = i0 > 0 ? keys[i0 - 1] - zlo : INT_MIN;
-    } else if (sub == 1) {
-      v = i1 < len ? keys[i1] - zlo : INT_MAX;
-    } else {
-      v = sub - 2 < n_in ? keys[i0 + sub - 2] - zlo : INT_MAX;
+    int over_delta = 0;
+    for (int32_t b0 = 0; b0 < nbk; b0 += 64) {
+      const int32_t b = b0 + lane;
+      if (b >= nbk) continue;
+      const int64_t a0 = (int64_t)zlo + ((int64_t)b << shift), a1 = a0 + ((int64_t)1 << shift);
+      const int32_t i0 = first_at_least(keys, len, a0), i1 = first_at_least(keys, len, a1);
+      const int32_t n_in = i1 - i0;
+      int4* line = reinterpret_cast<int4*>(bk + ((int64_t)band * nbk + b) * kLineInts);
+      const int old_over = partial ? (reinterpret_cast<const int32_t*>(line)[0] == kBucketOverflow) : 0;
+      if (n_in > kBucketKeys) {
+        line[0] = make_int4(kBucketOverflow, zlo, 0, 0);
+#pragma unroll
+        for (int q = 1; q < 8; ++q) line[q] = make_int4(0, 0, 0, 0);
+      } else {
+        int32_t e[32];
+        e[0] = i0 > 0 ? keys[i0 - 1] - zlo : INT_MIN;
+        e[1] = i1 < len ? keys[i1] - zlo : INT_MAX;
+#pragma unroll
+        for (int k = 0; k < kBucketKeys; ++k) e[2 + k] = k < n_in ? keys[i0 + k] - zlo : INT_MAX;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) line[q] = make_int4(e[4 * q], e[4 * q + 1], e[4 * q + 2], e[4 * q + 3]);
+      }
+      over_delta += (n_in > kBucketKeys ? 1 : 0) - old_over;
     }
-    line[sub] = v;
-    const int now_over = n_in > kBucketKeys ? 1 : 0;
-    if (sub == 0 && now_over != old_over) atomicAdd(over, (unsigned long long)(long long)(now_over - old_over));
+    if (over_delta != 0) atomicAdd(over, (unsigned long long)(long long)over_delta);
   }
 }
 
@@ -497,12 +503,11 @@ cddt_status fill_buckets(cddt_map_s* m, const uint32_t* rows_list, int64_t n_row
   if (!m->d_bk || n_rows <= 0) return CDDT_OK;
   const int partial = rows_list ? 1 : 0;
   if (!partial) CDDT_HIP(hipMemsetAsync(m->d_bk_over, 0, 8, st));
-  const uint64_t lines = (uint64_t)n_rows * (uint64_t)m->nbk;
-  const uint64_t blocks = std::min<uint64_t>((lines + 7) / 8, 1u << 20);  // 8 lines per 256-thread block
+  const uint64_t blocks = std::min<uint64_t>(((uint64_t)n_rows + 3) / 4, 1u << 16);  // 4 bands per block
   hipLaunchKernelGGL(k_bucket_fill, dim3((unsigned)std::max<uint64_t>(blocks, 1)), dim3(256), 0, st,
                      (const int32_t*)m->d_hdr, (const int32_t*)m->d_zeros, (const SliceDev*)m->d_slices,
-                     (const int32_t*)m->d_row_start, m->half, 16 + m->blog2, m->nbk, m->d_bk, rows_list, lines,
-                     m->d_bk_over, partial);
+                     (const int32_t*)m->d_row_start, m->half, 16 + m->blog2, m->nbk, m->d_bk, rows_list,
+                     (uint64_t)n_rows, m->d_bk_over, partial);
   CDDT_HIP(hipGetLastError());
   unsigned long long over = 0;
   CDDT_HIP(hipMemcpyAsync(&over, m->d_bk_over, 8, hipMemcpyDeviceToHost, st));
