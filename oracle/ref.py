@@ -15,13 +15,20 @@ SRC = os.path.join(HERE, "cddt_ref.cpp")
 LIB = os.path.join(HERE, "libcddt_ref.so")
 
 
+SRC_MCL = os.path.join(HERE, "mcl_ref.c")
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with the host compiler (no GPU code involved)."""
+    """Compile the oracle with the host compilers (no GPU code involved)."""
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
+        obj = LIB + ".mcl.o"
+        subprocess.run(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fPIC", "-c", SRC_MCL, "-o", obj],
+                       check=True)
         cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-pthread",
-               SRC, "-o", tmp]
+               SRC, obj, "-o", tmp]
         subprocess.run(cmd, check=True)
+        os.remove(obj)
         os.replace(tmp, LIB)
     return LIB
 
@@ -49,6 +56,14 @@ def lib():
         L.ref_weight.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, vp, i32, vp, vp, i32]
         L.ref_update.restype = i32
         L.ref_update.argtypes = [vp, vp, vp, vp, i64]
+        L.ref_det_exp_neg.restype = C.c_double
+        L.ref_det_exp_neg.argtypes = [C.c_double]
+        L.ref_det_sincos.argtypes = [C.c_double, vp, vp]
+        L.ref_motion.argtypes = [vp, vp, vp, i64, C.c_float, C.c_float, C.c_float, vp, vp, vp, vp, vp, vp]
+        L.ref_resample.restype = i32
+        L.ref_resample.argtypes = [vp, i64, C.c_uint32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ref_resample_weights.restype = C.c_uint64
+        L.ref_resample_weights.argtypes = [vp, i64, vp]
         _lib = L
     return _lib
 
@@ -147,3 +162,50 @@ class RefCDDT:
         for x, y, v in zip(xs.tolist(), ys.tolist(), vals.tolist()):
             self.occ[y, x] = 1 if v else 0
         return r
+
+
+# ---------------------------------------------------------------------------
+# Particle-filter steps around the sensor model (mcl_ref.c)
+# ---------------------------------------------------------------------------
+def det_exp_neg(x: float) -> float:
+    return float(lib().ref_det_exp_neg(float(x)))
+
+
+def det_sincos(a: float):
+    s, c = C.c_double(), C.c_double()
+    lib().ref_det_sincos(float(a), C.byref(s), C.byref(c))
+    return s.value, c.value
+
+
+def motion(px, py, pth, odom, ex, ey, eth):
+    """Move every particle by the robot-frame odometry (dx, dy, dth) plus the given noise."""
+    a = [np.ascontiguousarray(v, np.float32) for v in (px, py, pth, ex, ey, eth)]
+    n = a[0].size
+    out = [np.empty(n, np.float32) for _ in range(3)]
+    dx, dy, dth = (float(v) for v in odom)
+    lib().ref_motion(_p(a[0]), _p(a[1]), _p(a[2]), n, dx, dy, dth, _p(a[3]), _p(a[4]), _p(a[5]),
+                     _p(out[0]), _p(out[1]), _p(out[2]))
+    return tuple(out)
+
+
+def resample_weights(logw):
+    """Integer weights q_k and their total T."""
+    lw = np.ascontiguousarray(logw, np.float32)
+    q = np.zeros(max(lw.size, 1), np.uint64)
+    total = int(lib().ref_resample_weights(_p(lw), lw.size, _p(q)))
+    return q[:lw.size], total
+
+
+def resample(logw, u: int, px, py, pth):
+    """Systematic resampling: (source index per output, gathered px, py, pth)."""
+    lw = np.ascontiguousarray(logw, np.float32)
+    n = lw.size
+    a = [np.ascontiguousarray(v, np.float32) for v in (px, py, pth)]
+    idx = np.full(n, -1, np.int32)
+    out = [np.empty(n, np.float32) for _ in range(3)]
+    q = np.zeros(max(n, 1), np.uint64)
+    r = lib().ref_resample(_p(lw), n, int(u) & 0xffffffff, _p(a[0]), _p(a[1]), _p(a[2]), _p(idx),
+                           _p(out[0]), _p(out[1]), _p(out[2]), _p(q))
+    if r != 0:
+        raise ValueError("resample: n must be in 0..2^20")
+    return idx, out[0], out[1], out[2]
