@@ -251,6 +251,58 @@ cddt_status cddt_plan_time(cddt_plan p, const cddt_tuning* tuning_h, int32_t rep
 cddt_status cddt_plan_run_plain(cddt_plan p, void* stream);
 cddt_status cddt_plan_destroy(cddt_plan p);
 
+/* ---------------------------------------------------------------------------
+ * The particle-filter steps around the sensor model.  The paper's Monte
+ * Carlo localization update moves every particle by the odometry, weighs it
+ * with the sensor model and resamples by the weights (Sec. I, Sec. VI) but
+ * gives no formulas for the first and last step; the library fixes them:
+ *
+ *   motion     odometry (dx, dy, dtheta) in the robot frame, noise drawn by
+ *              the caller; in double precision
+ *                x' = ((x + cos(th) dx) - sin(th) dy) + ex
+ *                y' = ((y + sin(th) dx) + cos(th) dy) + ey
+ *                th' = (th + dtheta) + eth, wrapped to [-pi, pi)
+ *              each rounded once to float32;
+ *   resample   systematic resampling with one uniform draw u (32 bits): the
+ *              integer weights q_k = floor(2^20 exp(l_k - max finite l))
+ *              (0 for a non-finite l_k; all 1 if no l_k is finite), T = sum,
+ *              s = floor((u >> 12) T / 2^20); particle k fills the output
+ *              slots [a_k, a_(k+1)), a_k = ceil((n C_k - s) / T) clamped at 0,
+ *              C_k = q_0 + ... + q_(k-1).  Copies keep source order.
+ *
+ * exp, sin and cos are evaluated by range reduction and Taylor series in a
+ * fixed order of double operations, so results are reproducible bit for bit.
+ * ------------------------------------------------------------------------- */
+
+/* Move n particles in place.  px, py, ptheta: device float32[n];
+ * noise: device float32[3n] = (ex[n], ey[n], eth[n]).  Asynchronous.
+ * Errors: EINVAL. */
+cddt_status cddt_motion(float* px, float* py, float* ptheta, int64_t n, float dx, float dy, float dtheta,
+                        const float* noise, void* stream);
+
+/* Systematic resampling of one filter (n <= 2^20).  logw: device float32[n];
+ * px/py/ptheta in and *_out: device float32[n], not overlapping;
+ * idx_out: device int32[n], the source particle of every output.  One
+ * workgroup; asynchronous.  Errors: EINVAL. */
+cddt_status cddt_resample(const float* logw, int64_t n, uint32_t u, const float* px, const float* py,
+                          const float* ptheta, float* px_out, float* py_out, float* ptheta_out, int32_t* idx_out,
+                          void* stream);
+
+/* A whole filter step for every filter of a plan: motion, the batched
+ * log-weights (written to each filter's logw_out) and resampling of each
+ * filter's poses in place (every filter n <= 2^20).  The step's inputs are
+ * device arrays the caller rewrites between steps: odom float32[3 F]
+ * ((dx, dy, dtheta) per filter), u uint32[F], noise float32[3 P] (filter f's
+ * (ex, ey, eth) blocks of n_f each, at 3 * (n_0 + ... + n_(f-1))), P = total
+ * particles.  set_mcl stores the pointers (and allocates the plan's
+ * resampling scratch on first use: 16 bytes per particle); it drops any
+ * captured graph.  run_mcl enqueues the step; capture_mcl captures it into
+ * the plan's graph (replayed with cddt_plan_replay).  Errors: EINVAL,
+ * ENOMEM. */
+cddt_status cddt_plan_set_mcl(cddt_plan p, const float* odom, const uint32_t* u, const float* noise);
+cddt_status cddt_plan_run_mcl(cddt_plan p, void* stream);
+cddt_status cddt_plan_capture_mcl(cddt_plan p, void* stream);
+
 /* Number of compute units of the current device (for tuning spaces). */
 int32_t cddt_device_cus(void);
 

@@ -113,6 +113,11 @@ SIGNATURES = {
     "cddt_server_create": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, C.POINTER(ServerConfig), C.POINTER(_vp)]),
     "cddt_server_submit": (_i32, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, C.POINTER(_i64)]),
     "cddt_server_replay": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cddt_motion": (_i32, [_vp, _vp, _vp, _i64, C.c_float, C.c_float, C.c_float, _vp, _vp]),
+    "cddt_resample": (_i32, [_vp, _i64, C.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cddt_plan_set_mcl": (_i32, [_vp, _vp, _vp, _vp]),
+    "cddt_plan_run_mcl": (_i32, [_vp, _vp]),
+    "cddt_plan_capture_mcl": (_i32, [_vp, _vp]),
     "cddt_server_poll": (_i32, [_vp, _i64, _vp, C.POINTER(_i32)]),
     "cddt_server_wait": (_i32, [_vp, _i64, _vp]),
     "cddt_server_times": (_i32, [_vp, _i64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -315,6 +320,24 @@ def make_filter(m: Map, px, py, pth, offsets, obs, log_table, max_range: int, lo
     return f
 
 
+def motion(px, py, pth, odom, noise, stream=None):
+    """Move particles in place (cddt_motion): odom = (dx, dy, dtheta), noise device float32[3n]."""
+    n = px.numel()
+    _check(lib().cddt_motion(_ptr(px), _ptr(py), _ptr(pth), n, float(odom[0]), float(odom[1]), float(odom[2]),
+                             _ptr(noise), _stream(stream)))
+
+
+def resample(logw, u: int, px, py, pth, stream=None):
+    """Systematic resampling (cddt_resample): returns (idx, px', py', pth') as new device tensors."""
+    import torch
+    n = logw.numel()
+    outs = [torch.empty_like(px), torch.empty_like(py), torch.empty_like(pth)]
+    idx = torch.empty(n, dtype=torch.int32, device=logw.device)
+    _check(lib().cddt_resample(_ptr(logw), n, int(u) & 0xffffffff, _ptr(px), _ptr(py), _ptr(pth),
+                               _ptr(outs[0]), _ptr(outs[1]), _ptr(outs[2]), _ptr(idx), _stream(stream)))
+    return (idx, *outs)
+
+
 class Plan:
     """Many filters in one persistent launch (cddt_plan_*)."""
 
@@ -361,6 +384,18 @@ class Plan:
 
     def replay(self, stream=None):
         _check(lib().cddt_plan_replay(self.handle, _stream(stream)))
+
+    # -- the whole particle-filter step (motion, weights, resampling) --------
+    def set_mcl(self, odom, u, noise):
+        """odom: device float32[3F]; u: device int32/uint32[F]; noise: device float32[3P] (kept alive here)."""
+        self._mcl = (odom, u, noise)
+        _check(lib().cddt_plan_set_mcl(self.handle, _ptr(odom), _ptr(u), _ptr(noise)))
+
+    def run_mcl(self, stream=None):
+        _check(lib().cddt_plan_run_mcl(self.handle, _stream(stream)))
+
+    def capture_mcl(self, stream):
+        _check(lib().cddt_plan_capture_mcl(self.handle, _stream(stream)))
 
     def time(self, tuning, reps: int = 5, stream=None) -> float:
         t = Tuning(*tuning)

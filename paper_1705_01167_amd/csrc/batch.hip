@@ -28,6 +28,14 @@ struct cddt_plan_s {
   int32_t cus = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // particle-filter step (motion, weights, resampling)
+  int64_t total_particles = 0;
+  int64_t* d_ppre = nullptr;   // n_filters + 1 particle offsets
+  float* d_stage = nullptr;    // 3 * total_particles pose scratch for resampling
+  int32_t* d_idx = nullptr;    // total_particles source indices
+  const float* mcl_odom = nullptr;
+  const uint32_t* mcl_u = nullptr;
+  const float* mcl_noise = nullptr;
 };
 
 namespace cddt {
@@ -111,6 +119,32 @@ cddt_status launch_plan(cddt_plan_s* p, hipStream_t st) {
                       p->d_counter, p->cus, st);
 }
 
+void drop_graph(cddt_plan_s* p);
+
+cddt_status launch_mcl(cddt_plan_s* p, hipStream_t st) {
+  const int32_t nf = (int32_t)p->filters.size();
+  CDDT_TRY(launch_motion_many(p->d_filters, p->d_ppre, nf, p->total_particles, p->mcl_odom, p->mcl_noise, st));
+  CDDT_TRY(launch_plan(p, st));
+  return launch_resample_many(p->d_filters, p->d_ppre, nf, p->mcl_u, p->d_stage, p->d_idx, st);
+}
+
+template <class Body>
+cddt_status capture_into(cddt_plan_s* p, hipStream_t st, Body body) {
+  drop_graph(p);
+  CDDT_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  cddt_status s = body();
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(st, &g);
+  if (s != CDDT_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return fail(CDDT_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  p->graph = g;
+  CDDT_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+  return CDDT_OK;
+}
+
 void drop_graph(cddt_plan_s* p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -143,19 +177,25 @@ cddt_status cddt_plan_create(const cddt_filter* filters_h, int32_t n_filters, co
     delete p;
     return fail(CDDT_EDEVICE, "cddt_plan_create: cannot query the device");
   }
+  std::vector<int64_t> ppre(n_filters + 1, 0);
+  for (int32_t f = 0; f < n_filters; ++f) ppre[f + 1] = ppre[f] + p->filters[f].n_particles;
+  p->total_particles = ppre.back();
   auto bail = [&](const std::string& msg) {
     if (p->d_filters) (void)hipFree(p->d_filters);
     if (p->d_prefix) (void)hipFree(p->d_prefix);
     if (p->d_counter) (void)hipFree(p->d_counter);
+    if (p->d_ppre) (void)hipFree(p->d_ppre);
     delete p;
     return fail(CDDT_EDEVICE, msg);
   };
   if (hipMalloc(&p->d_filters, sizeof(FilterDev) * n_filters) != hipSuccess ||
       hipMalloc(&p->d_prefix, sizeof(int64_t) * (n_filters + 1)) != hipSuccess ||
-      hipMalloc(&p->d_counter, kBatchCounterBytes) != hipSuccess)
+      hipMalloc(&p->d_counter, kBatchCounterBytes) != hipSuccess ||
+      hipMalloc(&p->d_ppre, sizeof(int64_t) * (n_filters + 1)) != hipSuccess)
     return bail("cddt_plan_create: hipMalloc failed");
   if (hipMemcpyAsync(p->d_filters, p->fdev.data(), sizeof(FilterDev) * n_filters, hipMemcpyHostToDevice, st) !=
-      hipSuccess)
+          hipSuccess ||
+      hipMemcpyAsync(p->d_ppre, ppre.data(), sizeof(int64_t) * ppre.size(), hipMemcpyHostToDevice, st) != hipSuccess)
     return bail("cddt_plan_create: descriptor upload failed");
   cddt_status s = apply_tuning(p, t, st);
   if (s != CDDT_OK) return bail(cddt_last_error());
@@ -185,19 +225,41 @@ cddt_status cddt_plan_capture(cddt_plan p, void* stream) {
   if (!p) return fail(CDDT_EINVAL, "cddt_plan_capture: plan is NULL");
   if (!stream) return fail(CDDT_EINVAL, "cddt_plan_capture: capture needs a non-default stream");
   hipStream_t st = (hipStream_t)stream;
-  drop_graph(p);
-  CDDT_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  cddt_status s = launch_plan(p, st);
-  hipGraph_t g = nullptr;
-  hipError_t e = hipStreamEndCapture(st, &g);
-  if (s != CDDT_OK) {
-    if (g) (void)hipGraphDestroy(g);
-    return s;
+  return capture_into(p, st, [&] { return launch_plan(p, st); });
+}
+
+cddt_status cddt_plan_set_mcl(cddt_plan p, const float* odom, const uint32_t* u, const float* noise) {
+  if (!p || !odom || !u || !noise) return fail(CDDT_EINVAL, "cddt_plan_set_mcl: NULL argument");
+  for (const auto& f : p->filters)
+    if (f.n_particles > kMaxResample)
+      return fail(CDDT_EINVAL, "cddt_plan_set_mcl: resampling takes at most 2^20 particles per filter");
+  if (!p->d_stage && p->total_particles > 0) {
+    if (hipMalloc(&p->d_stage, sizeof(float) * 3 * (size_t)p->total_particles) != hipSuccess ||
+        hipMalloc(&p->d_idx, sizeof(int32_t) * (size_t)p->total_particles) != hipSuccess) {
+      if (p->d_stage) (void)hipFree(p->d_stage);
+      p->d_stage = nullptr;
+      return fail(CDDT_ENOMEM, "cddt_plan_set_mcl: scratch allocation failed");
+    }
   }
-  if (e != hipSuccess) return fail(CDDT_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-  p->graph = g;
-  CDDT_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+  drop_graph(p);  // a captured step would keep the old pointers
+  p->mcl_odom = odom;
+  p->mcl_u = u;
+  p->mcl_noise = noise;
   return CDDT_OK;
+}
+
+cddt_status cddt_plan_run_mcl(cddt_plan p, void* stream) {
+  if (!p) return fail(CDDT_EINVAL, "cddt_plan_run_mcl: plan is NULL");
+  if (!p->mcl_odom) return fail(CDDT_EINVAL, "cddt_plan_run_mcl: call cddt_plan_set_mcl first");
+  return launch_mcl(p, (hipStream_t)stream);
+}
+
+cddt_status cddt_plan_capture_mcl(cddt_plan p, void* stream) {
+  if (!p) return fail(CDDT_EINVAL, "cddt_plan_capture_mcl: plan is NULL");
+  if (!stream) return fail(CDDT_EINVAL, "cddt_plan_capture_mcl: capture needs a non-default stream");
+  if (!p->mcl_odom) return fail(CDDT_EINVAL, "cddt_plan_capture_mcl: call cddt_plan_set_mcl first");
+  hipStream_t st = (hipStream_t)stream;
+  return capture_into(p, st, [&] { return launch_mcl(p, st); });
 }
 
 cddt_status cddt_plan_replay(cddt_plan p, void* stream) {
@@ -244,6 +306,9 @@ cddt_status cddt_plan_destroy(cddt_plan p) {
   if (p->d_filters) (void)hipFree(p->d_filters);
   if (p->d_prefix) (void)hipFree(p->d_prefix);
   if (p->d_counter) (void)hipFree(p->d_counter);
+  if (p->d_ppre) (void)hipFree(p->d_ppre);
+  if (p->d_stage) (void)hipFree(p->d_stage);
+  if (p->d_idx) (void)hipFree(p->d_idx);
   delete p;
   return CDDT_OK;
 }

@@ -113,6 +113,13 @@ cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, in
                          int64_t total_tiles, const cddt_tuning& t, unsigned long long* d_counter, int32_t cus,
                          hipStream_t st, bool counter_zeroed = false);
 cddt_status check_tuning(const cddt_tuning& t);
+// mcl.hip: motion of every particle of every filter (particle offsets d_pre,
+// n_filters + 1 entries), and one resampling workgroup per filter.
+constexpr int64_t kMaxResample = int64_t(1) << 20;
+cddt_status launch_motion_many(const FilterDev* d_filters, const int64_t* d_pre, int32_t nf, int64_t total,
+                               const float* d_odom, const float* d_noise, hipStream_t st);
+cddt_status launch_resample_many(const FilterDev* d_filters, const int64_t* d_pre, int32_t nf,
+                                 const uint32_t* d_u, float* d_stage, int32_t* d_idx, hipStream_t st);
 cddt_tuning default_tuning();
 // api.hip
 FilterDev filter_dev(const cddt_filter& f);

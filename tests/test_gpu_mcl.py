@@ -1,0 +1,181 @@
+"""Motion model, systematic resampling and the whole particle-filter step on the GPU.
+
+Motion and resampling are bit-identical to the oracle (both evaluate exp / sin /
+cos by the same sequence of double operations and decide every slot in
+integers).  In the plan's step, the log-weights come from the GPU kernel, so
+the oracle resamples those same log-weights; the moved poses and the
+resampled poses must then match bit for bit.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ref as oref
+from paper_1705_01167_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_motion_equals_oracle(seed):
+    from paper_1705_01167_amd import cddt
+    rng = wl.rng_for(801, seed)
+    n = int(rng.choice([1, 63, 64, 1000, 100003]))
+    px = rng.uniform(-10, 4000, n).astype(np.float32)
+    py = rng.uniform(-10, 4000, n).astype(np.float32)
+    pth = rng.uniform(-50, 50, n).astype(np.float32)
+    pth[: min(n, 4)] = np.array([0.0, -0.0, math.pi, -math.pi], np.float32)[: min(n, 4)]
+    noise = rng.normal(0, 0.1, 3 * n).astype(np.float32)
+    odom = tuple(float(v) for v in rng.normal(0, 1, 3))
+    _say(f"motion seed={seed} n={n} odom={odom}")
+    want = oref.motion(px, py, pth, odom, noise[:n], noise[n:2 * n], noise[2 * n:])
+    t = [_dev(px), _dev(py), _dev(pth)]
+    cddt.motion(*t, odom, _dev(noise))
+    for got, w in zip(t, want):
+        assert (got.cpu().numpy() == w).all()
+
+
+def _logw_cases(rng, n):
+    yield "normal", (rng.normal(0, 10, n) - 500).astype(np.float32)
+    yield "peaked", (rng.normal(0, 300, n)).astype(np.float32)
+    lw = np.full(n, -np.inf, np.float32)
+    lw[int(rng.integers(0, n))] = -7.0
+    yield "one", lw
+    lw = (rng.normal(0, 3, n)).astype(np.float32)
+    lw[rng.integers(0, n, max(1, n // 4))] = np.nan
+    lw[rng.integers(0, n, max(1, n // 4))] = -np.inf
+    yield "nan_inf", lw
+    yield "none_finite", np.full(n, np.nan, np.float32)
+    yield "equal", np.full(n, -1.25, np.float32)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 1023, 1024, 1025, 4097, 65539, 1 << 20])
+def test_resample_equals_oracle(n):
+    from paper_1705_01167_amd import cddt
+    rng = wl.rng_for(802, n)
+    px = rng.uniform(0, 100, n).astype(np.float32)
+    py = rng.uniform(0, 100, n).astype(np.float32)
+    pth = rng.uniform(-3, 3, n).astype(np.float32)
+    dpx, dpy, dpt = _dev(px), _dev(py), _dev(pth)
+    for name, lw in _logw_cases(rng, n):
+        for u in (0, int(rng.integers(0, 2**32)), 2**32 - 1):
+            _say(f"resample n={n} {name} u={u}")
+            idx, x, y, t = oref.resample(lw, u, px, py, pth)
+            gi, gx, gy, gt = cddt.resample(_dev(lw), u, dpx, dpy, dpt)
+            assert (gi.cpu().numpy() == idx).all(), f"{(gi.cpu().numpy() != idx).sum()} indices differ"
+            assert (gx.cpu().numpy() == x).all() and (gy.cpu().numpy() == y).all() and (gt.cpu().numpy() == t).all()
+        if n > 4096:
+            break   # one weight shape is enough for the large sizes
+
+
+def test_resample_refuses_oversize():
+    from paper_1705_01167_amd import cddt
+    torch = _torch()
+    n = (1 << 20) + 1
+    z = torch.zeros(n, device="cuda")
+    with pytest.raises(cddt.CddtError):
+        cddt.resample(z, 0, z, z, z)
+
+
+def _plan_setup(seed=0, n_filters=5):
+    from paper_1705_01167_amd import cddt
+    torch = _torch()
+    rng = wl.rng_for(803, seed)
+    M = 500
+    off_h = wl.ray_offsets(61)
+    off = _dev(off_h)
+    filters, keep, host = [], [], []
+    for f in range(n_filters):
+        side = int(rng.integers(150, 600))
+        occ = wl.building_map(rng, side, side)
+        n = int(rng.choice([108, 200, 360]))
+        gm = cddt.Map(_dev(occ), n, buckets=(7 if f % 2 == 0 else None))
+        P = int(rng.integers(1, 4000))
+        px, py, pth = wl.free_poses(rng, occ, P)
+        obs, _ = wl.observations(rng, occ, off_h, M)
+        table = wl.beam_table(M, wl.beam_params(rng))
+        d = [_dev(px), _dev(py), _dev(pth), off, _dev(obs), _dev(table)]
+        lw = torch.zeros(P, dtype=torch.float32, device="cuda")
+        filters.append(cddt.make_filter(gm, *d, M, lw))
+        keep.append((gm, d, lw))
+        host.append(dict(occ=occ, n=n, obs=obs, table=table, P=P))
+    plan = cddt.Plan(filters, keepalive=keep)
+    return rng, plan, keep, host, off_h, M
+
+
+def _step_inputs(rng, host):
+    F = len(host)
+    P = sum(h["P"] for h in host)
+    odom = rng.normal(0, 0.5, 3 * F).astype(np.float32)
+    u = rng.integers(0, 2**32, F, dtype=np.uint64).astype(np.uint32)
+    noise = np.concatenate([rng.normal(0, 0.05, 3 * h["P"]).astype(np.float32) for h in host])
+    assert noise.size == 3 * P
+    return odom, u, noise
+
+
+def test_plan_step_equals_oracle():
+    """Two steps: moved poses exact, log-weights within 1e-5 of the oracle, resampled poses exact."""
+    torch = _torch()
+    rng, plan, keep, host, off_h, M = _plan_setup(0)
+    for step in range(2):
+        odom, u, noise = _step_inputs(rng, host)
+        before = [[t.cpu().numpy() for t in k[1][:3]] for k in keep]
+        d_odom, d_u, d_noise = _dev(odom), _dev(u.view(np.int32)), _dev(noise)
+        plan.set_mcl(d_odom, d_u, d_noise)
+        plan.run_mcl()
+        torch.cuda.synchronize()
+        base = 0
+        for f, (k, h) in enumerate(zip(keep, host)):
+            P = h["P"]
+            nz = noise[3 * base: 3 * base + 3 * P]
+            mx, my, mt = oref.motion(*before[f], odom[3 * f: 3 * f + 3], nz[:P], nz[P:2 * P], nz[2 * P:])
+            rm = oref.RefCDDT(h["occ"], h["n"])
+            ref_lw = rm.weight(mx, my, mt, off_h, h["obs"], h["table"], M)
+            lw = k[2].cpu().numpy()
+            assert (np.abs(lw.astype(np.float64) - ref_lw) <= 1e-5 * np.maximum(1.0, np.abs(ref_lw))).all()
+            idx, rx, ry, rt = oref.resample(lw, int(u[f]), mx, my, mt)
+            got = [t.cpu().numpy() for t in k[1][:3]]
+            assert (got[0] == rx).all() and (got[1] == ry).all() and (got[2] == rt).all(), f"step {step} filter {f}"
+            base += P
+
+
+def test_plan_step_graph_replays_equal_eager():
+    """The captured step, replayed several times with eager work between, equals the eager step."""
+    torch = _torch()
+    rng, plan_g, keep_g, host, off_h, M = _plan_setup(1, n_filters=4)
+    _, plan_e, keep_e, _, _, _ = _plan_setup(1, n_filters=4)
+    odom, u, noise = _step_inputs(rng, host)
+    ins_g = [_dev(odom), _dev(u.view(np.int32)), _dev(noise)]
+    ins_e = [_dev(odom), _dev(u.view(np.int32)), _dev(noise)]
+    plan_g.set_mcl(*ins_g)
+    plan_e.set_mcl(*ins_e)
+    s = torch.cuda.Stream()
+    plan_g.capture_mcl(s)
+    for rep in range(3):
+        plan_g.replay(s)
+        s.synchronize()
+        plan_e.run_mcl()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()   # unrelated eager work between replays
+        for kg, ke in zip(keep_g, keep_e):
+            for tg, te in zip(kg[1][:3], ke[1][:3]):
+                assert torch.equal(tg, te), f"replay {rep}"
+            assert torch.equal(kg[2], ke[2])
