@@ -113,6 +113,10 @@ def build_batched(n_filters: int):
     off = t_dev(off_h)
     filters, keep, host = [], [], []
     t_gen = t_build = 0.0
+    # every filter's poses are views of one buffer, so one copy can restore them all
+    total_p = sum(sp["particles"] for sp in specs)
+    pose_buf = torch.empty(3 * total_p, dtype=torch.float32, device="cuda")
+    p_off = 0
     for f, sp in enumerate(specs):
         t0 = time.perf_counter()
         occ = wl.building_map(wl.rng_for(wl.BATCHED, wl.S_MAP, f), sp["side"], sp["side"])
@@ -125,7 +129,12 @@ def build_batched(n_filters: int):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         del occ_d
-        d = {k: t_dev(v) for k, v in dict(px=px, py=py, pth=pth, obs=obs, table=table).items()}
+        d = {k: t_dev(v) for k, v in dict(obs=obs, table=table).items()}
+        P = sp["particles"]
+        for i, (k, v) in enumerate((("px", px), ("py", py), ("pth", pth))):
+            d[k] = pose_buf[3 * p_off + i * P: 3 * p_off + (i + 1) * P]
+            d[k].copy_(torch.from_numpy(v))
+        p_off += P
         lw = torch.zeros(sp["particles"], dtype=torch.float32, device="cuda")
         filters.append(cddt.make_filter(m, d["px"], d["py"], d["pth"], off, d["obs"], d["table"], MAX_RANGE,
                                         lw, pair=pair))
@@ -133,7 +142,7 @@ def build_batched(n_filters: int):
         host.append(dict(occ=occ, px=px, py=py, pth=pth, obs=obs, table=table, n=sp["theta_bins"]))
         t_gen += t1 - t0
         t_build += t2 - t1
-    return specs, filters, keep, host, off_h, dict(generate_s=t_gen, gpu_build_s=t_build)
+    return specs, filters, keep, host, off_h, dict(generate_s=t_gen, gpu_build_s=t_build, pose_buf=pose_buf)
 
 
 def cpu_baseline(specs, host, off_h, budget_s: float, max_build_s: float = 40.0):
@@ -175,6 +184,7 @@ def run_batched(args) -> dict:
 
     log("bench: generating and building maps")
     specs, filters, keep, host, off_h, times = build_batched(args.filters)
+    pose_buf = times.pop("pose_buf")
     particles = sum(s["particles"] for s in specs)
     rays_per_step = particles * RAYS
     stats = [k[0].info() for k in keep]
@@ -207,6 +217,8 @@ def run_batched(args) -> dict:
     wall, batched_ms = timed(step, args.steps, args.warmup, stream)
     exact = all(torch.equal(a, k[2]) for a, k in zip(plain_out, keep))
     _, plain_ms = timed(plan.run_plain, args.steps, max(1, args.warmup // 2), stream)
+
+    mcl = None if args.no_mcl else run_mcl_step(args, plan, pose_buf, specs, stream, batched_ms)
 
     value = rays_per_step / (wall / args.steps)
     algo_bytes = particles * BYTES_PER_PARTICLE
@@ -263,6 +275,7 @@ def run_batched(args) -> dict:
             "bytes_per_particle": BYTES_PER_PARTICLE,
             "kernel_ms": batched_ms,
         },
+        "mcl_step": mcl,
         "gather_probe": probe,
         "cpu_baseline": None,
         "context": "paper: 2500 particles x 61 rays at 40 Hz = 6.1e6 rays/s on one Jetson TX1 CPU thread",
@@ -280,6 +293,39 @@ def run_batched(args) -> dict:
         log("bench: timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(specs, host, off_h, args.cpu_budget)
     return out
+
+
+def run_mcl_step(args, plan, pose_buf, specs, stream, sensor_ms: float) -> dict:
+    """The whole particle-filter step of every filter (motion, weights, resampling), one captured graph.
+
+    Each timed step first restores every filter's particles from a snapshot (one 3.8 MB device copy,
+    included in the time), so every step starts from the same particles as the sensor-only step.
+    """
+    import torch
+    from paper_1705_01167_amd import workloads as wl
+    rng = wl.rng_for(wl.BATCHED, wl.S_MOTION)
+    F = len(specs)
+    P = sum(sp["particles"] for sp in specs)
+    odom = t_dev(rng.normal(0, 0.5, 3 * F).astype(np.float32))
+    u = t_dev(rng.integers(0, 2**32, F, dtype=np.uint64).astype(np.uint32).view(np.int32))
+    noise = t_dev(rng.normal(0, 0.05, 3 * P).astype(np.float32))
+    snapshot = pose_buf.clone()
+    plan.set_mcl(odom, u, noise)
+    plan.capture_mcl(stream)
+
+    def step(s):
+        with torch.cuda.stream(s):
+            pose_buf.copy_(snapshot)
+        plan.replay(s)
+
+    wall, ms = timed(step, args.steps, args.warmup, stream)
+    with torch.cuda.stream(stream):
+        pose_buf.copy_(snapshot)
+    stream.synchronize()
+    return {"ms_per_step": wall / args.steps * 1e3, "kernel_ms": ms, "sensor_only_kernel_ms": sensor_ms,
+            "particles_per_s": P / (wall / args.steps), "rays_per_s": P * RAYS / (wall / args.steps),
+            "steps": "motion (odometry + caller noise) -> batched log-weights -> systematic resampling per "
+                     "filter, in place; each step restores the particles first (one device copy)"}
 
 
 # ---------------------------------------------------------------------------
@@ -514,6 +560,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving summary")
     ap.add_argument("--no-probe", action="store_true", help="skip the gather-bandwidth probe")
+    ap.add_argument("--no-mcl", action="store_true", help="skip the whole-filter-step (motion + resampling) timing")
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle timing to aim for")
     ap.add_argument("--no-tune-cache", action="store_true")
     ap.add_argument("--tuning", type=str, default=None,

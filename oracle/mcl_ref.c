@@ -24,7 +24,8 @@
  *   whose cumulative weight n C_(k+1) exceeds s + j T.)
  *
  *   exp, sin and cos are evaluated by the functions below (range reduction
- *   and Taylor series in a fixed order of IEEE double operations), so a
+ *   and Taylor series by Horner's rule with the coefficients below, in a
+ *   fixed order of IEEE double operations), so a
  *   second implementation that performs the same operations gets the same
  *   bits and takes the same integer decisions.
  *
@@ -42,29 +43,45 @@
 #define MCL_PI 3.141592653589793
 #define MCL_TWO_PI 6.283185307179586
 
+/* Taylor coefficients: 1/k! (exp), (-1)^n/(2n+1)! (sin), (-1)^n/(2n)! (cos),
+ * each the double nearest to the exact value. */
+static const double kExpC[16] = {
+    1.0, 1.0, 0.5, 0.16666666666666666,
+    0.041666666666666664, 0.008333333333333333, 0.001388888888888889, 0.0001984126984126984,
+    2.48015873015873e-05, 2.7557319223985893e-06, 2.755731922398589e-07, 2.505210838544172e-08,
+    2.08767569878681e-09, 1.6059043836821613e-10, 1.1470745597729725e-11, 7.647163731819816e-13};
+static const double kSinC[11] = {
+    1.0, -0.16666666666666666, 0.008333333333333333, -0.0001984126984126984,
+    2.7557319223985893e-06, -2.505210838544172e-08, 1.6059043836821613e-10, -7.647163731819816e-13,
+    2.8114572543455206e-15, -8.22063524662433e-18, 1.9572941063391263e-20};
+static const double kCosC[11] = {
+    1.0, -0.5, 0.041666666666666664, -0.001388888888888889,
+    2.48015873015873e-05, -2.755731922398589e-07, 2.08767569878681e-09, -1.1470745597729725e-11,
+    4.779477332387385e-14, -1.5619206968586225e-16, 4.110317623312165e-19};
+
 /* exp(x) for x <= 0: x log2(e) = k + f with k = floor, 2^f = e^(f ln 2) by
- * its Taylor series to degree 15 in nested form, times 2^k.  0 below -64. */
+ * its Taylor series to degree 15 (Horner), times 2^k.  0 below -64. */
 double ref_det_exp_neg(double x) {
   if (!(x >= -64.0)) return 0.0; /* also NaN and -inf */
   const double y = x * MCL_LOG2E;
   const double k = floor(y);
   const double t = (y - k) * MCL_LN2;
-  double p = 1.0;
-  for (int n = 15; n >= 1; --n) p = 1.0 + (t / (double)n) * p;
+  double p = kExpC[15];
+  for (int n = 14; n >= 0; --n) p = p * t + kExpC[n];
   return ldexp(p, (int)k);
 }
 
 /* sin and cos: a = k pi/2 + r with k = floor(a 2/pi + 1/2) and a two-part
- * pi/2, |r| <= about pi/4; Taylor series in r^2 in nested form (terms to
- * r^21 and r^20); the quadrant k mod 4 picks and signs the results. */
+ * pi/2, |r| <= about pi/4; Taylor series in r^2 by Horner (terms to r^21 and
+ * r^20); the quadrant k mod 4 picks and signs the results. */
 void ref_det_sincos(double a, double* s_out, double* c_out) {
   const double k = floor(a * MCL_TWO_OVER_PI + 0.5);
   const double r = (a - k * MCL_PIO2_HI) - k * MCL_PIO2_LO;
   const double r2 = r * r;
-  double qs = 1.0, qc = 1.0;
-  for (int n = 10; n >= 1; --n) {
-    qs = 1.0 - (r2 / (double)((2 * n) * (2 * n + 1))) * qs;
-    qc = 1.0 - (r2 / (double)((2 * n - 1) * (2 * n))) * qc;
+  double qs = kSinC[10], qc = kCosC[10];
+  for (int n = 9; n >= 0; --n) {
+    qs = qs * r2 + kSinC[n];
+    qc = qc * r2 + kCosC[n];
   }
   const double sr = r * qs, cr = qc;
   const long long kq = (long long)k;

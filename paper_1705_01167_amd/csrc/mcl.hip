@@ -16,9 +16,9 @@
 //                After the weights everything is integer arithmetic, so the
 //                result is independent of the order of the scan.
 //
-// exp, sin and cos come from range reduction and Taylor series in a fixed
-// order of IEEE double operations (below), so the results are the same bits
-// on any implementation that performs the same operations.
+// exp, sin and cos come from range reduction and Taylor series by Horner's
+// rule in a fixed order of IEEE double operations (below), so the results are
+// the same bits on any implementation that performs the same operations.
 #include <algorithm>
 #include <climits>
 
@@ -37,28 +37,46 @@ constexpr double kTwoPi = 6.283185307179586;
 constexpr int kResampleThreads = 1024;
 constexpr int kMotionThreads = 256;
 
+// Taylor coefficients, the nearest doubles to 1/k! (exp), (-1)^n/(2n+1)! (sin)
+// and (-1)^n/(2n)! (cos).
+__constant__ const double kExpC[16] = {
+    1.0, 1.0, 0.5, 0.16666666666666666,
+    0.041666666666666664, 0.008333333333333333, 0.001388888888888889, 0.0001984126984126984,
+    2.48015873015873e-05, 2.7557319223985893e-06, 2.755731922398589e-07, 2.505210838544172e-08,
+    2.08767569878681e-09, 1.6059043836821613e-10, 1.1470745597729725e-11, 7.647163731819816e-13};
+__constant__ const double kSinC[11] = {
+    1.0, -0.16666666666666666, 0.008333333333333333, -0.0001984126984126984,
+    2.7557319223985893e-06, -2.505210838544172e-08, 1.6059043836821613e-10, -7.647163731819816e-13,
+    2.8114572543455206e-15, -8.22063524662433e-18, 1.9572941063391263e-20};
+__constant__ const double kCosC[11] = {
+    1.0, -0.5, 0.041666666666666664, -0.001388888888888889,
+    2.48015873015873e-05, -2.755731922398589e-07, 2.08767569878681e-09, -1.1470745597729725e-11,
+    4.779477332387385e-14, -1.5619206968586225e-16, 4.110317623312165e-19};
+
 // e^x for x <= 0 (0 below -64 and for NaN): x log2 e = k + f, e^(f ln 2) by
-// the Taylor series to degree 15 (nested), scaled by 2^k.
+// the Taylor series to degree 15 (Horner), scaled by 2^k.
 __device__ double exp_neg(double x) {
   if (!(x >= -64.0)) return 0.0;
   const double y = x * kLog2e;
   const double k = floor(y);
   const double t = (y - k) * kLn2;
-  double p = 1.0;
-  for (int n = 15; n >= 1; --n) p = 1.0 + (t / (double)n) * p;
+  double p = kExpC[15];
+#pragma unroll
+  for (int n = 14; n >= 0; --n) p = p * t + kExpC[n];
   return ldexp(p, (int)k);
 }
 
 // sin and cos by quadrant reduction with a two-part pi/2 and Taylor series in
-// r^2 (to r^21 / r^20, nested).
+// r^2 by Horner (to r^21 / r^20).
 __device__ void sin_cos(double a, double& s_out, double& c_out) {
   const double k = floor(a * kTwoOverPi + 0.5);
   const double r = (a - k * kPio2Hi) - k * kPio2Lo;
   const double r2 = r * r;
-  double qs = 1.0, qc = 1.0;
-  for (int n = 10; n >= 1; --n) {
-    qs = 1.0 - (r2 / (double)((2 * n) * (2 * n + 1))) * qs;
-    qc = 1.0 - (r2 / (double)((2 * n - 1) * (2 * n))) * qc;
+  double qs = kSinC[10], qc = kCosC[10];
+#pragma unroll
+  for (int n = 9; n >= 0; --n) {
+    qs = qs * r2 + kSinC[n];
+    qc = qc * r2 + kCosC[n];
   }
   const double sr = r * qs, cr = qc;
   const long long kq = (long long)k;
@@ -126,71 +144,104 @@ __global__ void k_motion_many(const FilterDev* __restrict__ filters, const int64
 }
 
 // ---------------------------------------------------------------------------
-// Workgroup reductions and scans (kResampleThreads threads)
+// Workgroup reductions and scans (kResampleThreads threads = 16 waves): a
+// shuffle scan inside each wave, then one wave scans the 16 wave totals.
 // ---------------------------------------------------------------------------
+constexpr int kWaves = kResampleThreads / 64;
+constexpr int kItems = 4;  // consecutive elements per thread in every pass
+constexpr int kChunk = kResampleThreads * kItems;
+
 struct ResampleShared {
-  unsigned long long s64[kResampleThreads];
-  int32_t s32[kResampleThreads];
-  float f32[kResampleThreads];
+  unsigned long long w64[kWaves];
+  int32_t w32[kWaves];
+  float wf[kWaves];
 };
 
-__device__ unsigned long long block_sum_u64(unsigned long long v, ResampleShared& sh) {
-  sh.s64[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = kResampleThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh.s64[threadIdx.x] += sh.s64[threadIdx.x + w];
-    __syncthreads();
+__device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long x, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const unsigned long long y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
   }
-  const unsigned long long r = sh.s64[0];
-  __syncthreads();
-  return r;
+  return x;
+}
+
+__device__ __forceinline__ int32_t wave_incl_max_i32(int32_t x, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x = max(x, y);
+  }
+  return x;
 }
 
 // Exclusive prefix sum over the block; *total gets the block's sum.
 __device__ unsigned long long block_exscan_u64(unsigned long long v, ResampleShared& sh, unsigned long long* total) {
-  sh.s64[threadIdx.x] = v;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const unsigned long long x = wave_incl_scan_u64(v, lane);
+  if (lane == 63) sh.w64[wid] = x;
   __syncthreads();
-  for (int d = 1; d < kResampleThreads; d <<= 1) {
-    const unsigned long long add = (int)threadIdx.x >= d ? sh.s64[threadIdx.x - d] : 0ull;
-    __syncthreads();
-    sh.s64[threadIdx.x] += add;
-    __syncthreads();
+  if (wid == 0) {
+    unsigned long long w = lane < kWaves ? sh.w64[lane] : 0ull;
+    w = wave_incl_scan_u64(w, lane);
+    if (lane < kWaves) sh.w64[lane] = w;
   }
-  const unsigned long long incl = sh.s64[threadIdx.x];
-  *total = sh.s64[kResampleThreads - 1];
   __syncthreads();
-  return incl - v;
+  const unsigned long long before = wid > 0 ? sh.w64[wid - 1] : 0ull;
+  *total = sh.w64[kWaves - 1];
+  __syncthreads();
+  return before + x - v;
 }
 
-__device__ int32_t block_inclusive_max_i32(int32_t v, ResampleShared& sh, int32_t* last) {
-  sh.s32[threadIdx.x] = v;
+__device__ unsigned long long block_sum_u64(unsigned long long v, ResampleShared& sh) {
+  unsigned long long total = 0;
+  (void)block_exscan_u64(v, sh, &total);
+  return total;
+}
+
+// Exclusive running maximum over the block (INT_MIN for thread 0); *last
+// gets the block's maximum.
+__device__ int32_t block_excl_max_i32(int32_t v, ResampleShared& sh, int32_t* last) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int32_t x = wave_incl_max_i32(v, lane);
+  int32_t ex = __shfl_up(x, 1, 64);
+  if (lane == 0) ex = INT_MIN;
+  if (lane == 63) sh.w32[wid] = x;
   __syncthreads();
-  for (int d = 1; d < kResampleThreads; d <<= 1) {
-    const int32_t o = (int)threadIdx.x >= d ? sh.s32[threadIdx.x - d] : INT_MIN;
-    __syncthreads();
-    sh.s32[threadIdx.x] = max(sh.s32[threadIdx.x], o);
-    __syncthreads();
+  if (wid == 0) {
+    int32_t w = lane < kWaves ? sh.w32[lane] : INT_MIN;
+    w = wave_incl_max_i32(w, lane);
+    if (lane < kWaves) sh.w32[lane] = w;
   }
-  const int32_t r = sh.s32[threadIdx.x];
-  *last = sh.s32[kResampleThreads - 1];
   __syncthreads();
-  return r;
+  if (wid > 0) ex = max(ex, sh.w32[wid - 1]);
+  *last = sh.w32[kWaves - 1];
+  __syncthreads();
+  return ex;
 }
 
 // (largest finite value, whether there is one) over the block.
 __device__ float block_max_finite(float v, bool ok, ResampleShared& sh, bool* any) {
-  sh.f32[threadIdx.x] = ok ? v : -INFINITY;
-  sh.s32[threadIdx.x] = ok ? 1 : 0;
-  __syncthreads();
-  for (int w = kResampleThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      sh.f32[threadIdx.x] = fmaxf(sh.f32[threadIdx.x], sh.f32[threadIdx.x + w]);
-      sh.s32[threadIdx.x] |= sh.s32[threadIdx.x + w];
-    }
-    __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  float m = ok ? v : -INFINITY;
+  int32_t a = ok ? 1 : 0;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    m = fmaxf(m, __shfl_xor(m, d, 64));
+    a |= __shfl_xor(a, d, 64);
   }
-  const float r = sh.f32[0];
-  *any = sh.s32[0] != 0;
+  if (lane == 0) {
+    sh.wf[wid] = m;
+    sh.w32[wid] = a;
+  }
+  __syncthreads();
+  float r = sh.wf[0];
+  int32_t ra = sh.w32[0];
+  for (int w = 1; w < kWaves; ++w) {
+    r = fmaxf(r, sh.wf[w]);
+    ra |= sh.w32[w];
+  }
+  *any = ra != 0;
   __syncthreads();
   return r;
 }
@@ -202,16 +253,25 @@ __device__ __forceinline__ unsigned long long weight_q(float l, bool any, float 
 }
 
 // First output slot of cumulative weight c: ceil((n c - s) / T), 0 when n c <= s.
+// A double-precision estimate (inv_t = 1 / T) is corrected by exact integer
+// products, so the result is the exact ceiling without a 64-bit division
+// (n c <= 2^60, the estimate is off by at most one or two).
 __device__ __forceinline__ int64_t first_slot(unsigned long long n, unsigned long long c, unsigned long long s,
-                                              unsigned long long T) {
+                                              unsigned long long T, double inv_t) {
   const unsigned long long num = n * c;
-  return num <= s ? 0 : (int64_t)((num - s + T - 1) / T);
+  if (num <= s) return 0;
+  const unsigned long long d = num - s;
+  unsigned long long j = (unsigned long long)((double)d * inv_t);
+  while (j * T < d) ++j;
+  while (j > 0 && (j - 1) * T >= d) --j;
+  return (int64_t)j;
 }
 
 // Systematic resampling of one filter by one workgroup.  Reads logw and the
 // poses in (ix, iy, it); writes idx (n) and the gathered poses to (ox, oy, ot).
 // With stage != nullptr the poses are first copied there and gathered from it,
-// so (ix, iy, it) may equal (ox, oy, ot).
+// so (ix, iy, it) may equal (ox, oy, ot).  Scans run over chunks of kChunk
+// elements, kItems consecutive ones per thread, with a running carry.
 __device__ void resample_block(const float* __restrict__ logw, int64_t n, uint32_t u, const float* ix,
                                const float* iy, const float* it, float* ox, float* oy, float* ot, int32_t* idx,
                                float* stage, ResampleShared& sh) {
@@ -240,18 +300,29 @@ __device__ void resample_block(const float* __restrict__ logw, int64_t n, uint32
   for (int64_t i = tid; i < n; i += kResampleThreads) part += weight_q(logw[i], any, m);
   const unsigned long long T = block_sum_u64(part, sh);
   const unsigned long long s = ((unsigned long long)(u >> 12) * T) >> 20;
-  // 3. first output slot of every particle with copies (chunks of the block size, running carry)
+  const double inv_t = 1.0 / (double)T;
+  // 3. first output slot of every particle with copies
   unsigned long long carry = 0;
-  for (int64_t c0 = 0; c0 < n; c0 += kResampleThreads) {
-    const int64_t i = c0 + tid;
-    const unsigned long long q = i < n ? weight_q(logw[i], any, m) : 0ull;
+  for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
+    const int64_t i0 = c0 + (int64_t)tid * kItems;
+    uint32_t q[kItems];  // q <= 2^20
+    unsigned long long local = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      q[k] = i0 + k < n ? (uint32_t)weight_q(logw[i0 + k], any, m) : 0u;
+      local += q[k];
+    }
     unsigned long long chunk = 0;
-    const unsigned long long before = carry + block_exscan_u64(q, sh, &chunk);
-    if (i < n && q > 0) {
-      const int64_t a0 = first_slot((unsigned long long)n, before, s, T);
-      int64_t a1 = first_slot((unsigned long long)n, before + q, s, T);
-      if (a1 > n) a1 = n;
-      if (a0 < a1) idx[a0] = (int32_t)i;
+    unsigned long long before = carry + block_exscan_u64(local, sh, &chunk);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      if (q[k] > 0) {
+        const int64_t a0 = first_slot((unsigned long long)n, before, s, T, inv_t);
+        int64_t a1 = first_slot((unsigned long long)n, before + q[k], s, T, inv_t);
+        if (a1 > n) a1 = n;
+        if (a0 < a1) idx[a0] = (int32_t)(i0 + k);
+      }
+      before += q[k];
     }
     carry += chunk;
   }
@@ -262,19 +333,27 @@ __device__ void resample_block(const float* __restrict__ logw, int64_t n, uint32
   const float* gy = stage ? stage + n : iy;
   const float* gt = stage ? stage + 2 * n : it;
   int32_t run = -1;
-  for (int64_t c0 = 0; c0 < n; c0 += kResampleThreads) {
-    const int64_t j = c0 + tid;
-    const int32_t v = j < n ? idx[j] : -1;
+  for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
+    const int64_t j0 = c0 + (int64_t)tid * kItems;
+    int32_t v[kItems], local = -1;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      v[k] = j0 + k < n ? idx[j0 + k] : -1;
+      local = max(local, v[k]);
+    }
     int32_t last = -1;
-    int32_t k = block_inclusive_max_i32(v, sh, &last);
-    k = max(k, run);
+    int32_t k_run = max(run, block_excl_max_i32(local, sh, &last));  // everything before this thread's items
     run = max(run, last);
-    k = k < 0 ? 0 : k;  // slot 0 is always marked (T > 0); kept in bounds regardless
-    if (j < n) {
-      idx[j] = k;
-      ox[j] = gx[k];
-      oy[j] = gy[k];
-      ot[j] = gt[k];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      k_run = max(k_run, v[k]);
+      const int32_t src = k_run < 0 ? 0 : k_run;  // slot 0 is always marked (T > 0); kept in bounds regardless
+      if (j0 + k < n) {
+        idx[j0 + k] = src;
+        ox[j0 + k] = gx[src];
+        oy[j0 + k] = gy[src];
+        ot[j0 + k] = gt[src];
+      }
     }
   }
 }

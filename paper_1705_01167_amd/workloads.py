@@ -21,7 +21,7 @@ import numpy as np
 SMALL, FLOOR, BATCHED, UPDATES, SERVING = 1, 2, 3, 4, 5
 
 # Stream ids (second SeedSequence word).
-S_MAP, S_POSES, S_TABLE, S_OBS, S_OPS, S_SPEC, S_ARRIVALS = range(7)
+S_MAP, S_POSES, S_TABLE, S_OBS, S_OPS, S_SPEC, S_ARRIVALS, S_MOTION = range(8)
 
 
 def rng_for(config: int, stream: int, extra: int | None = None) -> np.random.Generator:
