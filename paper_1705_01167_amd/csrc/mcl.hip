@@ -278,26 +278,50 @@ __device__ void resample_block(const float* __restrict__ logw, int64_t n, uint32
   const int tid = threadIdx.x;
   if (n <= 0) return;
   // 1. largest finite log-weight; optional staging copy; clear the slot marks
+  // (kItems strided elements per thread per iteration, loads issued together)
   float m = -INFINITY;
   bool mine = false;
-  for (int64_t i = tid; i < n; i += kResampleThreads) {
-    const float l = logw[i];
-    if (isfinite(l) && (!mine || l > m)) {
-      m = l;
-      mine = true;
+  for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
+    float l[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int64_t i = c0 + tid + (int64_t)k * kResampleThreads;
+      l[k] = i < n ? logw[i] : NAN;
     }
-    idx[i] = -1;
-    if (stage) {
-      stage[i] = ix[i];
-      stage[n + i] = iy[i];
-      stage[2 * n + i] = it[i];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int64_t i = c0 + tid + (int64_t)k * kResampleThreads;
+      if (isfinite(l[k]) && (!mine || l[k] > m)) {
+        m = l[k];
+        mine = true;
+      }
+      if (i < n) {
+        idx[i] = -1;
+        if (stage) {
+          stage[i] = ix[i];
+          stage[n + i] = iy[i];
+          stage[2 * n + i] = it[i];
+        }
+      }
     }
   }
   bool any = false;
   m = block_max_finite(m, mine, sh, &any);
   // 2. total integer weight
   unsigned long long part = 0;
-  for (int64_t i = tid; i < n; i += kResampleThreads) part += weight_q(logw[i], any, m);
+  for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
+    float l[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int64_t i = c0 + tid + (int64_t)k * kResampleThreads;
+      l[k] = i < n ? logw[i] : NAN;
+    }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int64_t i = c0 + tid + (int64_t)k * kResampleThreads;
+      part += i < n ? weight_q(l[k], any, m) : 0ull;
+    }
+  }
   const unsigned long long T = block_sum_u64(part, sh);
   const unsigned long long s = ((unsigned long long)(u >> 12) * T) >> 20;
   const double inv_t = 1.0 / (double)T;
@@ -305,11 +329,14 @@ __device__ void resample_block(const float* __restrict__ logw, int64_t n, uint32
   unsigned long long carry = 0;
   for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
     const int64_t i0 = c0 + (int64_t)tid * kItems;
+    float l[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) l[k] = i0 + k < n ? logw[i0 + k] : NAN;
     uint32_t q[kItems];  // q <= 2^20
     unsigned long long local = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-      q[k] = i0 + k < n ? (uint32_t)weight_q(logw[i0 + k], any, m) : 0u;
+      q[k] = i0 + k < n ? (uint32_t)weight_q(l[k], any, m) : 0u;
       local += q[k];
     }
     unsigned long long chunk = 0;
