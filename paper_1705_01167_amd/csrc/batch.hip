@@ -36,6 +36,9 @@ struct cddt_plan_s {
   const float* mcl_odom = nullptr;
   const uint32_t* mcl_u = nullptr;
   const float* mcl_noise = nullptr;
+  // resampling segments (built with the scratch on first use)
+  std::vector<void*> seg_mem;
+  cddt::ResampleSegs segs{};
 };
 
 namespace cddt {
@@ -123,9 +126,10 @@ void drop_graph(cddt_plan_s* p);
 
 cddt_status launch_mcl(cddt_plan_s* p, hipStream_t st) {
   const int32_t nf = (int32_t)p->filters.size();
+  if (p->total_particles == 0) return launch_plan(p, st);
   CDDT_TRY(launch_motion_many(p->d_filters, p->d_ppre, nf, p->total_particles, p->mcl_odom, p->mcl_noise, st));
   CDDT_TRY(launch_plan(p, st));
-  return launch_resample_many(p->d_filters, p->d_ppre, nf, p->mcl_u, p->d_stage, p->d_idx, st);
+  return launch_resample_many(p->d_filters, p->d_ppre, p->mcl_u, p->d_stage, p->d_idx, p->segs, st);
 }
 
 template <class Body>
@@ -234,12 +238,41 @@ cddt_status cddt_plan_set_mcl(cddt_plan p, const float* odom, const uint32_t* u,
     if (f.n_particles > kMaxResample)
       return fail(CDDT_EINVAL, "cddt_plan_set_mcl: resampling takes at most 2^20 particles per filter");
   if (!p->d_stage && p->total_particles > 0) {
-    if (hipMalloc(&p->d_stage, sizeof(float) * 3 * (size_t)p->total_particles) != hipSuccess ||
-        hipMalloc(&p->d_idx, sizeof(int32_t) * (size_t)p->total_particles) != hipSuccess) {
-      if (p->d_stage) (void)hipFree(p->d_stage);
-      p->d_stage = nullptr;
+    // segments of kResampleSegment particles per filter
+    std::vector<int32_t> seg_f, seg_lo, fseg(p->filters.size() + 1, 0);
+    for (size_t f = 0; f < p->filters.size(); ++f) {
+      for (int64_t lo = 0; lo < p->filters[f].n_particles; lo += kResampleSegment) {
+        seg_f.push_back((int32_t)f);
+        seg_lo.push_back((int32_t)lo);
+      }
+      fseg[f + 1] = (int32_t)seg_f.size();
+    }
+    const size_t ns = seg_f.size();
+    void* mem[9] = {};
+    const size_t bytes[9] = {sizeof(float) * 3 * (size_t)p->total_particles, sizeof(int32_t) * (size_t)p->total_particles,
+                             4 * ns, 4 * ns, 4 * fseg.size(), 4 * ns, 4 * ns, 8 * ns, 4 * ns};
+    bool ok = true;
+    for (int k = 0; k < 9 && ok; ++k) ok = hipMalloc(&mem[k], bytes[k]) == hipSuccess;
+    if (ok)
+      ok = hipMemcpy(mem[2], seg_f.data(), bytes[2], hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(mem[3], seg_lo.data(), bytes[3], hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(mem[4], fseg.data(), bytes[4], hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+      for (void* q : mem)
+        if (q) (void)hipFree(q);
       return fail(CDDT_ENOMEM, "cddt_plan_set_mcl: scratch allocation failed");
     }
+    p->d_stage = (float*)mem[0];
+    p->d_idx = (int32_t*)mem[1];
+    p->seg_mem.assign(mem + 2, mem + 9);
+    p->segs.seg_f = (const int32_t*)mem[2];
+    p->segs.seg_lo = (const int32_t*)mem[3];
+    p->segs.fseg = (const int32_t*)mem[4];
+    p->segs.seg_max = (float*)mem[5];
+    p->segs.seg_any = (int32_t*)mem[6];
+    p->segs.seg_sum = (unsigned long long*)mem[7];
+    p->segs.seg_mmax = (int32_t*)mem[8];
+    p->segs.nseg = (int32_t)ns;
   }
   drop_graph(p);  // a captured step would keep the old pointers
   p->mcl_odom = odom;
@@ -309,6 +342,7 @@ cddt_status cddt_plan_destroy(cddt_plan p) {
   if (p->d_ppre) (void)hipFree(p->d_ppre);
   if (p->d_stage) (void)hipFree(p->d_stage);
   if (p->d_idx) (void)hipFree(p->d_idx);
+  for (void* q : p->seg_mem) (void)hipFree(q);
   delete p;
   return CDDT_OK;
 }

@@ -118,8 +118,22 @@ cddt_status check_tuning(const cddt_tuning& t);
 constexpr int64_t kMaxResample = int64_t(1) << 20;
 cddt_status launch_motion_many(const FilterDev* d_filters, const int64_t* d_pre, int32_t nf, int64_t total,
                                const float* d_odom, const float* d_noise, hipStream_t st);
-cddt_status launch_resample_many(const FilterDev* d_filters, const int64_t* d_pre, int32_t nf,
-                                 const uint32_t* d_u, float* d_stage, int32_t* d_idx, hipStream_t st);
+// Segmented resampling of many filters: segment g covers particles
+// [seg_lo[g], seg_lo[g] + kResampleSegment) of filter seg_f[g]; filter f owns
+// segments fseg[f] .. fseg[f+1]-1.  The per-segment arrays are scratch.
+constexpr int32_t kResampleSegment = 4096;
+struct ResampleSegs {
+  const int32_t* seg_f;
+  const int32_t* seg_lo;
+  const int32_t* fseg;
+  float* seg_max;
+  int32_t* seg_any;
+  unsigned long long* seg_sum;
+  int32_t* seg_mmax;
+  int32_t nseg;
+};
+cddt_status launch_resample_many(const FilterDev* d_filters, const int64_t* d_pre, const uint32_t* d_u,
+                                 float* d_stage, int32_t* d_idx, const ResampleSegs& segs, hipStream_t st);
 cddt_tuning default_tuning();
 // api.hip
 FilterDev filter_dev(const cddt_filter& f);

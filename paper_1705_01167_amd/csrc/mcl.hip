@@ -8,13 +8,15 @@
 //                particle's heading plus caller-drawn noise, in double
 //                precision, rounded once to float32; heading wrapped to
 //                [-pi, pi).  Many filters in one launch (particle prefix).
-//   k_resample   one workgroup per filter: the largest finite log-weight, the
+//   k_resample   one workgroup for one filter: the largest finite log-weight, the
 //                integer weights q = floor(2^20 exp(l - max)) and their total,
 //                then a chunked exclusive scan of q gives every particle its
 //                first output slot; the slot array is max-scanned into the
 //                source index of every output, and the poses are gathered.
 //                After the weights everything is integer arithmetic, so the
 //                result is independent of the order of the scan.
+//   k_rs_*       the same for many filters in segments of kResampleSegment
+//                particles, one workgroup per segment (five launches).
 //
 // exp, sin and cos come from range reduction and Taylor series by Horner's
 // rule in a fixed order of IEEE double operations (below), so the results are
@@ -150,6 +152,7 @@ __global__ void k_motion_many(const FilterDev* __restrict__ filters, const int64
 constexpr int kWaves = kResampleThreads / 64;
 constexpr int kItems = 4;  // consecutive elements per thread in every pass
 constexpr int kChunk = kResampleThreads * kItems;
+static_assert(kChunk == kResampleSegment, "a resampling segment is one chunk of one workgroup");
 
 struct ResampleShared {
   unsigned long long w64[kWaves];
@@ -392,19 +395,192 @@ __global__ __launch_bounds__(kResampleThreads) void k_resample(const float* __re
   resample_block(logw, n, u, ix, iy, it, ox, oy, ot, idx, nullptr, sh);
 }
 
-// Many filters, one workgroup each, in place: stage holds 3 pre[f] + ...
-// floats of scratch per filter and idx pre[f] + ... ints.
-__global__ __launch_bounds__(kResampleThreads) void k_resample_many(const FilterDev* __restrict__ filters,
-                                                                    const int64_t* __restrict__ pre,
-                                                                    const uint32_t* __restrict__ u, float* stage,
-                                                                    int32_t* idx) {
+// ---------------------------------------------------------------------------
+// Many filters: the same resampling split into segments of kResampleSegment
+// particles, one workgroup per segment and five launches, so large filters
+// use many compute units.  Every segment recomputes what it needs from the
+// per-segment partial results of its filter (at most 256 segments for 2^20
+// particles), so the integer results are those of resample_block.
+// ---------------------------------------------------------------------------
+struct SegView {
+  int32_t f;
+  int64_t lo, hi, n;  // segment particles [lo, hi) of a filter of n
+  int32_t first, last;  // the filter's segments [first, last)
+};
+
+__device__ __forceinline__ SegView seg_view(const FilterDev* filters, const ResampleSegs& sg, int32_t g) {
+  SegView v;
+  v.f = sg.seg_f[g];
+  v.n = filters[v.f].n_particles;
+  v.lo = sg.seg_lo[g];
+  v.hi = min(v.n, v.lo + (int64_t)kResampleSegment);
+  v.first = sg.fseg[v.f];
+  v.last = sg.fseg[v.f + 1];
+  return v;
+}
+
+__device__ __forceinline__ float filter_max(const ResampleSegs& sg, const SegView& v, bool* any) {
+  float m = -INFINITY;
+  bool a = false;
+  for (int32_t h = v.first; h < v.last; ++h) {
+    if (sg.seg_any[h]) {
+      const float x = sg.seg_max[h];
+      if (!a || x > m) m = x;
+      a = true;
+    }
+  }
+  *any = a;
+  return m;
+}
+
+// 1. segment maxima; slot marks cleared; poses staged
+__global__ __launch_bounds__(kResampleThreads) void k_rs_max(const FilterDev* __restrict__ filters,
+                                                             const int64_t* __restrict__ pre, ResampleSegs sg,
+                                                             float* stage, int32_t* idx) {
   __shared__ ResampleShared sh;
-  const int32_t f = blockIdx.x;
-  const FilterDev& fd = filters[f];
+  const SegView v = seg_view(filters, sg, blockIdx.x);
+  const FilterDev& fd = filters[v.f];
+  const int64_t base = pre[v.f];
+  float m = -INFINITY;
+  bool mine = false;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t i = v.lo + threadIdx.x + (int64_t)k * kResampleThreads;
+    if (i < v.hi) {
+      const float l = fd.logw[i];
+      if (isfinite(l) && (!mine || l > m)) {
+        m = l;
+        mine = true;
+      }
+      idx[base + i] = -1;
+      float* st = stage + 3 * base;
+      st[i] = fd.px[i];
+      st[v.n + i] = fd.py[i];
+      st[2 * v.n + i] = fd.pth[i];
+    }
+  }
+  bool any = false;
+  m = block_max_finite(m, mine, sh, &any);
+  if (threadIdx.x == 0) {
+    sg.seg_max[blockIdx.x] = m;
+    sg.seg_any[blockIdx.x] = any ? 1 : 0;
+  }
+}
+
+// 2. segment sums of the integer weights
+__global__ __launch_bounds__(kResampleThreads) void k_rs_sum(const FilterDev* __restrict__ filters, ResampleSegs sg) {
+  __shared__ ResampleShared sh;
+  const SegView v = seg_view(filters, sg, blockIdx.x);
+  const FilterDev& fd = filters[v.f];
+  bool any = false;
+  const float m = filter_max(sg, v, &any);
+  unsigned long long part = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t i = v.lo + threadIdx.x + (int64_t)k * kResampleThreads;
+    if (i < v.hi) part += weight_q(fd.logw[i], any, m);
+  }
+  const unsigned long long t = block_sum_u64(part, sh);
+  if (threadIdx.x == 0) sg.seg_sum[blockIdx.x] = t;
+}
+
+// 3. first output slot of every particle with copies
+__global__ __launch_bounds__(kResampleThreads) void k_rs_mark(const FilterDev* __restrict__ filters,
+                                                              const int64_t* __restrict__ pre,
+                                                              const uint32_t* __restrict__ u, ResampleSegs sg,
+                                                              int32_t* idx) {
+  __shared__ ResampleShared sh;
+  const int32_t g = blockIdx.x;
+  const SegView v = seg_view(filters, sg, g);
+  const FilterDev& fd = filters[v.f];
+  bool any = false;
+  const float m = filter_max(sg, v, &any);
+  unsigned long long T = 0, carry = 0;
+  for (int32_t h = v.first; h < v.last; ++h) {
+    T += sg.seg_sum[h];
+    if (h < g) carry += sg.seg_sum[h];
+  }
+  const unsigned long long s = ((unsigned long long)(u[v.f] >> 12) * T) >> 20;
+  const double inv_t = 1.0 / (double)T;
+  const int64_t i0 = v.lo + (int64_t)threadIdx.x * kItems;
+  float l[kItems];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) l[k] = i0 + k < v.hi ? fd.logw[i0 + k] : NAN;
+  uint32_t q[kItems];
+  unsigned long long local = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    q[k] = i0 + k < v.hi ? (uint32_t)weight_q(l[k], any, m) : 0u;
+    local += q[k];
+  }
+  unsigned long long chunk = 0;
+  unsigned long long before = carry + block_exscan_u64(local, sh, &chunk);
+  int32_t* fidx = idx + pre[v.f];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    if (q[k] > 0) {
+      const int64_t a0 = first_slot((unsigned long long)v.n, before, s, T, inv_t);
+      int64_t a1 = first_slot((unsigned long long)v.n, before + q[k], s, T, inv_t);
+      if (a1 > v.n) a1 = v.n;
+      if (a0 < a1) fidx[a0] = (int32_t)(i0 + k);
+    }
+    before += q[k];
+  }
+}
+
+// 4. largest mark in every output segment
+__global__ __launch_bounds__(kResampleThreads) void k_rs_segmax(const FilterDev* __restrict__ filters,
+                                                                const int64_t* __restrict__ pre, ResampleSegs sg,
+                                                                const int32_t* __restrict__ idx) {
+  __shared__ ResampleShared sh;
+  const SegView v = seg_view(filters, sg, blockIdx.x);
+  const int32_t* fidx = idx + pre[v.f];
+  int32_t mx = -1;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t j = v.lo + threadIdx.x + (int64_t)k * kResampleThreads;
+    if (j < v.hi) mx = max(mx, fidx[j]);
+  }
+  int32_t last = -1;
+  (void)block_excl_max_i32(mx, sh, &last);
+  if (threadIdx.x == 0) sg.seg_mmax[blockIdx.x] = last;
+}
+
+// 5. every output takes the last mark at or before it; poses gathered in place
+__global__ __launch_bounds__(kResampleThreads) void k_rs_fill(const FilterDev* __restrict__ filters,
+                                                              const int64_t* __restrict__ pre, ResampleSegs sg,
+                                                              const float* __restrict__ stage, int32_t* idx) {
+  __shared__ ResampleShared sh;
+  const int32_t g = blockIdx.x;
+  const SegView v = seg_view(filters, sg, g);
+  const FilterDev& fd = filters[v.f];
+  int32_t run = -1;
+  for (int32_t h = v.first; h < g; ++h) run = max(run, sg.seg_mmax[h]);
+  int32_t* fidx = idx + pre[v.f];
+  const float* st = stage + 3 * pre[v.f];
+  const int64_t j0 = v.lo + (int64_t)threadIdx.x * kItems;
+  int32_t w[kItems], local = -1;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    w[k] = j0 + k < v.hi ? fidx[j0 + k] : -1;
+    local = max(local, w[k]);
+  }
+  int32_t last = -1;
+  int32_t k_run = max(run, block_excl_max_i32(local, sh, &last));
   float* px = const_cast<float*>(fd.px);
   float* py = const_cast<float*>(fd.py);
   float* pt = const_cast<float*>(fd.pth);
-  resample_block(fd.logw, fd.n_particles, u[f], px, py, pt, px, py, pt, idx + pre[f], stage + 3 * pre[f], sh);
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    k_run = max(k_run, w[k]);
+    const int32_t src = k_run < 0 ? 0 : k_run;  // slot 0 is always marked (T > 0); kept in bounds regardless
+    if (j0 + k < v.hi) {
+      fidx[j0 + k] = src;
+      px[j0 + k] = st[src];
+      py[j0 + k] = st[v.n + src];
+      pt[j0 + k] = st[2 * v.n + src];
+    }
+  }
 }
 
 }  // namespace
@@ -419,11 +595,15 @@ cddt_status launch_motion_many(const FilterDev* d_filters, const int64_t* d_pre,
   return CDDT_OK;
 }
 
-cddt_status launch_resample_many(const FilterDev* d_filters, const int64_t* d_pre, int32_t nf,
-                                 const uint32_t* d_u, float* d_stage, int32_t* d_idx, hipStream_t st) {
-  if (nf <= 0) return CDDT_OK;
-  hipLaunchKernelGGL(k_resample_many, dim3((unsigned)nf), dim3(kResampleThreads), 0, st, d_filters, d_pre, d_u,
-                     d_stage, d_idx);
+cddt_status launch_resample_many(const FilterDev* d_filters, const int64_t* d_pre, const uint32_t* d_u,
+                                 float* d_stage, int32_t* d_idx, const ResampleSegs& segs, hipStream_t st) {
+  if (segs.nseg <= 0) return CDDT_OK;
+  const dim3 grid((unsigned)segs.nseg), block(kResampleThreads);
+  hipLaunchKernelGGL(k_rs_max, grid, block, 0, st, d_filters, d_pre, segs, d_stage, d_idx);
+  hipLaunchKernelGGL(k_rs_sum, grid, block, 0, st, d_filters, segs);
+  hipLaunchKernelGGL(k_rs_mark, grid, block, 0, st, d_filters, d_pre, d_u, segs, d_idx);
+  hipLaunchKernelGGL(k_rs_segmax, grid, block, 0, st, d_filters, d_pre, segs, (const int32_t*)d_idx);
+  hipLaunchKernelGGL(k_rs_fill, grid, block, 0, st, d_filters, d_pre, segs, (const float*)d_stage, d_idx);
   CDDT_HIP(hipGetLastError());
   return CDDT_OK;
 }

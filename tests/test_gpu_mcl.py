@@ -95,7 +95,7 @@ def test_resample_refuses_oversize():
         cddt.resample(z, 0, z, z, z)
 
 
-def _plan_setup(seed=0, n_filters=5):
+def _plan_setup(seed=0, n_filters=5, sizes=None):
     from paper_1705_01167_amd import cddt
     torch = _torch()
     rng = wl.rng_for(803, seed)
@@ -108,7 +108,7 @@ def _plan_setup(seed=0, n_filters=5):
         occ = wl.building_map(rng, side, side)
         n = int(rng.choice([108, 200, 360]))
         gm = cddt.Map(_dev(occ), n, buckets=(7 if f % 2 == 0 else None))
-        P = int(rng.integers(1, 4000))
+        P = int(rng.integers(1, 4000)) if sizes is None else int(sizes[f])
         px, py, pth = wl.free_poses(rng, occ, P)
         obs, _ = wl.observations(rng, occ, off_h, M)
         table = wl.beam_table(M, wl.beam_params(rng))
@@ -179,3 +179,25 @@ def test_plan_step_graph_replays_equal_eager():
             for tg, te in zip(kg[1][:3], ke[1][:3]):
                 assert torch.equal(tg, te), f"replay {rep}"
             assert torch.equal(kg[2], ke[2])
+
+
+def test_plan_step_segments_equal_oracle():
+    """Filters spanning several resampling segments (4096 particles each), odd sizes, in one plan."""
+    torch = _torch()
+    sizes = [1, 4095, 4096, 4097, 20000, 8193]
+    rng, plan, keep, host, off_h, M = _plan_setup(2, n_filters=len(sizes), sizes=sizes)
+    odom, u, noise = _step_inputs(rng, host)
+    before = [[t.cpu().numpy() for t in k[1][:3]] for k in keep]
+    plan.set_mcl(_dev(odom), _dev(u.view(np.int32)), _dev(noise))
+    plan.run_mcl()
+    torch.cuda.synchronize()
+    base = 0
+    for f, (k, h) in enumerate(zip(keep, host)):
+        P = h["P"]
+        nz = noise[3 * base: 3 * base + 3 * P]
+        mx, my, mt = oref.motion(*before[f], odom[3 * f: 3 * f + 3], nz[:P], nz[P:2 * P], nz[2 * P:])
+        lw = k[2].cpu().numpy()
+        idx, rx, ry, rt = oref.resample(lw, int(u[f]), mx, my, mt)
+        got = [t.cpu().numpy() for t in k[1][:3]]
+        assert (got[0] == rx).all() and (got[1] == ry).all() and (got[2] == rt).all(), f"filter {f} (n={P})"
+        base += P
