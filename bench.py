@@ -409,6 +409,7 @@ def run_updates(args) -> dict:
         ops.append((xs, ys, vals))
     stream = torch.cuda.Stream()
     upd_s = cast_s = 0.0
+    upd_each = []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for i, (xs, ys, vals) in enumerate(ops):
         t0 = time.perf_counter()
@@ -420,6 +421,7 @@ def run_updates(args) -> dict:
         stream.synchronize()
         if i >= args.warmup:
             upd_s += t1 - t0
+            upd_each.append(t1 - t0)
             cast_s += e0.elapsed_time(e1) / 1e3
     fresh = cddt.Map(t_dev(cur), n, buckets=BUCKETS)
     same = all((a == b).all() for a, b in zip(m.export(), fresh.export()))
@@ -429,6 +431,7 @@ def run_updates(args) -> dict:
             "value": rays * steps / (upd_s + cast_s), "unit": "rays/s", "steps": steps,
             "cast_rays_per_s": rays * steps / cast_s, "update_ms_per_step": upd_s / steps * 1e3,
             "cast_ms_per_step": cast_s / steps * 1e3, "update_equals_rebuild": bool(same),
+            "update_ms_median": float(np.median(upd_each) * 1e3), "update_ms_max": float(np.max(upd_each) * 1e3),
             "build_seconds": build_s, "rebuilds": info["rebuilds"],
             "config": {"workload": "updates: 4000^2 room/corridor map, 200 bins, each step 1000 random "
                                    "toggles (incremental update) then 1M particles x 61 rays as plain casts",

@@ -304,6 +304,10 @@ int32_t cddt_pair_offset(const float* offsets_h, int32_t n_rays) {
 
 cddt_status cddt_info(cddt_map m, cddt_stats* out_h) {
   if (!m || !out_h) return fail(CDDT_EINVAL, "cddt_info: NULL argument");
+  if (m->stats_stale) {  // the longest band after updates: one reduction over the band headers
+    CDDT_TRY(refresh_stats(m, nullptr));
+    m->stats_stale = false;
+  }
   cddt_stats s{};
   s.width = m->w;
   s.height = m->h;

@@ -416,6 +416,7 @@ cddt_status refresh_stats(cddt_map_s* m, hipStream_t st) {
   CDDT_HIP(hipStreamSynchronize(st));
   m->zero_points = (int64_t)hc.total_len;
   m->max_row_len = (int64_t)hc.max_len;
+  m->stats_stale = false;
   return CDDT_OK;
 }
 

@@ -64,6 +64,7 @@ struct cddt_map_s {
   int32_t* d_hdr = nullptr;      // rows * kNodeInts header nodes
   int32_t* d_zeros = nullptr;    // band regions
   int64_t capacity = 0, zero_points = 0, edge_cells = 0, max_row_len = 0, rebuilds = 0;
+  bool stats_stale = false;  // max_row_len not recomputed since the last update
   int64_t device_bytes = 0;
   // bucket index (CDDT_FLAG_BUCKETS): rows * nbk lines of 128 bytes
   int32_t blog2 = 0, nbk = 0;

@@ -47,21 +47,34 @@ struct UpdCounters {
   uint32_t touched;
   uint32_t overflow;
   uint32_t missing;   // a removal found no matching zero point (structure inconsistent)
-  uint32_t pad;
+  int32_t delta;      // change of the zero-point total when every record applies
 };
 
 __device__ __forceinline__ uint32_t pack_cell(int i, int j) { return (uint32_t)i | ((uint32_t)j << 16); }
 __device__ __forceinline__ int cell_i(uint32_t p) { return (int)(p & 0xffffu); }
 __device__ __forceinline__ int cell_j(uint32_t p) { return (int)(p >> 16); }
 
+// Op i changes its cell when no later op writes the same cell and its value
+// differs from the grid's.  The later ops are compared from LDS tiles.
+constexpr int kTile = 1024;
 __global__ void k_changed(const int32_t* __restrict__ xs, const int32_t* __restrict__ ys,
                           const uint8_t* __restrict__ vals, int32_t n, const uint8_t* __restrict__ occ, int w,
                           int2* __restrict__ changed, UpdCounters* ctr) {
+  __shared__ uint32_t tile[kTile];
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const bool live = i < n;
+  const uint32_t key = live ? pack_cell(xs[i], ys[i]) : 0xffffffffu;
+  bool later = false;
+  for (int32_t t0 = blockIdx.x * blockDim.x; t0 < n; t0 += kTile) {  // ops before this block never matter
+    __syncthreads();
+    for (int32_t k = threadIdx.x; k < kTile; k += blockDim.x)
+      tile[k] = t0 + k < n ? pack_cell(xs[t0 + k], ys[t0 + k]) : 0xfffffffeu;
+    __syncthreads();
+    const int32_t lim = min(kTile, n - t0);
+    for (int32_t k = 0; k < lim; ++k) later |= (t0 + k > i) && tile[k] == key;
+  }
+  if (!live || later) return;  // a later op wins
   const int32_t x = xs[i], y = ys[i];
-  for (int32_t j = i + 1; j < n; ++j)
-    if (xs[j] == x && ys[j] == y) return;  // a later op wins
   const uint8_t v = vals[i] ? 1 : 0;
   const uint8_t cur = occ[(size_t)y * w + x] ? 1 : 0;
   if (v == cur) return;
@@ -69,20 +82,33 @@ __global__ void k_changed(const int32_t* __restrict__ xs, const int32_t* __restr
   changed[k] = make_int2((int32_t)pack_cell(x, y), v);
 }
 
+// Cell (i, j) next to changed cell k is a candidate unless an earlier changed
+// cell is also next to it (the lowest-index changed neighbour owns it); the
+// earlier changed cells are compared from LDS tiles.
 __global__ void k_candidates(const int2* __restrict__ changed, const UpdCounters* ctr_in,
                              const uint8_t* __restrict__ occ, int w, int h, int full, int2* __restrict__ cand,
                              UpdCounters* ctr) {
+  __shared__ uint32_t tile[kTile];
   const uint32_t nc = ctr_in->changed;
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nc * 9u) return;
-  const uint32_t k = t / 9u, o = t - k * 9u;
-  const uint32_t pk = (uint32_t)changed[k].x;
+  const bool live = t < nc * 9u;
+  const uint32_t k = live ? t / 9u : 0u, o = live ? t - k * 9u : 0u;
+  const uint32_t pk = live ? (uint32_t)changed[k].x : 0u;
   const int i = cell_i(pk) + (int)(o % 3u) - 1, j = cell_j(pk) + (int)(o / 3u) - 1;
-  if (i < 0 || j < 0 || i >= w || j >= h) return;
-  for (uint32_t q = 0; q < k; ++q) {  // owned by the lowest-index changed cell next to it
-    const uint32_t pq = (uint32_t)changed[q].x;
-    if (abs(cell_i(pq) - i) <= 1 && abs(cell_j(pq) - j) <= 1) return;
+  bool owned = false;
+  const uint32_t k_max = (uint32_t)min((uint64_t)nc, ((uint64_t)blockIdx.x * blockDim.x + blockDim.x) / 9u + 1);
+  for (uint32_t q0 = 0; q0 < k_max; q0 += kTile) {
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < kTile; q += blockDim.x)
+      tile[q] = q0 + q < nc ? (uint32_t)changed[q0 + q].x : 0u;
+    __syncthreads();
+    const uint32_t lim = min((uint32_t)kTile, k > q0 ? k - q0 : 0u);
+    for (uint32_t q = 0; q < lim; ++q) {
+      const uint32_t pq = tile[q];
+      owned |= abs(cell_i(pq) - i) <= 1 && abs(cell_j(pq) - j) <= 1;
+    }
   }
+  if (!live || owned || i < 0 || j < 0 || i >= w || j >= h) return;
   const uint32_t slot = atomicAdd(&ctr->cand, 1u);
   cand[slot] = make_int2((int32_t)pack_cell(i, j), edge_cell(occ, w, h, i, j, full) ? 1 : 0);
 }
@@ -126,6 +152,8 @@ __global__ void k_records(const SliceDev* __restrict__ slices, const int2* __res
   const int32_t z = (int32_t)((i2 * sl.c + j2 * sl.s) >> 15);
   const uint32_t rm = ed.y < 0 ? 0x80000000u : 0u;
   const uint32_t base = atomicAdd(&ctr->records, (uint32_t)(hi - lo + 1));
+  // zero-point total change if every record applies (otherwise the structure is rebuilt)
+  atomicAdd(&ctr->delta, rm ? -(hi - lo + 1) : (hi - lo + 1));
   for (int32_t r = lo; r <= hi; ++r) {
     Rec q;
     q.row = (uint32_t)(sl.row_off + r) | rm;
@@ -433,10 +461,12 @@ cddt_status apply_update(cddt_map_s* m, const int32_t* xs_h, const int32_t* ys_h
       CDDT_TRY(build_structure(m, st));
       ++m->rebuilds;
     } else {
+      m->zero_points += hc.delta;  // exact: every applied band reported its length change
+      m->stats_stale = true;       // the longest band is recomputed when asked for
       CDDT_TRY(fill_buckets(m, touched, (int64_t)hc.touched, st));  // buckets of the edited bands
     }
   }
-  return refresh_stats(m, st);
+  return CDDT_OK;
 }
 
 }  // namespace cddt
