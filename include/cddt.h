@@ -136,7 +136,8 @@ cddt_status cddt_destroy(cddt_map m);
  * re-classified against the edge map and their zero points removed from or
  * inserted into every slice and band they cover, so the structure afterwards
  * equals cddt_create on the new grid (same rows as multisets).  A row that
- * runs out of slack triggers a rebuild of the whole structure.
+ * runs out of slack moves to a spare area at the end of the structure; only
+ * when that is used up is the whole structure rebuilt.
  *   xs_h, ys_h, values_h  host arrays of n_ops (n_ops >= 0).
  * Blocks until applied.  Errors: EINVAL if any op is off the map (none is
  * applied), ENOMEM, EDEVICE. */

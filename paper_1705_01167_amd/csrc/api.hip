@@ -78,6 +78,8 @@ void release_all(cddt_map_s* m) {
   if (m->d_bk) m->alloc.release(m->d_bk);
   if (m->d_row_start) m->alloc.release(m->d_row_start);
   if (m->d_bk_over) m->alloc.release(m->d_bk_over);
+  if (m->d_spare) m->alloc.release(m->d_spare);
+  m->d_spare = nullptr;
   m->d_occ = nullptr;
   m->d_slices = nullptr;
   m->d_bk = nullptr;

@@ -470,13 +470,25 @@ cddt_status build_structure(cddt_map_s* m, hipStream_t st) {
   CDDT_HIP(hipGetLastError());
   CDDT_HIP(hipMemcpyAsync(&hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
   CDDT_HIP(hipStreamSynchronize(st));
-  if (hc.total_cap >= (1ull << 32)) {
+
+  // a spare area (1/8 of the regions, at least 64 Ki slots; none for static
+  // maps) takes bands that outgrow their region during updates
+  const uint64_t used = hc.total_cap;
+  const uint64_t spare = no_slack ? 0 : (uint64_t)round_line(std::max<uint64_t>(used / 8, 65536));
+  if (used + spare >= (1ull << 32)) {
     free_structure(m);
     return fail(CDDT_ENOMEM, "structure needs more than 2^32 zero-point slots");
   }
-  m->capacity = (int64_t)hc.total_cap;
+  m->capacity = (int64_t)(used + spare);
+  m->spare_end = (int64_t)(used + spare);
   m->zero_points = (int64_t)hc.total_len;
   m->max_row_len = (int64_t)hc.max_len;
+  if (!m->d_spare) CDDT_TRY(m->alloc.alloc((void**)&m->d_spare, 8, "spare cursor"));
+  {
+    const unsigned long long cursor = used;
+    CDDT_HIP(hipMemcpyAsync(m->d_spare, &cursor, 8, hipMemcpyHostToDevice, st));
+    CDDT_HIP(hipStreamSynchronize(st));  // the host value goes out of scope
+  }
 
   // 4. fill, sort, finalize
   cddt_status st_alloc = m->alloc.alloc((void**)&m->d_zeros, (size_t)(m->capacity ? m->capacity : 1) * 4,

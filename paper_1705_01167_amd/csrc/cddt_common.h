@@ -65,6 +65,10 @@ struct cddt_map_s {
   int32_t* d_zeros = nullptr;    // band regions
   int64_t capacity = 0, zero_points = 0, edge_cells = 0, max_row_len = 0, rebuilds = 0;
   bool stats_stale = false;  // max_row_len not recomputed since the last update
+  // spare area at the end of the zero-point array, for bands that outgrow
+  // their region during updates: [capacity - spare, capacity); cursor on device
+  unsigned long long* d_spare = nullptr;
+  int64_t spare_end = 0;
   int64_t device_bytes = 0;
   // bucket index (CDDT_FLAG_BUCKETS): rows * nbk lines of 128 bytes
   int32_t blog2 = 0, nbk = 0;

@@ -312,9 +312,14 @@ __device__ int32_t bound(const int32_t* keys, int32_t len, int32_t z, bool upper
   return lo;
 }
 
+// A band whose edits exceed its capacity moves to a new region taken from the
+// spare area at the end of the zero-point array (1.5x its new length plus the
+// usual slack); only when the spare area is used up is the overflow flagged
+// (the host then re-lays the whole structure).
 __global__ void k_apply_bands(int32_t* __restrict__ hdr, int32_t* __restrict__ zeros,
                               const uint32_t* __restrict__ touched, const uint32_t* __restrict__ toff,
-                              uint32_t* __restrict__ rowcnt, const Rec* __restrict__ grp, UpdCounters* ctr) {
+                              uint32_t* __restrict__ rowcnt, const Rec* __restrict__ grp, UpdCounters* ctr,
+                              unsigned long long* __restrict__ spare_cursor, uint64_t spare_end) {
   const uint32_t t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (t >= ctr->touched) return;  // uniform per wave
   const int lane = threadIdx.x & 63;
@@ -322,17 +327,35 @@ __global__ void k_apply_bands(int32_t* __restrict__ hdr, int32_t* __restrict__ z
   const uint32_t cnt = rowcnt[row];
   const Rec* g = grp + toff[t];
   int32_t* node = hdr + (int64_t)row * kNodeInts;
-  const uint32_t start = (uint32_t)node[0];
+  uint32_t start = (uint32_t)node[0];
   int32_t len = node[1];
-  const int32_t cap = node[2];
+  int32_t cap = node[2];
   int32_t ins = 0, rem = 0;
   for (uint32_t k = 0; k < cnt; ++k) (g[k].row & 0x80000000u) ? ++rem : ++ins;
   if (len - rem + ins > cap) {
-    if (lane == 0) {
-      atomicOr(&ctr->overflow, 1u);
-      rowcnt[row] = 0;
+    const uint32_t need = (uint32_t)(len + ins);
+    const uint32_t ncap = key_capacity(need + (need >> 1), false);
+    const uint64_t slots = region_slots(ncap);
+    unsigned long long pos = 0;
+    if (lane == 0 && spare_cursor) pos = atomicAdd(spare_cursor, (unsigned long long)slots);
+    pos = __shfl(pos, 0);
+    if (spare_cursor == nullptr || pos + slots > spare_end) {
+      if (lane == 0) {
+        atomicOr(&ctr->overflow, 1u);
+        rowcnt[row] = 0;
+      }
+      return;
     }
-    return;
+    int32_t* nk = zeros + pos;
+    for (int32_t k = lane; k < len; k += 64) nk[k] = zeros[start + k];
+    __threadfence_block();
+    if (lane == 0) {
+      node[0] = (int32_t)pos;
+      node[2] = (int32_t)ncap;
+    }
+    __threadfence_block();
+    start = (uint32_t)pos;
+    cap = (int32_t)ncap;
   }
   int32_t* keys = zeros + start;
   for (uint32_t k = 0; k < cnt; ++k) {  // removals first: every one must find its key
@@ -448,7 +471,8 @@ cddt_status apply_update(cddt_map_s* m, const int32_t* xs_h, const int32_t* ys_h
     hipLaunchKernelGGL(k_group_fill, dim3(blocks_for(max_rec, kThreads)), dim3(kThreads), 0, st, rec,
                        (const UpdCounters*)ctr, slot, toff, local, (Rec*)m->upd_grp.ptr);
     hipLaunchKernelGGL(k_apply_bands, dim3(blocks_for(max_rec, 4)), dim3(kThreads), 0, st, m->d_hdr, m->d_zeros,
-                       touched, toff, rowcnt, (const Rec*)m->upd_grp.ptr, ctr);
+                       touched, toff, rowcnt, (const Rec*)m->upd_grp.ptr, ctr, m->d_spare,
+                       (uint64_t)m->spare_end);
     CDDT_HIP(hipGetLastError());
     CDDT_HIP(hipMemcpyAsync(&hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
     CDDT_HIP(hipStreamSynchronize(st));

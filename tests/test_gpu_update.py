@@ -91,6 +91,32 @@ def test_overflow_relays_structure():
     assert _same_export(gm2.export(), gm.export())
 
 
+def test_outgrown_bands_move_to_spare_area():
+    """Bands that outgrow their slack move to the spare area: no re-layout, same structure as a fresh build."""
+    occ = np.zeros((160, 200), np.uint8)
+    occ[0, :] = 1
+    for n in (108, 200):
+        for buckets in (None, 6):
+            gm = _map(occ, n, buckets=buckets)
+            cur = occ.copy()
+            rng = wl.rng_for(405, n)
+            for step in range(3):
+                # long walls: every row band of the axis slices gains ~200 zero points
+                j = int(rng.integers(10, 150))
+                xs = np.arange(200, dtype=np.int32)
+                ys = np.full(200, j, np.int32)
+                gm.update(xs, ys, np.ones(200, np.uint8))
+                wl.apply_ops(cur, xs, ys, np.ones(200, np.uint8))
+                assert gm.info()["rebuilds"] == 0
+                assert _same_export(gm.export(), oref.RefCDDT(cur, n).export())
+            q = wl.rng_for(406, n)
+            x = q.uniform(0, 200, 20000).astype(np.float32)
+            y = q.uniform(0, 160, 20000).astype(np.float32)
+            th = q.uniform(-4, 4, 20000).astype(np.float32)
+            assert (gm.cast(_dev(x), _dev(y), _dev(th), 300).cpu().numpy()
+                    == oref.RefCDDT(cur, n).cast(x, y, th, 300)).all()
+
+
 def test_chunked_ops_last_write_wins():
     """More ops than one device chunk (4096); a cell written in two chunks keeps the later value."""
     rng = wl.rng_for(402, 0)
