@@ -26,6 +26,12 @@
 //   range:                     min(M, (|Z - Xq| + 2^15) >> 16), M when no zero point.
 // Right shifts of negative values are arithmetic (floor), as C++20 defines.
 //
+// 16-bit reading (Sec. IV-C suggests 16-bit zero points at a small precision
+// loss): every zero point Z of slice s is replaced by the centre of its
+// 1/8-cell bin, zlo + 8192 floor((Z - zlo) / 8192) + 4096, where zlo is the
+// lowest projection of the map rectangle, (min(0, W 2^16 C) + min(0, H 2^16 S))
+// >> 30; queries, ranges and updates then proceed unchanged on those values.
+//
 // Build: g++ -std=c++17 -O2 -ffp-contract=off -shared -fPIC -pthread
 #include <algorithm>
 #include <cmath>
@@ -43,12 +49,14 @@ struct Slice {
   int64_t c, s;
   int64_t row_min;
   int64_t nrows;
+  int64_t zlo;  // lowest along-slice projection of the map rectangle (16-bit reading)
   std::vector<std::vector<int32_t>> rows;
 };
 
 struct RefMap {
   int w, h, n;
   bool full;
+  bool zp16;  // zero points rounded to 1/8-cell bins (the 16-bit reading)
   std::vector<uint8_t> occ;
   std::vector<Slice> slices;
   float k_scale;
@@ -83,9 +91,18 @@ void bands(int64_t i, int64_t j, int64_t c, int64_t s, int64_t* lo, int64_t* hi)
   *hi = (yc + hs - 1) >> 31;
 }
 
+// The stored zero point: exact, or under the 16-bit reading the centre of its
+// 1/8-cell bin counted from the slice's lowest projection zlo.
+int32_t stored_point(const RefMap& m, const Slice& sl, int64_t i, int64_t j) {
+  const int32_t z = zero_point(i, j, sl.c, sl.s);
+  if (!m.zp16) return z;
+  const int64_t b = ((int64_t)z - sl.zlo) >> 13;
+  return (int32_t)(sl.zlo + b * 8192 + 4096);
+}
+
 void touch(RefMap& m, int sidx, int i, int j, int sign) {
   Slice& sl = m.slices[sidx];
-  int32_t z = zero_point(i, j, sl.c, sl.s);
+  int32_t z = stored_point(m, sl, i, j);
   int64_t lo, hi;
   bands(i, j, sl.c, sl.s, &lo, &hi);
   for (int64_t r = lo; r <= hi; ++r) {
@@ -104,7 +121,7 @@ void build_slice(RefMap& m, int sidx, const std::vector<int32_t>& ci, const std:
   Slice& sl = m.slices[sidx];
   sl.rows.assign((size_t)sl.nrows, {});
   for (size_t e = 0; e < ci.size(); ++e) {  // every edge cell, appended to each band it covers
-    int32_t z = zero_point(ci[e], cj[e], sl.c, sl.s);
+    int32_t z = stored_point(m, sl, ci[e], cj[e]);
     int64_t lo, hi;
     bands(ci[e], cj[e], sl.c, sl.s, &lo, &hi);
     for (int64_t r = lo; r <= hi; ++r) sl.rows[(size_t)(r - sl.row_min)].push_back(z);
@@ -210,13 +227,15 @@ int32_t cast_brute(const RefMap& m, float x, float y, float theta, int32_t max_r
 
 extern "C" {
 
-void* ref_create(const uint8_t* occ, int32_t w, int32_t h, int32_t n, int32_t full_map, int32_t threads) {
+void* ref_create(const uint8_t* occ, int32_t w, int32_t h, int32_t n, int32_t full_map, int32_t threads,
+                 int32_t zp16) {
   if (w < 1 || h < 1 || n < 2 || (n & 1)) return nullptr;
   RefMap* m = new RefMap();
   m->w = w;
   m->h = h;
   m->n = n;
   m->full = full_map != 0;
+  m->zp16 = zp16 != 0;
   m->occ.assign(occ, occ + (size_t)w * h);
   m->k_scale = (float)((double)n / (2.0 * M_PI));
   int half = n / 2;
@@ -226,6 +245,10 @@ void* ref_create(const uint8_t* occ, int32_t w, int32_t h, int32_t n, int32_t fu
     Slice& sl = m->slices[s];
     sl.c = std::llround(std::cos(a) * 1073741824.0);
     sl.s = std::llround(std::sin(a) * 1073741824.0);
+    {
+      const int64_t wc = ((int64_t)w << 16) * sl.c, hs = ((int64_t)h << 16) * sl.s;
+      sl.zlo = (std::min<int64_t>(0, wc) + std::min<int64_t>(0, hs)) >> 30;
+    }
     int64_t lo = INT64_MAX, hi = INT64_MIN;
     for (int64_t X : {(int64_t)0, (int64_t)w})
       for (int64_t Y : {(int64_t)0, (int64_t)h}) {

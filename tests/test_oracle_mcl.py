@@ -159,3 +159,4 @@ def test_resample_special_cases():
     assert (np.abs(q.astype(np.int64) - ref_q.astype(np.int64)) <= 1).all()
     with pytest.raises(ValueError):
         oref.resample(np.zeros((1 << 20) + 1, np.float32), 0, np.zeros(1), np.zeros(1), np.zeros(1))
+
