@@ -73,7 +73,8 @@ enum {
 enum {
   CDDT_FLAG_FULL_MAP = 1u << 0, /* project every occupied cell, not only the edge map */
   CDDT_FLAG_STATIC = 1u << 1,   /* no per-row slack: smallest structure, updates rebuild */
-  CDDT_FLAG_BUCKETS = 1u << 2   /* add the bucket index described below */
+  CDDT_FLAG_BUCKETS = 1u << 2,  /* add the bucket index described below */
+  CDDT_FLAG_ZP16 = 1u << 3      /* 16-bit zero points in the bucket index (below) */
 };
 /* Bucket index (an addition to Sec. IV-A's bins, same results): every band
  * of every stored slice is cut into fixed-width buckets along the slice
@@ -87,6 +88,15 @@ enum {
  * width * height * 128 / 2^k bytes for a square map; kept current by
  * cddt_update.  k (4..10) goes in bits 8..11 of flags; 0 selects k = 7. */
 #define CDDT_BUCKET_LOG2(k) ((uint32_t)(k) << 8)
+/* 16-bit zero points (Sec. IV-C suggests them at a small precision loss;
+ * needs CDDT_FLAG_BUCKETS): the bucket lines hold each zero point as a 16-bit
+ * index of its 1/8-cell bin (60 per line, so buckets can be twice as wide for
+ * the same overflow rate), and every query answers as if each zero point Z of
+ * slice s were the centre of its bin, zlo + 8192 floor((Z - zlo) / 8192) +
+ * 4096 (Q16), zlo = (min(0, W 2^16 C) + min(0, H 2^16 S)) >> 30.  Ranges then
+ * differ from the exact ones by at most one cell except for rays that start
+ * within about 1/8 cell of a zero point of their band.  cddt_export still
+ * returns the exact zero points. */
 
 /* Device memory for the structure.  alloc returns a device pointer of at
  * least `bytes` bytes (NULL on failure); free releases it.  Both are called

@@ -18,6 +18,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EBUSY, EINTERNAL = 0, -1, -2, -3, -4, -5
 FLAG_FULL_MAP = 1
 FLAG_STATIC = 2
 FLAG_BUCKETS = 4
+FLAG_ZP16 = 8
 
 
 def bucket_flags(log2_width: int | None) -> int:
@@ -196,8 +197,10 @@ class Map:
     """A CDDT resident on the GPU (cddt_create / cddt_destroy)."""
 
     def __init__(self, occ, theta_bins: int, full_map: bool = False, static: bool = False,
-                 allocator: Allocator | None = None, stream=None, buckets: int | None = None):
-        """buckets: None for no bucket index, else log2 of the bucket width in cells (0: default 7)."""
+                 allocator: Allocator | None = None, stream=None, buckets: int | None = None,
+                 zp16: bool = False):
+        """buckets: None for no bucket index, else log2 of the bucket width in cells (0: default 7);
+        zp16: 16-bit zero points in the bucket index (the 16-bit reading; needs buckets)."""
         import torch
         _need(occ, torch.uint8, "occ")
         if occ.dim() != 2:
@@ -206,6 +209,7 @@ class Map:
         self.theta_bins = int(theta_bins)
         self._alloc = allocator       # keep callbacks alive
         flags = (FLAG_FULL_MAP if full_map else 0) | (FLAG_STATIC if static else 0) | bucket_flags(buckets)
+        flags |= FLAG_ZP16 if zp16 else 0
         h = C.c_void_p()
         _check(lib().cddt_create(_ptr(occ), self.width, self.height, self.theta_bins, flags,
                                  C.byref(allocator) if allocator is not None else None,

@@ -26,6 +26,7 @@ struct cddt_plan_s {
   cddt_tuning tuning{};
   int64_t total_tiles = 0;
   int32_t cus = 0;
+  bool zp16 = false;  // some filter's map has 16-bit zero points
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   // particle-filter step (motion, weights, resampling)
@@ -46,7 +47,7 @@ namespace cddt {
 // Counter reset plus one persistent launch over the tiles of n_filters filters.
 cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, int32_t n_filters,
                          int64_t total_tiles, const cddt_tuning& t, unsigned long long* d_counter, int32_t cus,
-                         hipStream_t st, bool counter_zeroed) {
+                         hipStream_t st, bool zp16, bool counter_zeroed) {
   if (!counter_zeroed) hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, d_counter);
   if (total_tiles > 0) {
     const unsigned blocks = (unsigned)std::max(1, cus * t.blocks_per_cu);
@@ -56,8 +57,12 @@ cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, in
     switch (t.search_mode) {
 #define CDDT_BATCH_K(KK)                                                                                        \
   case KK:                                                                                                      \
-    hipLaunchKernelGGL(k_batch<KK>, dim3(blocks), dim3(threads), lds, st, d_filters, d_prefix, n_filters,       \
-                       total_tiles, ppt, d_counter);                                                            \
+    if (zp16)                                                                                                   \
+      hipLaunchKernelGGL((k_batch<KK, true>), dim3(blocks), dim3(threads), lds, st, d_filters, d_prefix,        \
+                         n_filters, total_tiles, ppt, d_counter);                                               \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_batch<KK, false>), dim3(blocks), dim3(threads), lds, st, d_filters, d_prefix,       \
+                         n_filters, total_tiles, ppt, d_counter);                                               \
     break;
       CDDT_BATCH_K(1)
       CDDT_BATCH_K(2)
@@ -119,7 +124,7 @@ cddt_status apply_tuning(cddt_plan_s* p, const cddt_tuning& t, hipStream_t st) {
 
 cddt_status launch_plan(cddt_plan_s* p, hipStream_t st) {
   return launch_batch(p->d_filters, p->d_prefix, (int32_t)p->filters.size(), p->total_tiles, p->tuning,
-                      p->d_counter, p->cus, st);
+                      p->d_counter, p->cus, st, p->zp16);
 }
 
 void drop_graph(cddt_plan_s* p);
@@ -176,6 +181,7 @@ cddt_status cddt_plan_create(const cddt_filter* filters_h, int32_t n_filters, co
   cddt_plan_s* p = new cddt_plan_s();
   p->filters.assign(filters_h, filters_h + n_filters);
   for (auto& f : p->filters) p->fdev.push_back(filter_dev(f));
+  for (auto& f : p->fdev) p->zp16 = p->zp16 || f.map.zp16;
   p->cus = cddt_device_cus();
   if (p->cus <= 0) {
     delete p;

@@ -53,7 +53,9 @@ __host__ __device__ constexpr size_t tile_lds_bytes(int mode, int waves) {
   return (size_t)waves * tile_q(mode) * kWave * (sizeof(int2) + sizeof(int32_t));
 }
 
-template <int Mode>
+// Z: instantiated for batches that hold a map with 16-bit zero points in its
+// bucket lines (the plain instantiation has no code for them).
+template <int Mode, bool Z>
 __global__ __launch_bounds__(kMaxBatchThreads) void k_batch(const FilterDev* __restrict__ filters, const int64_t* __restrict__ prefix,
                         int32_t n_filters, int64_t total_tiles, int32_t ppt,
                         unsigned long long* __restrict__ counter) {
@@ -90,13 +92,13 @@ __global__ __launch_bounds__(kMaxBatchThreads) void k_batch(const FilterDev* __r
     if constexpr (Q > 0) {
       if (f.n_rays <= kWave) {
         for (int64_t p = p0; p < p1; p += Q)
-          wave_tile_logw<Q, tile_x2(Mode)>(f, p, (int32_t)min((int64_t)Q, p1 - p), jobs, codes);
+          wave_tile_logw<Q, tile_x2(Mode), Z>(f, p, (int32_t)min((int64_t)Q, p1 - p), jobs, codes);
         continue;
       }
     }
     constexpr int K = Q > 0 ? 0 : Mode;
     for (int64_t p = p0; p < p1; ++p) {
-      float lw = wave_particle_logw<K>(f.map, ldg(f.px + p), ldg(f.py + p), ldg(f.pth + p), f.offsets, f.obs,
+      float lw = wave_particle_logw<K, Z>(f.map, ldg(f.px + p), ldg(f.py + p), ldg(f.pth + p), f.offsets, f.obs,
                                        f.n_rays, f.pair_offset, f.table, f.max_range,
                                        f.ranges ? f.ranges + p * f.n_rays : nullptr);
       if (lane == 0) stg(f.logw + p, lw);

@@ -113,7 +113,7 @@ __global__ void k_bucket_fill(const int32_t* __restrict__ hdr, const int32_t* __
                               const SliceDev* __restrict__ slices, const int32_t* __restrict__ row_start,
                               int32_t half, int32_t shift, int32_t nbk, int32_t* __restrict__ bk,
                               const uint32_t* __restrict__ rows_list, uint64_t n_bands,
-                              unsigned long long* __restrict__ over, int partial) {
+                              unsigned long long* __restrict__ over, int partial, int zp16) {
   const int lane = threadIdx.x & 63;
   const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   for (uint64_t t = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < n_bands; t += n_waves) {
@@ -141,10 +141,24 @@ __global__ void k_bucket_fill(const int32_t* __restrict__ hdr, const int32_t* __
       const int32_t n_in = i1 - i0;
       int4* line = reinterpret_cast<int4*>(bk + ((int64_t)band * nbk + b) * kLineInts);
       const int old_over = partial ? (reinterpret_cast<const int32_t*>(line)[0] == kBucketOverflow) : 0;
-      if (n_in > kBucketKeys) {
+      const int cap_keys = zp16 ? kBucketKeys16 : kBucketKeys;
+      if (n_in > cap_keys) {
         line[0] = make_int4(kBucketOverflow, zlo, 0, 0);
 #pragma unroll
         for (int q = 1; q < 8; ++q) line[q] = make_int4(0, 0, 0, 0);
+      } else if (zp16) {  // bin centres of the neighbours; bins relative to the bucket's first bin
+        const int32_t base = b << (shift - kBinShift);
+        int32_t e[32];
+        e[0] = i0 > 0 ? ((keys[i0 - 1] - zlo) >> kBinShift) * 8192 + 4096 : INT_MIN;
+        e[1] = i1 < len ? ((keys[i1] - zlo) >> kBinShift) * 8192 + 4096 : INT_MAX;
+#pragma unroll
+        for (int k = 0; k < kBucketKeys16 / 2; ++k) {
+          const int32_t lo = 2 * k < n_in ? ((keys[i0 + 2 * k] - zlo) >> kBinShift) - base : 0xffff;
+          const int32_t hi = 2 * k + 1 < n_in ? ((keys[i0 + 2 * k + 1] - zlo) >> kBinShift) - base : 0xffff;
+          e[2 + k] = (int32_t)(((uint32_t)hi << 16) | (uint32_t)lo);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) line[q] = make_int4(e[4 * q], e[4 * q + 1], e[4 * q + 2], e[4 * q + 3]);
       } else {
         int32_t e[32];
         e[0] = i0 > 0 ? keys[i0 - 1] - zlo : INT_MIN;
@@ -154,7 +168,7 @@ __global__ void k_bucket_fill(const int32_t* __restrict__ hdr, const int32_t* __
 #pragma unroll
         for (int q = 0; q < 8; ++q) line[q] = make_int4(e[4 * q], e[4 * q + 1], e[4 * q + 2], e[4 * q + 3]);
       }
-      over_delta += (n_in > kBucketKeys ? 1 : 0) - old_over;
+      over_delta += (n_in > cap_keys ? 1 : 0) - old_over;
     }
     if (over_delta != 0) atomicAdd(over, (unsigned long long)(long long)over_delta);
   }
@@ -520,7 +534,7 @@ cddt_status fill_buckets(cddt_map_s* m, const uint32_t* rows_list, int64_t n_row
   hipLaunchKernelGGL(k_bucket_fill, dim3((unsigned)std::max<uint64_t>(blocks, 1)), dim3(256), 0, st,
                      (const int32_t*)m->d_hdr, (const int32_t*)m->d_zeros, (const SliceDev*)m->d_slices,
                      (const int32_t*)m->d_row_start, m->half, 16 + m->blog2, m->nbk, m->d_bk, rows_list,
-                     (uint64_t)n_rows, m->d_bk_over, partial);
+                     (uint64_t)n_rows, m->d_bk_over, partial, (m->flags & CDDT_FLAG_ZP16) ? 1 : 0);
   CDDT_HIP(hipGetLastError());
   unsigned long long over = 0;
   CDDT_HIP(hipMemcpyAsync(&over, m->d_bk_over, 8, hipMemcpyDeviceToHost, st));

@@ -94,7 +94,7 @@ struct cddt_map_s {
     m.k_scale = k_scale;
     m.bshift = d_bk ? 16 + blog2 : 0;
     m.nbk = nbk;
-    m.pad = 0;
+    m.zp16 = d_bk && (flags & CDDT_FLAG_ZP16) ? 1 : 0;
     return m;
   }
 };
@@ -116,7 +116,7 @@ cddt_status launch_weight(const FilterDev& f, hipStream_t st);
 // stream order.
 cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, int32_t n_filters,
                          int64_t total_tiles, const cddt_tuning& t, unsigned long long* d_counter, int32_t cus,
-                         hipStream_t st, bool counter_zeroed = false);
+                         hipStream_t st, bool zp16, bool counter_zeroed = false);
 cddt_status check_tuning(const cddt_tuning& t);
 // mcl.hip: motion of every particle of every filter (particle offsets d_pre,
 // n_filters + 1 entries), and one resampling workgroup per filter.

@@ -29,7 +29,7 @@ struct MapDev {
   float k_scale;             // (float)(n / (2 pi))
   int32_t bshift;            // bucket width 2^bshift in Q16 units
   int32_t nbk;               // buckets per band
-  int32_t pad;
+  int32_t zp16;              // bucket lines hold 16-bit zero points (1/8-cell bins)
 };
 
 // One filter of a batched step (device copy of cddt_filter plus its map).
@@ -73,6 +73,12 @@ constexpr int kMaxRays = 1024;
 // relative to the slice's zlo.  An overflowing bucket holds kBucketOverflow
 // in [0] and zlo in [1].
 constexpr int kBucketKeys = 30;
+// With 16-bit zero points a line holds [0] the previous key's bin centre,
+// [1] the next key's bin centre (both relative to zlo, INT_MIN / INT_MAX for
+// none) and [2..31] 60 bin indices relative to the bucket's first bin, two per
+// word (low half first), ascending, padded with 0xffff.
+constexpr int kBucketKeys16 = 60;
+constexpr int kBinShift = 13;  // 1/8 cell in Q16
 constexpr int32_t kBucketOverflow = INT_MIN + 1;
 constexpr int kBucketLog2Default = 7;
 // Bytes of device memory holding the persistent batched kernel's tile counters.

@@ -13,6 +13,8 @@ constexpr int kWeightK = 0;
 
 // One wave takes 64 consecutive rays at a time (lane = ray); the loop bound is
 // the same for every lane of a wave so the cooperative search stays converged.
+// Z: instantiated for maps with 16-bit zero points in their bucket lines.
+template <bool Z>
 __global__ __launch_bounds__(kCastThreads) void k_cast(MapDev m, const float* __restrict__ x,
                                                        const float* __restrict__ y,
                                                        const float* __restrict__ th, int64_t n,
@@ -24,7 +26,7 @@ __global__ __launch_bounds__(kCastThreads) void k_cast(MapDev m, const float* __
     const int64_t i = c * kWave + lane;
     const bool active = i < n;
     const float xi = active ? ldg(x + i) : 0.0f, yi = active ? ldg(y + i) : 0.0f, ti = active ? ldg(th + i) : 0.0f;
-    const int32_t r = wave_cast<kCastK>(m, active, xi, yi, ti, max_range);
+    const int32_t r = wave_cast<kCastK, Z>(m, active, xi, yi, ti, max_range);
     if (active) stg(out + i, r);
   }
 }
@@ -32,6 +34,7 @@ __global__ __launch_bounds__(kCastThreads) void k_cast(MapDev m, const float* __
 // Q particles per wave through the phased tile routine (ray layouts of <= 64 rays).
 constexpr int kWeightQ = 4;
 constexpr int64_t kTileMinParticles = 1 << 17;
+template <bool Z>
 __global__ __launch_bounds__(kWeightThreads) void k_weight_tiles(FilterDev f) {
   __shared__ int2 jobs[kWeightThreads / kWave][kWeightQ * kWave];
   __shared__ int32_t codes[kWeightThreads / kWave][kWeightQ * kWave];
@@ -39,13 +42,14 @@ __global__ __launch_bounds__(kWeightThreads) void k_weight_tiles(FilterDev f) {
   const int64_t p0 = ((int64_t)blockIdx.x * (kWeightThreads / kWave) + wave) * kWeightQ;
   if (p0 >= f.n_particles) return;  // whole wave leaves together
   const int32_t cnt = (int32_t)min((int64_t)kWeightQ, f.n_particles - p0);
-  wave_tile_logw<kWeightQ, false>(f, p0, cnt, jobs[wave], codes[wave]);
+  wave_tile_logw<kWeightQ, false, Z>(f, p0, cnt, jobs[wave], codes[wave]);
 }
 
+template <bool Z>
 __global__ __launch_bounds__(kWeightThreads) void k_weight(FilterDev f) {
   const int64_t p = (int64_t)blockIdx.x * (kWeightThreads / kWave) + (threadIdx.x >> 6);
   if (p >= f.n_particles) return;  // whole wave leaves together
-  float lw = wave_particle_logw<kWeightK>(f.map, ldg(f.px + p), ldg(f.py + p), ldg(f.pth + p), f.offsets, f.obs,
+  float lw = wave_particle_logw<kWeightK, Z>(f.map, ldg(f.px + p), ldg(f.py + p), ldg(f.pth + p), f.offsets, f.obs,
                                           f.n_rays, f.pair_offset,
                                 f.table, f.max_range, f.ranges ? f.ranges + p * f.n_rays : nullptr);
   if ((threadIdx.x & 63) == 0) stg(f.logw + p, lw);
@@ -58,7 +62,10 @@ cddt_status launch_cast(const MapDev& m, const float* x, const float* y, const f
   if (n == 0) return CDDT_OK;
   int64_t blocks = (n + kCastThreads - 1) / kCastThreads;
   if (blocks > (1 << 16)) blocks = 1 << 16;
-  hipLaunchKernelGGL(k_cast, dim3((unsigned)blocks), dim3(kCastThreads), 0, st, m, x, y, th, n, max_range, out);
+  if (m.zp16)
+    hipLaunchKernelGGL(k_cast<true>, dim3((unsigned)blocks), dim3(kCastThreads), 0, st, m, x, y, th, n, max_range, out);
+  else
+    hipLaunchKernelGGL(k_cast<false>, dim3((unsigned)blocks), dim3(kCastThreads), 0, st, m, x, y, th, n, max_range, out);
   CDDT_HIP(hipGetLastError());
   return CDDT_OK;
 }
@@ -70,11 +77,17 @@ cddt_status launch_weight(const FilterDev& f, hipStream_t st) {
   if (f.n_rays <= kWave && f.n_particles >= kTileMinParticles) {
     const int64_t blocks = (f.n_particles + per_block * kWeightQ - 1) / (per_block * kWeightQ);
     if (blocks > 0x7fffffffLL) return fail(CDDT_EINVAL, "too many particles for one launch");
-    hipLaunchKernelGGL(k_weight_tiles, dim3((unsigned)blocks), dim3(kWeightThreads), 0, st, f);
+    if (f.map.zp16)
+      hipLaunchKernelGGL(k_weight_tiles<true>, dim3((unsigned)blocks), dim3(kWeightThreads), 0, st, f);
+    else
+      hipLaunchKernelGGL(k_weight_tiles<false>, dim3((unsigned)blocks), dim3(kWeightThreads), 0, st, f);
   } else {
     const int64_t blocks = (f.n_particles + per_block - 1) / per_block;
     if (blocks > 0x7fffffffLL) return fail(CDDT_EINVAL, "too many particles for one launch");
-    hipLaunchKernelGGL(k_weight, dim3((unsigned)blocks), dim3(kWeightThreads), 0, st, f);
+    if (f.map.zp16)
+      hipLaunchKernelGGL(k_weight<true>, dim3((unsigned)blocks), dim3(kWeightThreads), 0, st, f);
+    else
+      hipLaunchKernelGGL(k_weight<false>, dim3((unsigned)blocks), dim3(kWeightThreads), 0, st, f);
   }
   CDDT_HIP(hipGetLastError());
   return CDDT_OK;

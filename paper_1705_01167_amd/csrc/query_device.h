@@ -312,32 +312,43 @@ __device__ __forceinline__ Line32 load_line(const int32_t* p) {
   return L;
 }
 
+// Nearest entries by unsigned minima instead of compare-and-select chains
+// (whose 64-bit lane masks would all be held in scalar registers at once).
+// Modulo 2^32, d = e - x - 1 puts the entries above x first: e > x exactly
+// when d < INT_MAX - x, and then e = x + 1 + d.  Likewise d = x - e puts the
+// entries <= x first: e <= x exactly when d <= x + 2^31, and then e = x - d.
+// Both hold for every pair of int32 values.
+__device__ __forceinline__ uint32_t above_gap(int32_t e, int32_t x) { return (uint32_t)e - (uint32_t)x - 1u; }
+__device__ __forceinline__ uint32_t below_gap(int32_t e, int32_t x) { return (uint32_t)x - (uint32_t)e; }
+__device__ __forceinline__ bool has_above(uint32_t d, int32_t x) { return d < (uint32_t)INT_MAX - (uint32_t)x; }
+__device__ __forceinline__ bool has_below(uint32_t d, int32_t x) { return d <= ((uint32_t)x ^ 0x80000000u); }
+
 // Entries First..31 of a sorted line (unused slots hold INT_MAX): c = number
 // of entries <= x, prv = the largest of them (INT_MIN if none), nxt = the
 // smallest entry > x, or `carried` when every entry is <= x.
 template <int First>
 __device__ __forceinline__ void scan_line(const Line32& L, int32_t x, int32_t carried, int32_t& c, int32_t& nxt,
                                           int32_t& prv) {
+  uint32_t dn = 0xffffffffu, dp = 0xffffffffu;
   c = 0;
-  prv = INT_MIN;
-  nxt = L.e[First];
 #pragma unroll
   for (int i = First; i < 32; ++i) {
-    const bool le = L.e[i] <= x;
-    c = le ? i + 1 - First : c;
-    prv = le ? L.e[i] : prv;
-    nxt = le ? (i + 1 < 32 ? L.e[i + 1] : carried) : nxt;
+    dn = min(dn, above_gap(L.e[i], x));
+    dp = min(dp, below_gap(L.e[i], x));
+    c += L.e[i] <= x ? 1 : 0;
   }
+  nxt = has_above(dn, x) ? (int32_t)((uint32_t)x + 1u + dn) : carried;
+  prv = has_below(dp, x) ? (int32_t)((uint32_t)x - dp) : INT_MIN;
 }
 
 // Band search by one lane: the header line, then one line per level below the
 // top.  Same results as wave_search; no cross-lane traffic, and a wave keeps up
 // to 64 independent lines in flight.  Lanes without a query return max_range.
-__device__ __forceinline__ void tree_search(const MapDev& m, bool want, int32_t row, int32_t x, int32_t max_range,
-                                            int32_t& r_succ, int32_t& r_pred) {
-  r_succ = max_range;
-  r_pred = max_range;
-  if (!want) return;
+// The band's nearest keys around x: succ = smallest key > x, pred = largest
+// key < x, or <= x when strict_pred is false (INT_MAX / INT_MIN when there is
+// none).
+__device__ __forceinline__ void tree_keys(const MapDev& m, int32_t row, int32_t x, bool strict_pred, int32_t& succ,
+                                          int32_t& pred) {
   Line32 L = load_line(m.hdr + (int64_t)row * kNodeInts);
   const uint32_t start = (uint32_t)L.e[0];
   const int32_t len = L.e[1];
@@ -351,15 +362,27 @@ __device__ __forceinline__ void tree_search(const MapDev& m, bool want, int32_t 
     scan_line<0>(L, x, nxt, lc, nxt, prv);
     c = blk * kLineInts + lc;
   }
-  if (c < len) r_succ = range_of((int64_t)nxt - x, max_range);
+  succ = c < len ? nxt : INT_MAX;
+  pred = INT_MIN;
   if (c > 0) {
     int32_t pv = prv;
-    if (pv == x) {  // rare: x equals a key; find the last key strictly below it
+    if (strict_pred && pv == x) {  // rare: x equals a key; find the last key strictly below it
       const int32_t lb = lower_bound_i32(m.zeros + start, c, x);
       pv = lb > 0 ? ldg(m.zeros + start + lb - 1) : INT_MIN;
     }
-    if (pv != INT_MIN) r_pred = range_of((int64_t)x - pv, max_range);
+    pred = pv;
   }
+}
+
+__device__ __forceinline__ void tree_search(const MapDev& m, bool want, int32_t row, int32_t x, int32_t max_range,
+                                            int32_t& r_succ, int32_t& r_pred) {
+  r_succ = max_range;
+  r_pred = max_range;
+  if (!want) return;
+  int32_t succ, pred;
+  tree_keys(m, row, x, true, succ, pred);
+  if (succ != INT_MAX) r_succ = range_of((int64_t)succ - x, max_range);
+  if (pred != INT_MIN) r_pred = range_of((int64_t)x - pred, max_range);
 }
 
 // Bucket-index search by one lane: the bucket line of (band, x) gives the
@@ -374,40 +397,136 @@ __device__ __forceinline__ int32_t bucket_of(const MapDev& m, int32_t x) {
 
 __device__ __forceinline__ void scan_bucket(const Line32& L, int32_t x, int32_t max_range, int32_t& r_succ,
                                             int32_t& r_pred) {
-  int32_t prv = L.e[0], nxt = INT_MAX;
+  // x > INT_MIN here (x >= 0 relative to the bucket origin), so the keys < x
+  // are the keys <= x - 1
+  const int32_t xm = x - 1;
+  uint32_t dn = 0xffffffffu, dp = 0xffffffffu;
 #pragma unroll
-  for (int i = 2; i < 32; ++i) prv = L.e[i] < x ? L.e[i] : prv;   // ascending: the last one below x
-#pragma unroll
-  for (int i = 31; i >= 2; --i) nxt = L.e[i] > x ? L.e[i] : nxt;  // descending: the first one above x
+  for (int i = 2; i < 32; ++i) {
+    dn = min(dn, above_gap(L.e[i], x));
+    dp = min(dp, below_gap(L.e[i], xm));
+  }
+  int32_t nxt = has_above(dn, x) ? (int32_t)((uint32_t)x + 1u + dn) : INT_MAX;
+  const int32_t prv = has_below(dp, xm) ? (int32_t)((uint32_t)xm - dp) : L.e[0];
   nxt = nxt < L.e[1] ? nxt : L.e[1];
   r_succ = nxt != INT_MAX ? range_of((int64_t)nxt - x, max_range) : max_range;
   r_pred = prv != INT_MIN ? range_of((int64_t)x - prv, max_range) : max_range;
 }
 
+// 16-bit zero points: a key of bin B stands for the bin centre B 8192 + 4096
+// (relative to zlo).  The successor is the first key of bin >= bmin, the
+// predecessor the last key of bin <= bmax, with bmin / bmax the bins whose
+// centres lie strictly above / below x.
+__device__ __forceinline__ int32_t bin_min_above(int32_t x) { return ((x - 4096) >> kBinShift) + 1; }
+__device__ __forceinline__ int32_t bin_max_below(int32_t x) { return ((x - 4096 + 8191) >> kBinShift) - 1; }
+__device__ __forceinline__ int32_t bin_centre(int32_t b) { return b * 8192 + 4096; }
+
+__device__ __forceinline__ void scan_bucket16(const MapDev& m, const Line32& L, int32_t x, int32_t b,
+                                              int32_t max_range, int32_t& r_succ, int32_t& r_pred) {
+  const int32_t base = b << (m.bshift - kBinShift);  // first bin of the bucket
+  const int32_t ts = bin_min_above(x) - base, tp = bin_max_below(x) - base;
+  // One pass of unsigned minima, each word read once: the smallest key >= ts
+  // and the largest key <= tp.  Keys, ts and tp are far below 2^31 in
+  // magnitude, so v - ts (tp - v) is below 2^31 as an unsigned number exactly
+  // when v >= ts (v <= tp).  Padding 0xffff lies above every bin of a bucket:
+  // it never counts as <= tp, and as the only key >= ts it reads as none.
+  uint32_t ds = 0xffffffffu, dp = 0xffffffffu;
+#pragma unroll
+  for (int i = 2; i < 32; ++i) {
+    const uint32_t w = (uint32_t)L.e[i];
+    const uint32_t lo = w & 0xffffu, hi = w >> 16;
+    ds = min(ds, min(lo - (uint32_t)ts, hi - (uint32_t)ts));
+    dp = min(dp, min((uint32_t)tp - lo, (uint32_t)tp - hi));
+  }
+  const int32_t s16 = ds < 0x80000000u ? ts + (int32_t)ds : 0xffff;
+  const int32_t p16 = dp < 0x80000000u ? tp - (int32_t)dp : -1;
+  const int32_t nxt = s16 != 0xffff ? bin_centre(base + s16) : L.e[1];
+  const int32_t prv = p16 >= 0 ? bin_centre(base + p16) : L.e[0];
+  r_succ = nxt != INT_MAX ? range_of((int64_t)nxt - x, max_range) : max_range;
+  r_pred = prv != INT_MIN ? range_of((int64_t)x - prv, max_range) : max_range;
+}
+
+// Overflowing bucket: the band's exact keys by one tree descent, in a kernel
+// that also serves maps with 16-bit zero points (z).  32-bit keys: the nearest
+// keys around x, as tree_search.  16-bit: the first key >= t1 (the start of
+// bin bmin) and the last key < t2 (the end of bin bmax), mapped to their bin
+// centres; t2 = t1 unless x is itself a bin centre (t2 = t1 - 8192), the one
+// case that takes a second descent.  A single call site of tree_keys keeps the
+// kernel's register count down.
+__device__ __forceinline__ void tree_search_any(const MapDev& m, bool z, int32_t row, int32_t x, int32_t zlo,
+                                                int32_t max_range, int32_t& r_succ, int32_t& r_pred) {
+  const int32_t t1 = zlo + bin_min_above(x) * 8192, t2 = zlo + (bin_max_below(x) + 1) * 8192;
+  int32_t xt = z ? t1 - 1 : x + zlo, succ = INT_MAX, pred = INT_MIN;
+  for (int pass = 0; pass < 2; ++pass) {
+    int32_t s1, p1;
+    tree_keys(m, row, xt, !z, s1, p1);
+    if (pass == 0) succ = s1;
+    pred = p1;
+    if (!z || t2 == t1) break;
+    xt = t2 - 1;
+  }
+  int32_t vs = succ, vp = pred, xr = x + zlo;
+  if (z) {  // bin centres, relative to zlo like x
+    vs = bin_centre((succ - zlo) >> kBinShift);
+    vp = bin_centre((pred - zlo) >> kBinShift);
+    xr = x;
+  }
+  r_succ = succ != INT_MAX ? range_of((int64_t)vs - xr, max_range) : max_range;
+  r_pred = pred != INT_MIN ? range_of((int64_t)xr - vp, max_range) : max_range;
+}
+
+// Z: the caller's kernel handles maps with 16-bit zero points (Z = false
+// compiles the 32-bit line scan alone; the host never hands such a kernel a
+// map with 16-bit zero points).
+template <bool Z>
+__device__ __forceinline__ void scan_bucket_any(const MapDev& m, const Line32& L, int32_t row, int32_t x,
+                                                int32_t max_range, int32_t& r_succ, int32_t& r_pred) {
+  // The scan runs before the overflow test and its results pass through an
+  // empty asm statement, which the compiler cannot move into a branch: this
+  // keeps all eight loads of the line ahead of the test.  (Otherwise the
+  // compiler moves the loads of words 4..31 into the branch that reads them,
+  // and every search waits for two memory round trips in a row.)  An
+  // overflowing line's scan result is discarded.
+  if constexpr (Z) {
+    if (m.zp16)
+      scan_bucket16(m, L, x, bucket_of(m, x), max_range, r_succ, r_pred);
+    else
+      scan_bucket(L, x, max_range, r_succ, r_pred);
+  } else {
+    scan_bucket(L, x, max_range, r_succ, r_pred);
+  }
+  asm volatile("" : "+v"(r_succ), "+v"(r_pred));
+  if (L.e[0] == kBucketOverflow) {
+    if constexpr (Z)
+      tree_search_any(m, m.zp16, row, x, L.e[1], max_range, r_succ, r_pred);
+    else
+      tree_search(m, true, row, x + L.e[1], max_range, r_succ, r_pred);
+  }
+}
+
+template <bool Z>
 __device__ __forceinline__ void bucket_search(const MapDev& m, bool want, int32_t row, int32_t x, int32_t max_range,
                                               int32_t& r_succ, int32_t& r_pred) {
   r_succ = max_range;
   r_pred = max_range;
   if (!want) return;
   const Line32 L = load_line(m.bk + ((int64_t)row * m.nbk + bucket_of(m, x)) * kLineInts);
-  if (L.e[0] == kBucketOverflow) {
-    tree_search(m, true, row, x + L.e[1], max_range, r_succ, r_pred);
-    return;
-  }
-  scan_bucket(L, x, max_range, r_succ, r_pred);
+  scan_bucket_any<Z>(m, L, row, x, max_range, r_succ, r_pred);
 }
 
 // Band search by one lane (bucket index when the map has one, else the
 // band's search lines).
+template <bool Z>
 __device__ __forceinline__ void lane_search(const MapDev& m, bool want, int32_t row, int32_t x, int32_t max_range,
                                             int32_t& r_succ, int32_t& r_pred) {
   if (m.bk)
-    bucket_search(m, want, row, x, max_range, r_succ, r_pred);
+    bucket_search<Z>(m, want, row, x, max_range, r_succ, r_pred);
   else
     tree_search(m, want, row, x, max_range, r_succ, r_pred);
 }
 
 // Two bucket searches by one lane, both lines in flight together.
+template <bool Z>
 __device__ __forceinline__ void bucket_search2(const MapDev& m, bool wa, int32_t ra, int32_t xa, bool wb, int32_t rb,
                                                int32_t xb, int32_t max_range, int32_t& sa, int32_t& pa, int32_t& sb,
                                                int32_t& pb) {
@@ -416,28 +535,19 @@ __device__ __forceinline__ void bucket_search2(const MapDev& m, bool wa, int32_t
   Line32 A, B;
   if (wa) A = load_line(m.bk + ((int64_t)ra * m.nbk + bucket_of(m, xa)) * kLineInts);
   if (wb) B = load_line(m.bk + ((int64_t)rb * m.nbk + bucket_of(m, xb)) * kLineInts);
-  if (wa) {
-    if (A.e[0] == kBucketOverflow)
-      tree_search(m, true, ra, xa + A.e[1], max_range, sa, pa);
-    else
-      scan_bucket(A, xa, max_range, sa, pa);
-  }
-  if (wb) {
-    if (B.e[0] == kBucketOverflow)
-      tree_search(m, true, rb, xb + B.e[1], max_range, sb, pb);
-    else
-      scan_bucket(B, xb, max_range, sb, pb);
-  }
+  if (wa) scan_bucket_any<Z>(m, A, ra, xa, max_range, sa, pa);
+  if (wb) scan_bucket_any<Z>(m, B, rb, xb, max_range, sb, pb);
 }
 
 // Two independent band searches by one lane, their line requests issued side
 // by side (the second search's lines are in flight while the first's are
 // scanned).  Same results as two lane_search calls.
+template <bool Z>
 __device__ __forceinline__ void lane_search2(const MapDev& m, bool wa, int32_t ra, int32_t xa, bool wb, int32_t rb,
                                              int32_t xb, int32_t max_range, int32_t& sa, int32_t& pa, int32_t& sb,
                                              int32_t& pb) {
   if (m.bk) {
-    bucket_search2(m, wa, ra, xa, wb, rb, xb, max_range, sa, pa, sb, pb);
+    bucket_search2<Z>(m, wa, ra, xa, wb, rb, xb, max_range, sa, pa, sb, pb);
     return;
   }
   sa = pa = sb = pb = max_range;
@@ -497,21 +607,21 @@ __device__ __forceinline__ void lane_search2(const MapDev& m, bool wa, int32_t r
 // Search strategy: K = 0 one lane per search, K >= 1 eight lanes per search
 // with K searches per group in flight (maps with a bucket index always search
 // one lane per bucket line).
-template <int K>
+template <int K, bool Z>
 __device__ __forceinline__ void band_search(const MapDev& m, bool want, int32_t row, int32_t xq, int32_t max_range,
                                             int32_t& r_succ, int32_t& r_pred) {
   if constexpr (K == 0) {
-    lane_search(m, want, row, xq, max_range, r_succ, r_pred);
+    lane_search<Z>(m, want, row, xq, max_range, r_succ, r_pred);
   } else {
     if (m.bk)
-      bucket_search(m, want, row, xq, max_range, r_succ, r_pred);
+      bucket_search<Z>(m, want, row, xq, max_range, r_succ, r_pred);
     else
       wave_search<K>(m, want, row, xq, max_range, r_succ, r_pred);
   }
 }
 
 // Plain casts for up to 64 rays, one per lane (Sec. IV-B).  All lanes call.
-template <int K>
+template <int K, bool Z>
 __device__ __forceinline__ int32_t wave_cast(const MapDev& m, bool active, float x, float y, float theta,
                                              int32_t max_range) {
   bool valid = active && (fabsf(theta) < 1e6f) && pose_inside(m, x, y);
@@ -529,7 +639,7 @@ __device__ __forceinline__ int32_t wave_cast(const MapDev& m, bool active, float
     l = land(m, fwd ? k : k - m.half, xf, yf);
   }
   int32_t rs, rp;
-  band_search<K>(m, valid, l.row, l.xq, max_range, rs, rp);
+  band_search<K, Z>(m, valid, l.row, l.xq, max_range, rs, rp);
   return valid ? (fwd ? rs : rp) : 0;
 }
 
@@ -541,7 +651,7 @@ __device__ __forceinline__ int32_t wave_cast(const MapDev& m, bool active, float
 // Radial pairing (Sec. IV-C): if pair_off > 0, lane l + pair_off reuses the
 // search of lane l when both rays land in the same slice (their bins differ by
 // n/2): every search returns both the successor and the predecessor.
-template <int K>
+template <int K, bool Z>
 __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, float py, float pth,
                                                     const float* __restrict__ offsets,
                                                     const int32_t* __restrict__ obs, int32_t n_rays,
@@ -584,7 +694,7 @@ __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, f
     Landing l{0, 0};
     if (valid && !paired) l = land(m, slice, xf, yf);
     int32_t rs, rp;
-    band_search<K>(m, valid && !paired, l.row, l.xq, max_range, rs, rp);
+    band_search<K, Z>(m, valid && !paired, l.row, l.xq, max_range, rs, rp);
     const int32_t opk = __shfl(rs | (rp << 16), src_c);  // partner's (successor, predecessor) ranges
     int32_t range = 0;
     if (valid) range = paired ? (fwd ? (opk & 0xffff) : (int32_t)((uint32_t)opk >> 16)) : (fwd ? rs : rp);
@@ -612,7 +722,7 @@ __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, f
 // jobs / codes: this wave's LDS slices of Q * 64 entries (a job's first word
 // is overwritten by its packed result).  With Lanes2 each lane runs two
 // searches of a round side by side (128 searches per round).
-template <int Q, int Lanes2>
+template <int Q, int Lanes2, bool Z>
 __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, int32_t cnt, int2* jobs,
                                                int32_t* codes) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -686,7 +796,7 @@ __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, i
       const int2 qa = wa ? jobs[ja] : make_int2(0, 0);
       const int2 qb = wb ? jobs[jb] : make_int2(0, 0);
       int32_t sa, pa, sb, pb;
-      lane_search2(m, wa, qa.x, qa.y, wb, qb.x, qb.y, M, sa, pa, sb, pb);
+      lane_search2<Z>(m, wa, qa.x, qa.y, wb, qb.x, qb.y, M, sa, pa, sb, pb);
       if (wa) jobs[ja].x = sa | (pa << 16);  // the result replaces its job
       if (wb) jobs[jb].x = sb | (pb << 16);
     }
@@ -696,7 +806,7 @@ __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, i
       const bool w = j < njobs;
       const int2 jb = w ? jobs[j] : make_int2(0, 0);
       int32_t rs, rp;
-      lane_search(m, w, jb.x, jb.y, M, rs, rp);
+      lane_search<Z>(m, w, jb.x, jb.y, M, rs, rp);
       if (w) jobs[j].x = rs | (rp << 16);
     }
   }

@@ -95,6 +95,7 @@ struct cddt_server_s {
   cddt_server_config cfg{};
   int32_t cus = 0;
   int device = 0;
+  bool zp16 = false;  // some map has 16-bit zero points
   std::vector<cddt::Lane> lanes;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -180,7 +181,7 @@ cddt_status launch_lane(const cddt_server_s* s, Lane& L) {
                      n16);
   CDDT_TRY(launch_batch((const FilterDev*)L.d_arena, (const int64_t*)(L.d_arena + desc_bytes), (int32_t)nb,
                         prefix[nb], s->cfg.tuning, (unsigned long long*)(L.d_arena + counter_off), s->cus,
-                        L.stream, /*counter_zeroed=*/true));
+                        L.stream, s->zp16, /*counter_zeroed=*/true));
   CDDT_HIP(hipMemcpyAsync(L.h_out, L.d_arena + in_bytes, out_floats * 4, hipMemcpyDeviceToHost, L.stream));
   CDDT_HIP(hipEventRecord(L.done, L.stream));
   return CDDT_OK;
@@ -389,6 +390,7 @@ cddt_status cddt_server_create(const cddt_map* maps_h, int32_t n_maps, const flo
   for (int32_t i = 0; i < n_maps; ++i) {
     ServedMap m{};
     m.map = maps_h[i];
+    s->zp16 = s->zp16 || (m.map->flags & CDDT_FLAG_ZP16) != 0;
     m.n_rays = n_rays_h[i];
     m.pair = cddt_pair_offset(offsets_h[i], n_rays_h[i]);
     m.table = log_tables[i];

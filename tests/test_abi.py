@@ -54,6 +54,9 @@ def test_validation_needs_no_gpu():
                          C.byref(out)) == cddt.EINVAL
     assert L.cddt_create(occ, 5, 5, 8, cddt.bucket_flags(3), None, None, C.byref(out)) == cddt.EINVAL
     assert L.cddt_create(occ, 5, 5, 8, cddt.bucket_flags(11), None, None, C.byref(out)) == cddt.EINVAL
+    # 16-bit zero points live in the bucket lines: the flag alone is refused
+    assert L.cddt_create(occ, 5, 5, 8, cddt.FLAG_ZP16, None, None, C.byref(out)) == cddt.EINVAL
+    assert b"BUCKETS" in L.cddt_last_error()
     assert L.cddt_create(None, 5, 5, 8, 0, None, None, C.byref(out)) == cddt.EINVAL
     assert not out.value
     assert L.cddt_cast(None, None, None, None, 1, 5, None, None) == cddt.EINVAL
