@@ -32,6 +32,16 @@
 // lowest projection of the map rectangle, (min(0, W 2^16 C) + min(0, H 2^16 S))
 // >> 30; queries, ranges and updates then proceed unchanged on those values.
 //
+// PCDDT reading (Sec. IV-C, pruning: cast from every state, drop every zero
+// point no cast returns): the states are the centres (i + 1/2, j + 1/2) of the
+// free cells under every theta bin, each bin at its centre angle 2 pi k / n.
+// A state of bin s < n/2 returns the successor of its Xq in its band of slice
+// s, one of bin s + n/2 the predecessor, so a pruned band holds the distinct
+// values that some state returns, ascending.  Casts from those states answer
+// as on the unpruned structure; other queries may see past a dropped point.
+// An update of a pruned map rebuilds and prunes again from the new grid (the
+// paper leaves incremental edits of a pruned structure open).
+//
 // Build: g++ -std=c++17 -O2 -ffp-contract=off -shared -fPIC -pthread
 #include <algorithm>
 #include <cmath>
@@ -56,7 +66,8 @@ struct Slice {
 struct RefMap {
   int w, h, n;
   bool full;
-  bool zp16;  // zero points rounded to 1/8-cell bins (the 16-bit reading)
+  bool zp16;   // zero points rounded to 1/8-cell bins (the 16-bit reading)
+  bool prune;  // PCDDT: only the zero points some discrete state's cast returns
   std::vector<uint8_t> occ;
   std::vector<Slice> slices;
   float k_scale;
@@ -191,19 +202,66 @@ int32_t finish(bool found, int64_t d, int32_t max_range) {
   return (int32_t)std::min<int64_t>(max_range, v);
 }
 
-int32_t cast_cddt(const RefMap& m, float x, float y, float theta, int32_t max_range) {
-  Prepared p = prepare(m, x, y, theta);
-  if (!p.valid) return 0;
+// The zero point a valid query's cast returns (Sec. IV-B: successor, or with
+// the theta + pi symmetry of Sec. IV-C predecessor); false when there is none.
+bool cast_search(const RefMap& m, const Prepared& p, int32_t* z) {
   const Slice& sl = m.slices[p.sidx];
   const std::vector<int32_t>& row = sl.rows[(size_t)(p.r - sl.row_min)];
   if (p.sigma > 0) {
     auto it = std::upper_bound(row.begin(), row.end(), (int32_t)p.xq);
-    if (it == row.end()) return max_range;
-    return finish(true, (int64_t)*it - p.xq, max_range);
+    if (it == row.end()) return false;
+    *z = *it;
+    return true;
   }
   auto it = std::lower_bound(row.begin(), row.end(), (int32_t)p.xq);
-  if (it == row.begin()) return max_range;
-  return finish(true, p.xq - (int64_t)*(it - 1), max_range);
+  if (it == row.begin()) return false;
+  *z = *(it - 1);
+  return true;
+}
+
+int32_t cast_cddt(const RefMap& m, float x, float y, float theta, int32_t max_range) {
+  Prepared p = prepare(m, x, y, theta);
+  if (!p.valid) return 0;
+  int32_t z = 0;
+  if (!cast_search(m, p, &z)) return max_range;
+  return finish(true, p.sigma > 0 ? (int64_t)z - p.xq : p.xq - (int64_t)z, max_range);
+}
+
+// PCDDT: cast from every state whose bin is s or s + n/2 (the two directions
+// stored in slice s), collect the zero points returned per band, and keep
+// only those (distinct, ascending).
+void prune_slice(RefMap& m, int sidx) {
+  Slice& sl = m.slices[sidx];
+  std::vector<std::vector<int32_t>> used(sl.rows.size());
+  for (int k : {sidx, sidx + m.n / 2}) {
+    const float theta = (float)(2.0 * M_PI * k / m.n);
+    for (int j = 0; j < m.h; ++j)
+      for (int i = 0; i < m.w; ++i) {
+        if (occupied(m, i, j)) continue;
+        const Prepared p = prepare(m, (float)i + 0.5f, (float)j + 0.5f, theta);
+        if (!p.valid || p.sidx != sidx || (p.sigma > 0) != (k == sidx)) std::abort();  // state outside its bin
+        int32_t z = 0;
+        if (cast_search(m, p, &z)) used[(size_t)(p.r - sl.row_min)].push_back(z);
+      }
+  }
+  for (size_t b = 0; b < used.size(); ++b) {
+    std::vector<int32_t>& u = used[b];
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+  }
+  sl.rows.swap(used);
+}
+
+void build_all(RefMap& m, int threads) {
+  const int half = m.n / 2;
+  collect_edges(m);
+  parallel_for(half, threads, [&](int64_t a, int64_t b) {
+    for (int64_t s = a; s < b; ++s) build_slice(m, (int)s, m.edge_i, m.edge_j);
+  });
+  if (m.prune)
+    parallel_for(half, threads, [&](int64_t a, int64_t b) {
+      for (int64_t s = a; s < b; ++s) prune_slice(m, (int)s);
+    });
 }
 
 int32_t cast_brute(const RefMap& m, float x, float y, float theta, int32_t max_range) {
@@ -228,14 +286,16 @@ int32_t cast_brute(const RefMap& m, float x, float y, float theta, int32_t max_r
 extern "C" {
 
 void* ref_create(const uint8_t* occ, int32_t w, int32_t h, int32_t n, int32_t full_map, int32_t threads,
-                 int32_t zp16) {
+                 int32_t zp16, int32_t prune) {
   if (w < 1 || h < 1 || n < 2 || (n & 1)) return nullptr;
+  if (zp16 && prune) return nullptr;  // the two readings are not combined
   RefMap* m = new RefMap();
   m->w = w;
   m->h = h;
   m->n = n;
   m->full = full_map != 0;
   m->zp16 = zp16 != 0;
+  m->prune = prune != 0;
   m->occ.assign(occ, occ + (size_t)w * h);
   m->k_scale = (float)((double)n / (2.0 * M_PI));
   int half = n / 2;
@@ -259,10 +319,7 @@ void* ref_create(const uint8_t* occ, int32_t w, int32_t h, int32_t n, int32_t fu
     sl.row_min = lo;
     sl.nrows = hi - lo + 1;
   }
-  collect_edges(*m);
-  parallel_for(half, threads, [&](int64_t a, int64_t b) {
-    for (int64_t s = a; s < b; ++s) build_slice(*m, (int)s, m->edge_i, m->edge_j);
-  });
+  build_all(*m, threads);
   return m;
 }
 
@@ -369,6 +426,10 @@ int32_t ref_update(void* h, const int32_t* xs, const int32_t* ys, const uint8_t*
     if (was != now) flips.emplace_back(c.second, c.first, now ? 1 : -1);
   }
   m.occ.swap(next);
+  if (m.prune) {  // PCDDT: rebuild and prune from the new grid
+    build_all(m, 1);
+    return (int32_t)flips.size();
+  }
   for (auto& f : flips)
     if (std::get<2>(f) < 0)
       for (int s = 0; s < m.n / 2; ++s) touch(m, s, std::get<0>(f), std::get<1>(f), -1);

@@ -244,6 +244,7 @@ class PlainCDDT:
     occ: np.ndarray
     n: int
     full_map: bool = False
+    prune: bool = False                # PCDDT: keep only zero points that some discrete state's cast returns
     tabs: tuple = field(init=False)
     row_min: list = field(init=False)
     nrows: list = field(init=False)
@@ -259,6 +260,9 @@ class PlainCDDT:
             lo, hi = row_range(self.tabs[0][s], self.tabs[1][s], w, h)
             self.row_min.append(lo)
             self.nrows.append(hi - lo + 1)
+        self._build()
+
+    def _build(self) -> None:
         self.rows = [[[] for _ in range(self.nrows[s])] for s in range(self.n // 2)]
         cells = (self.occ != 0) if self.full_map else edge_map(self.occ)
         jj, ii = np.nonzero(cells)
@@ -267,6 +271,33 @@ class PlainCDDT:
                 self._touch(s, i, j, +1)
             for row in self.rows[s]:                       # initialise each bin
                 row.sort()
+        if self.prune:
+            self._prune()
+
+    def _search(self, q: Query):
+        """The zero point a valid query's cast returns (successor or predecessor), or None."""
+        row = self.rows[q.s][q.r - self.row_min[q.s]]
+        if q.sigma > 0:
+            k = bisect.bisect_right(row, q.xq)           # first zero point > Xq
+            return None if k == len(row) else row[k]
+        k = bisect.bisect_left(row, q.xq) - 1            # last zero point < Xq
+        return None if k < 0 else row[k]
+
+    def _prune(self) -> None:
+        """PCDDT (Sec. IV-C): cast from every discrete state and keep, per band, only the
+        zero points some cast returns.  States: the centre of every free cell under every
+        theta bin, at the bin's centre angle 2 pi k / n."""
+        used = [[set() for _ in range(self.nrows[s])] for s in range(self.n // 2)]
+        free = np.argwhere(self.occ == 0)
+        for k in range(self.n):
+            theta = np.float32(2.0 * math.pi * k / self.n)
+            for j, i in free.tolist():
+                q = prepare(self.occ, self.n, self.tabs, np.float32(i + 0.5), np.float32(j + 0.5), theta)
+                assert q.valid and q.k == k, "a state fell outside its bin"
+                z = self._search(q)
+                if z is not None:
+                    used[q.s][q.r - self.row_min[q.s]].add(z)
+        self.rows = [[sorted(u) for u in per_slice] for per_slice in used]
 
     def _touch(self, s: int, i: int, j: int, sign: int) -> None:
         c, sn = self.tabs[0][s], self.tabs[1][s]
@@ -285,14 +316,8 @@ class PlainCDDT:
         q = prepare(self.occ, self.n, self.tabs, x, y, theta)
         if not q.valid:
             return 0
-        row = self.rows[q.s][q.r - self.row_min[q.s]]
-        if q.sigma > 0:
-            k = bisect.bisect_right(row, q.xq)           # first zero point > Xq
-            d = None if k == len(row) else row[k] - q.xq
-        else:
-            k = bisect.bisect_left(row, q.xq) - 1        # last zero point < Xq
-            d = None if k < 0 else q.xq - row[k]
-        return finish(d, max_range)
+        z = self._search(q)
+        return finish(None if z is None else q.sigma * (z - q.xq), max_range)
 
     def cast_many(self, xs, ys, ths, max_range: int) -> np.ndarray:
         return np.array([self.cast(a, b, t, max_range) for a, b, t in zip(xs, ys, ths)], np.int64)
@@ -303,12 +328,17 @@ class PlainCDDT:
         Ops are applied in order (last write per cell wins).  Only cells within
         one step (8-neighbourhood) of a changed cell can change edge status; each
         such cell whose status flipped has its zero points removed from or
-        inserted into every slice and every band it covers.
+        inserted into every slice and every band it covers.  A pruned (PCDDT)
+        structure is rebuilt and pruned again from the new grid.
         """
         h, w = self.occ.shape
         new = self.occ.copy()
         for x, y, v in zip(list(xs), list(ys), list(vals)):
             new[int(y), int(x)] = 1 if v else 0
+        if self.prune:
+            self.occ = new
+            self._build()
+            return
         changed = np.argwhere(new != self.occ)
         cand = set()
         for j, i in changed.tolist():

@@ -44,7 +44,7 @@ def lib():
         L = C.CDLL(LIB)
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         L.ref_create.restype = vp
-        L.ref_create.argtypes = [vp, i32, i32, i32, i32, i32, i32]
+        L.ref_create.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32]
         L.ref_destroy.argtypes = [vp]
         L.ref_edge_count.restype = i64
         L.ref_edge_count.argtypes = [vp]
@@ -80,12 +80,14 @@ class RefCDDT:
     """Plain CDDT built on the host: sorted std::vector rows, std::upper/lower_bound."""
 
     def __init__(self, occ: np.ndarray, theta_bins: int, full_map: bool = False, threads: int = 1,
-                 zp16: bool = False):
-        """zp16: the 16-bit reading (zero points rounded to 1/8-cell bin centres), see cddt_ref.cpp."""
+                 zp16: bool = False, prune: bool = False):
+        """zp16: the 16-bit reading (zero points rounded to 1/8-cell bin centres); prune: the PCDDT
+        reading (only the zero points some discrete state's cast returns).  See cddt_ref.cpp."""
         self.occ = np.ascontiguousarray(occ, dtype=np.uint8)
         self.h, self.w = self.occ.shape
         self.n = int(theta_bins)
-        self.h_ = lib().ref_create(_p(self.occ), self.w, self.h, self.n, int(full_map), int(threads), int(zp16))
+        self.h_ = lib().ref_create(_p(self.occ), self.w, self.h, self.n, int(full_map), int(threads), int(zp16),
+                                   int(prune))
         if not self.h_:
             raise ValueError("invalid oracle arguments")
 
