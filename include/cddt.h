@@ -74,7 +74,8 @@ enum {
   CDDT_FLAG_FULL_MAP = 1u << 0, /* project every occupied cell, not only the edge map */
   CDDT_FLAG_STATIC = 1u << 1,   /* no per-row slack: smallest structure, updates rebuild */
   CDDT_FLAG_BUCKETS = 1u << 2,  /* add the bucket index described below */
-  CDDT_FLAG_ZP16 = 1u << 3      /* 16-bit zero points in the bucket index (below) */
+  CDDT_FLAG_ZP16 = 1u << 3,     /* 16-bit zero points in the bucket index (below) */
+  CDDT_FLAG_PRUNE = 1u << 4     /* PCDDT: drop zero points no grid state returns (below) */
 };
 /* Bucket index (an addition to Sec. IV-A's bins, same results): every band
  * of every stored slice is cut into fixed-width buckets along the slice
@@ -97,6 +98,15 @@ enum {
  * differ from the exact ones by at most one cell except for rays that start
  * within about 1/8 cell of a zero point of their band.  cddt_export still
  * returns the exact zero points. */
+/* PCDDT (Sec. IV-C, pruning; needs CDDT_FLAG_STATIC, not with
+ * CDDT_FLAG_ZP16): after construction one cast is made from every discrete
+ * state, the centre (i + 1/2, j + 1/2) of every free cell under every theta
+ * bin, and each band keeps only the distinct zero points some state returned
+ * (30-40% fewer on room maps).  Casts from those states (and from those
+ * centres at any theta) return exactly what the full structure returns; other
+ * queries may see past a dropped zero point.  cddt_update applies the ops to
+ * the grid and rebuilds and prunes the whole structure; cddt_export returns
+ * the pruned bands. */
 
 /* Device memory for the structure.  alloc returns a device pointer of at
  * least `bytes` bytes (NULL on failure); free releases it.  Both are called

@@ -19,6 +19,7 @@ FLAG_FULL_MAP = 1
 FLAG_STATIC = 2
 FLAG_BUCKETS = 4
 FLAG_ZP16 = 8
+FLAG_PRUNE = 16
 
 
 def bucket_flags(log2_width: int | None) -> int:
@@ -198,9 +199,10 @@ class Map:
 
     def __init__(self, occ, theta_bins: int, full_map: bool = False, static: bool = False,
                  allocator: Allocator | None = None, stream=None, buckets: int | None = None,
-                 zp16: bool = False):
+                 zp16: bool = False, prune: bool = False):
         """buckets: None for no bucket index, else log2 of the bucket width in cells (0: default 7);
-        zp16: 16-bit zero points in the bucket index (the 16-bit reading; needs buckets)."""
+        zp16: 16-bit zero points in the bucket index (the 16-bit reading; needs buckets);
+        prune: PCDDT, only the zero points some grid state's cast returns (implies static)."""
         import torch
         _need(occ, torch.uint8, "occ")
         if occ.dim() != 2:
@@ -210,6 +212,7 @@ class Map:
         self._alloc = allocator       # keep callbacks alive
         flags = (FLAG_FULL_MAP if full_map else 0) | (FLAG_STATIC if static else 0) | bucket_flags(buckets)
         flags |= FLAG_ZP16 if zp16 else 0
+        flags |= (FLAG_PRUNE | FLAG_STATIC) if prune else 0
         h = C.c_void_p()
         _check(lib().cddt_create(_ptr(occ), self.width, self.height, self.theta_bins, flags,
                                  C.byref(allocator) if allocator is not None else None,

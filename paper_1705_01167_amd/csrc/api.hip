@@ -188,11 +188,15 @@ cddt_status cddt_create(const uint8_t* occ, int32_t width, int32_t height, int32
     return fail(CDDT_EINVAL, "cddt_create: width and height must be in 1..16384");
   if (theta_bins < 2 || theta_bins > kMaxBins || (theta_bins & 1))
     return fail(CDDT_EINVAL, "cddt_create: theta_bins must be even and in 2..8192");
-  if (flags & ~(uint32_t)(CDDT_FLAG_FULL_MAP | CDDT_FLAG_STATIC | CDDT_FLAG_BUCKETS | CDDT_FLAG_ZP16 |
+  if (flags & ~(uint32_t)(CDDT_FLAG_FULL_MAP | CDDT_FLAG_STATIC | CDDT_FLAG_BUCKETS | CDDT_FLAG_ZP16 | CDDT_FLAG_PRUNE |
                          CDDT_BUCKET_LOG2(15)))
     return fail(CDDT_EINVAL, "cddt_create: unknown flag bits");
   if ((flags & CDDT_FLAG_ZP16) && !(flags & CDDT_FLAG_BUCKETS))
     return fail(CDDT_EINVAL, "cddt_create: 16-bit zero points need CDDT_FLAG_BUCKETS");
+  if ((flags & CDDT_FLAG_PRUNE) && !(flags & CDDT_FLAG_STATIC))
+    return fail(CDDT_EINVAL, "cddt_create: CDDT_FLAG_PRUNE needs CDDT_FLAG_STATIC");
+  if ((flags & CDDT_FLAG_PRUNE) && (flags & CDDT_FLAG_ZP16))
+    return fail(CDDT_EINVAL, "cddt_create: CDDT_FLAG_PRUNE and CDDT_FLAG_ZP16 are not combined");
   int32_t blog2 = (int32_t)((flags >> 8) & 15u);
   if (!(flags & CDDT_FLAG_BUCKETS) && blog2)
     return fail(CDDT_EINVAL, "cddt_create: a bucket width needs CDDT_FLAG_BUCKETS");

@@ -440,7 +440,7 @@ cddt_status build_structure(cddt_map_s* m, hipStream_t st) {
   free_structure(m);
   const int64_t cells = (int64_t)m->w * m->h;
   const int64_t R = m->rows;
-  Temp ctr_t(&m->alloc), edges_t(&m->alloc), cnt_t(&m->alloc), tiles_t(&m->alloc), big_t(&m->alloc);
+  Temp ctr_t(&m->alloc), edges_t(&m->alloc), cnt_t(&m->alloc), big_t(&m->alloc);
   CDDT_TRY(ctr_t.get(sizeof(BuildCounters), "build counters"));
   BuildCounters* ctr = (BuildCounters*)ctr_t.p;
   CDDT_HIP(hipMemsetAsync(ctr, 0, sizeof(BuildCounters), st));
@@ -474,20 +474,11 @@ cddt_status build_structure(cddt_map_s* m, hipStream_t st) {
 
   // 3. band layout
   CDDT_TRY(m->alloc.alloc((void**)&m->d_hdr, (size_t)R * kNodeInts * 4, "band header nodes"));
-  const int64_t ntiles = (R + kScanTile - 1) / kScanTile;
-  CDDT_TRY(tiles_t.get((size_t)ntiles * 8, "scan tiles"));
-  uint64_t* tiles = (uint64_t*)tiles_t.p;
-  hipLaunchKernelGGL(k_tile_sum, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, cnt, R, no_slack, tiles);
-  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, st, tiles, ntiles, ctr);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, cnt, R, no_slack,
-                     (const uint64_t*)tiles, m->d_hdr, ctr);
-  CDDT_HIP(hipGetLastError());
-  CDDT_HIP(hipMemcpyAsync(&hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
-  CDDT_HIP(hipStreamSynchronize(st));
+  uint64_t used = 0;
+  CDDT_TRY(layout_bands(m, cnt, m->d_hdr, no_slack != 0, &used, &hc.total_len, &hc.max_len, st));
 
   // a spare area (1/8 of the regions, at least 64 Ki slots; none for static
   // maps) takes bands that outgrow their region during updates
-  const uint64_t used = hc.total_cap;
   const uint64_t spare = no_slack ? 0 : (uint64_t)round_line(std::max<uint64_t>(used / 8, 65536));
   if (used + spare >= (1ull << 32)) {
     free_structure(m);
@@ -519,10 +510,41 @@ cddt_status build_structure(cddt_map_s* m, hipStream_t st) {
                      R, (uint32_t*)big_t.p, ctr);
   hipLaunchKernelGGL(k_sort_large, dim3(2048), dim3(256), 0, st, (const int32_t*)m->d_hdr, m->d_zeros,
                      (const uint32_t*)big_t.p, (const BuildCounters*)ctr);
-  hipLaunchKernelGGL(k_finalize, dim3(grid_for(R, 4)), dim3(256), 0, st, m->d_hdr, m->d_zeros, R);
+  CDDT_TRY(finalize_bands(m->d_hdr, m->d_zeros, R, st));
+  if (m->flags & CDDT_FLAG_PRUNE) CDDT_TRY(prune_structure(m, st));
+  if (m->d_bk) return fill_buckets(m, nullptr, R, st);
+  return CDDT_OK;
+}
+
+cddt_status layout_bands(cddt_map_s* m, uint32_t* cnt, int32_t* hdr, bool no_slack, uint64_t* total_cap,
+                         uint64_t* total_len, uint64_t* max_len, hipStream_t st) {
+  const int64_t R = m->rows;
+  Temp ctr_t(&m->alloc), tiles_t(&m->alloc);
+  CDDT_TRY(ctr_t.get(sizeof(BuildCounters), "layout counters"));
+  BuildCounters* ctr = (BuildCounters*)ctr_t.p;
+  CDDT_HIP(hipMemsetAsync(ctr, 0, sizeof(BuildCounters), st));
+  const int64_t ntiles = (R + kScanTile - 1) / kScanTile;
+  CDDT_TRY(tiles_t.get((size_t)ntiles * 8, "scan tiles"));
+  uint64_t* tiles = (uint64_t*)tiles_t.p;
+  const int ns = no_slack ? 1 : 0;
+  hipLaunchKernelGGL(k_tile_sum, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, cnt, R, ns, tiles);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, st, tiles, ntiles, ctr);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, cnt, R, ns,
+                     (const uint64_t*)tiles, hdr, ctr);
+  CDDT_HIP(hipGetLastError());
+  BuildCounters hc{};
+  CDDT_HIP(hipMemcpyAsync(&hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
+  CDDT_HIP(hipStreamSynchronize(st));
+  *total_cap = hc.total_cap;
+  *total_len = hc.total_len;
+  *max_len = hc.max_len;
+  return CDDT_OK;
+}
+
+cddt_status finalize_bands(int32_t* hdr, int32_t* zeros, int64_t rows, hipStream_t st) {
+  if (rows > 0) hipLaunchKernelGGL(k_finalize, dim3(grid_for(rows, 4)), dim3(256), 0, st, hdr, zeros, rows);
   CDDT_HIP(hipGetLastError());
   CDDT_HIP(hipStreamSynchronize(st));
-  if (m->d_bk) return fill_buckets(m, nullptr, R, st);
   return CDDT_OK;
 }
 

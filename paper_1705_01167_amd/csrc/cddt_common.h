@@ -107,6 +107,15 @@ cddt_status build_structure(cddt_map_s* m, hipStream_t st);
 cddt_status fill_buckets(cddt_map_s* m, const uint32_t* rows_list, int64_t n_rows, hipStream_t st);
 void free_structure(cddt_map_s* m);
 cddt_status refresh_stats(cddt_map_s* m, hipStream_t st);
+// Band layout from per-band lengths cnt[rows] (reset to 0 on return): header
+// words {start, len, cap} of every band in hdr, with or without slack; the
+// total slots, total length and longest band come back.  Blocks.
+cddt_status layout_bands(cddt_map_s* m, uint32_t* cnt, int32_t* hdr, bool no_slack, uint64_t* total_cap,
+                         uint64_t* total_len, uint64_t* max_len, hipStream_t st);
+// Sample levels, padding and header top levels of every band (keys in place).
+cddt_status finalize_bands(int32_t* hdr, int32_t* zeros, int64_t rows, hipStream_t st);
+// prune.hip: PCDDT pruning of a freshly built static structure.  Blocks.
+cddt_status prune_structure(cddt_map_s* m, hipStream_t st);
 // query.hip
 cddt_status launch_cast(const MapDev& m, const float* x, const float* y, const float* th, int64_t n,
                         int32_t max_range, int32_t* out, hipStream_t st);

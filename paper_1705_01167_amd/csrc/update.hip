@@ -415,6 +415,10 @@ cddt_status apply_update(cddt_map_s* m, const int32_t* xs_h, const int32_t* ys_h
   CDDT_TRY(ensure(m->alloc, m->upd_edits, (size_t)kOpChunk * 9 * sizeof(int2), "edge flips"));
   UpdCounters* ctr = (UpdCounters*)m->upd_misc.ptr;
   std::vector<uint8_t> packed((size_t)kOpChunk * 9);
+  // A pruned (PCDDT) structure depends on every free cell, not only on edge
+  // flips: its grid takes the ops and the structure is rebuilt and pruned.
+  const bool pruned = (m->flags & CDDT_FLAG_PRUNE) != 0;
+  bool grid_changed = false;
 
   for (int64_t o0 = 0; o0 < n_ops; o0 += kOpChunk) {
     const int32_t n = (int32_t)std::min<int64_t>(kOpChunk, n_ops - o0);
@@ -441,6 +445,10 @@ cddt_status apply_update(cddt_map_s* m, const int32_t* xs_h, const int32_t* ys_h
     UpdCounters hc{};
     CDDT_HIP(hipMemcpyAsync(&hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
     CDDT_HIP(hipStreamSynchronize(st));
+    if (pruned) {
+      grid_changed = grid_changed || hc.changed > 0;
+      continue;
+    }
     if (hc.edits == 0) continue;
 
     // band records, grouped per band
@@ -489,6 +497,10 @@ cddt_status apply_update(cddt_map_s* m, const int32_t* xs_h, const int32_t* ys_h
       m->stats_stale = true;       // the longest band is recomputed when asked for
       CDDT_TRY(fill_buckets(m, touched, (int64_t)hc.touched, st));  // buckets of the edited bands
     }
+  }
+  if (grid_changed) {
+    CDDT_TRY(build_structure(m, st));
+    ++m->rebuilds;
   }
   return CDDT_OK;
 }

@@ -57,6 +57,11 @@ def test_validation_needs_no_gpu():
     # 16-bit zero points live in the bucket lines: the flag alone is refused
     assert L.cddt_create(occ, 5, 5, 8, cddt.FLAG_ZP16, None, None, C.byref(out)) == cddt.EINVAL
     assert b"BUCKETS" in L.cddt_last_error()
+    # pruning is for static maps and is not combined with 16-bit zero points
+    assert L.cddt_create(occ, 5, 5, 8, cddt.FLAG_PRUNE, None, None, C.byref(out)) == cddt.EINVAL
+    assert b"STATIC" in L.cddt_last_error()
+    assert L.cddt_create(occ, 5, 5, 8, cddt.FLAG_PRUNE | cddt.FLAG_STATIC | cddt.FLAG_ZP16 | cddt.FLAG_BUCKETS,
+                         None, None, C.byref(out)) == cddt.EINVAL
     assert L.cddt_create(None, 5, 5, 8, 0, None, None, C.byref(out)) == cddt.EINVAL
     assert not out.value
     assert L.cddt_cast(None, None, None, None, 1, 5, None, None) == cddt.EINVAL
