@@ -38,6 +38,7 @@ SEARCHES = 40         # 61 rays with radial pairing of rays r and r + 40 (21 pai
 MAX_RANGE = 500
 BUCKETS: int | None = 7  # log2 bucket width of the maps' bucket index (None: no index); set by --buckets
 ZP16 = False  # 16-bit zero points in the bucket lines (results then follow the 16-bit reading); set by --zp16
+PRUNE = False  # PCDDT: pruned static maps (exact for grid states only); set by --prune
 
 # Algorithmic bytes per particle of the fused step, as the method defines it
 # (a bin is a sorted array reached through its offset and length): pose 12 +
@@ -126,7 +127,7 @@ def build_batched(n_filters: int):
         table = wl.beam_table(MAX_RANGE, wl.beam_params(wl.rng_for(wl.BATCHED, wl.S_TABLE, f)))
         t1 = time.perf_counter()
         occ_d = t_dev(occ)
-        m = cddt.Map(occ_d, sp["theta_bins"], buckets=BUCKETS, zp16=ZP16)
+        m = cddt.Map(occ_d, sp["theta_bins"], buckets=BUCKETS, zp16=ZP16, prune=PRUNE)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         del occ_d
@@ -156,7 +157,7 @@ def cpu_baseline(specs, host, off_h, budget_s: float, max_build_s: float = 40.0)
     for f in picks:
         h = host[f]
         t0 = time.perf_counter()
-        built.append((f, oref.RefCDDT(h["occ"], h["n"], threads=threads, zp16=ZP16)))
+        built.append((f, oref.RefCDDT(h["occ"], h["n"], threads=threads, zp16=ZP16, prune=PRUNE)))
         build_s += time.perf_counter() - t0
         if build_s > max_build_s:
             break
@@ -217,7 +218,7 @@ def run_batched(args) -> dict:
     stream = torch.cuda.Stream()
     plan = cddt.Plan(filters, stream=stream, keepalive=keep)
     sig = tune.signature(len(specs), particles, [s["theta_bins"] for s in specs], torch.cuda.get_device_name(0),
-                         BUCKETS if not ZP16 else f"{BUCKETS}z16")
+                         BUCKETS if not (ZP16 or PRUNE) else f"{BUCKETS}{'z16' if ZP16 else ''}{'p' if PRUNE else ''}")
     t0 = time.perf_counter()
     if args.tuning:
         best = tuple(int(v) for v in args.tuning.split(","))
@@ -279,6 +280,7 @@ def run_batched(args) -> dict:
                               "overflow_buckets": int(sum(s["bucket_overflow"] for s in stats)),
                               "zero_points_16bit": ZP16}
                              if BUCKETS is not None else None),
+            "pcddt": PRUNE,
             "tuning": {"particles_per_tile": best[0], "waves_per_block": best[1], "blocks_per_cu": best[2],
                        "search_mode": best[3]},
             "parallelism": "single GPU",
@@ -360,7 +362,7 @@ def run_small(args) -> dict:
     from paper_1705_01167_amd import cddt
     from paper_1705_01167_amd import workloads as wl
     occ = wl.rect_map(wl.rng_for(wl.SMALL, wl.S_MAP))
-    m = cddt.Map(t_dev(occ), 108, buckets=BUCKETS, zp16=ZP16)
+    m = cddt.Map(t_dev(occ), 108, buckets=BUCKETS, zp16=ZP16, prune=PRUNE)
     px, py, pth = wl.free_poses(wl.rng_for(wl.SMALL, wl.S_POSES), occ, 1000)
     off = wl.ray_offsets(RAYS)
     x = t_dev(np.repeat(px, RAYS))
@@ -385,7 +387,7 @@ def run_floor(args) -> dict:
     from paper_1705_01167_amd import cddt
     from paper_1705_01167_amd import workloads as wl
     occ = wl.building_map(wl.rng_for(wl.FLOOR, wl.S_MAP), 2000, 2000)
-    m = cddt.Map(t_dev(occ), 200, buckets=BUCKETS, zp16=ZP16)
+    m = cddt.Map(t_dev(occ), 200, buckets=BUCKETS, zp16=ZP16, prune=PRUNE)
     off_h = wl.ray_offsets(RAYS)
     px, py, pth = wl.free_poses(wl.rng_for(wl.FLOOR, wl.S_POSES), occ, 2500)
     table = t_dev(wl.beam_table(MAX_RANGE, wl.beam_params(wl.rng_for(wl.FLOOR, wl.S_TABLE))))
@@ -414,7 +416,7 @@ def run_updates(args) -> dict:
     occ = wl.building_map(wl.rng_for(wl.UPDATES, wl.S_MAP), 4000, 4000)
     n, P = 200, 1_000_000
     t0 = time.perf_counter()
-    m = cddt.Map(t_dev(occ), n, buckets=BUCKETS, zp16=ZP16)
+    m = cddt.Map(t_dev(occ), n, buckets=BUCKETS, zp16=ZP16, prune=PRUNE)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     off = t_dev(wl.ray_offsets(RAYS))
@@ -447,7 +449,7 @@ def run_updates(args) -> dict:
             upd_s += t1 - t0
             upd_each.append(t1 - t0)
             cast_s += e0.elapsed_time(e1) / 1e3
-    fresh = cddt.Map(t_dev(cur), n, buckets=BUCKETS, zp16=ZP16)
+    fresh = cddt.Map(t_dev(cur), n, buckets=BUCKETS, zp16=ZP16, prune=PRUNE)
     same = all((a == b).all() for a, b in zip(m.export(), fresh.export()))
     rays = x.numel()
     info = m.info()
@@ -587,6 +589,8 @@ def main():
     ap.add_argument("--zp16", action="store_true",
                     help="16-bit zero points in the bucket lines (answers follow the 16-bit reading, not the "
                          "exact one; needs a bucket index)")
+    ap.add_argument("--prune", action="store_true",
+                    help="PCDDT: pruned static maps (answers equal the full structure only from grid states)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving summary")
     ap.add_argument("--no-probe", action="store_true", help="skip the gather-bandwidth probe")
@@ -612,8 +616,9 @@ def main():
         BUCKETS = None if args.workload in ("small", "updates", "serving") else 7
     else:
         BUCKETS = None if args.buckets.lower() == "none" else int(args.buckets)
-    global ZP16
+    global ZP16, PRUNE
     ZP16 = bool(args.zp16)
+    PRUNE = bool(args.prune)
     if ZP16 and BUCKETS is None:
         print("--zp16 needs a bucket index (--buckets k)", file=sys.stderr)
         sys.exit(2)
