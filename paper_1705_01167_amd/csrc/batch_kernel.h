@@ -47,10 +47,12 @@ __host__ __device__ constexpr bool tile_x2(int mode) { return mode == kModeTile8
 constexpr int kMaxBatchThreads = 512;
 
 // Dynamic LDS of one block: per wave and queued particle slot, a search job
-// (int2, whose first word later holds the packed result) and the lane's
-// result code (int32).
+// (int2, whose first word later holds the packed result), the lane's result
+// code (int32) and, for the one-search-per-lane modes, a slot of the queue of
+// searches left for the full pass (int32).
 __host__ __device__ constexpr size_t tile_lds_bytes(int mode, int waves) {
-  return (size_t)waves * tile_q(mode) * kWave * (sizeof(int2) + sizeof(int32_t));
+  return (size_t)waves * tile_q(mode) * kWave *
+         (sizeof(int2) + sizeof(int32_t) + (tile_x2(mode) ? 0 : sizeof(int32_t)));
 }
 
 // Z: instantiated for batches that hold a map with 16-bit zero points in its
@@ -65,6 +67,7 @@ __global__ __launch_bounds__(kMaxBatchThreads) void k_batch(const FilterDev* __r
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   int2* jobs = smem_jobs + wave * Q * kWave;
   int32_t* codes = reinterpret_cast<int32_t*>(smem_jobs + nw * Q * kWave) + wave * Q * kWave;
+  int32_t* later = reinterpret_cast<int32_t*>(smem_jobs + nw * Q * kWave) + (nw + wave) * Q * kWave;
   int part = (int)(blockIdx.x % kTileParts), exhausted = 0;
   for (;;) {
     const uint64_t part_lo = (uint64_t)total_tiles * part / kTileParts;
@@ -92,7 +95,7 @@ __global__ __launch_bounds__(kMaxBatchThreads) void k_batch(const FilterDev* __r
     if constexpr (Q > 0) {
       if (f.n_rays <= kWave) {
         for (int64_t p = p0; p < p1; p += Q)
-          wave_tile_logw<Q, tile_x2(Mode), Z>(f, p, (int32_t)min((int64_t)Q, p1 - p), jobs, codes);
+          wave_tile_logw<Q, tile_x2(Mode), Z>(f, p, (int32_t)min((int64_t)Q, p1 - p), jobs, codes, later);
         continue;
       }
     }

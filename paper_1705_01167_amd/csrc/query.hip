@@ -38,11 +38,12 @@ template <bool Z>
 __global__ __launch_bounds__(kWeightThreads) void k_weight_tiles(FilterDev f) {
   __shared__ int2 jobs[kWeightThreads / kWave][kWeightQ * kWave];
   __shared__ int32_t codes[kWeightThreads / kWave][kWeightQ * kWave];
+  __shared__ int32_t later[kWeightThreads / kWave][kWeightQ * kWave];
   const int wave = threadIdx.x >> 6;
   const int64_t p0 = ((int64_t)blockIdx.x * (kWeightThreads / kWave) + wave) * kWeightQ;
   if (p0 >= f.n_particles) return;  // whole wave leaves together
   const int32_t cnt = (int32_t)min((int64_t)kWeightQ, f.n_particles - p0);
-  wave_tile_logw<kWeightQ, false, Z>(f, p0, cnt, jobs[wave], codes[wave]);
+  wave_tile_logw<kWeightQ, false, Z>(f, p0, cnt, jobs[wave], codes[wave], later[wave]);
 }
 
 template <bool Z>

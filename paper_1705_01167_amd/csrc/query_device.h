@@ -604,6 +604,42 @@ __device__ __forceinline__ void lane_search2(const MapDev& m, bool wa, int32_t r
   finish(wb, st_b, ln_b, cb, nb, vb, xb, sb, pb);
 }
 
+// First pass of a bucket search on the first 64 bytes of the bucket line: the
+// carried neighbours and the bucket's lowest 14 keys (words 2..15).  When x
+// lies below the 14th key, the successor is among those keys (the 14th is
+// above x) and every key below x is among them too (keys come in ascending
+// order), so the results equal the whole line's; returns true.  Otherwise (x at
+// or beyond the 14th key, or an overflowing bucket) returns false and the
+// results are not set: the full search decides.  Reading half a line takes one
+// 64-byte memory request instead of two.
+__device__ __forceinline__ bool bucket_half(const MapDev& m, int32_t row, int32_t x, int32_t max_range,
+                                            int32_t& r_succ, int32_t& r_pred) {
+  const int4* p = reinterpret_cast<const int4*>(m.bk + ((int64_t)row * m.nbk + bucket_of(m, x)) * kLineInts);
+  int32_t e[16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int4 q = ldg4(p + i);
+    e[4 * i] = q.x;
+    e[4 * i + 1] = q.y;
+    e[4 * i + 2] = q.z;
+    e[4 * i + 3] = q.w;
+  }
+  const int32_t xm = x - 1;  // x >= 0 relative to the bucket origin
+  uint32_t dn = 0xffffffffu, dp = 0xffffffffu;
+#pragma unroll
+  for (int i = 2; i < 16; ++i) {
+    dn = min(dn, above_gap(e[i], x));
+    dp = min(dp, below_gap(e[i], xm));
+  }
+  int32_t nxt = has_above(dn, x) ? (int32_t)((uint32_t)x + 1u + dn) : INT_MAX;
+  nxt = nxt < e[1] ? nxt : e[1];
+  const int32_t prv = has_below(dp, xm) ? (int32_t)((uint32_t)xm - dp) : e[0];
+  r_succ = nxt != INT_MAX ? range_of((int64_t)nxt - x, max_range) : max_range;
+  r_pred = prv != INT_MIN ? range_of((int64_t)x - prv, max_range) : max_range;
+  asm volatile("" : "+v"(r_succ), "+v"(r_pred));  // keeps the four loads ahead of the test below
+  return e[0] != kBucketOverflow && x < e[15];
+}
+
 // Search strategy: K = 0 one lane per search, K >= 1 eight lanes per search
 // with K searches per group in flight (maps with a bucket index always search
 // one lane per bucket line).
@@ -719,12 +755,16 @@ __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, f
 //      is then drained 64 jobs per round, one lane per search;
 //   C  every ray reads its (or its partner's) result, the Q table gathers are
 //      issued together, and each particle's sum is reduced in the fixed order.
-// jobs / codes: this wave's LDS slices of Q * 64 entries (a job's first word
-// is overwritten by its packed result).  With Lanes2 each lane runs two
-// searches of a round side by side (128 searches per round).
+// jobs / codes / later: this wave's LDS slices of Q * 64 entries (a job's
+// first word is overwritten by its packed result).  With Lanes2 each lane
+// runs two searches of a round side by side (128 searches per round).
+// Otherwise, on maps with 32-bit bucket lines, a round reads only the first
+// half of each line (bucket_half); the searches it cannot settle are queued in
+// `later` and run in full after the last round, so that a round never waits
+// for a second line.
 template <int Q, int Lanes2, bool Z>
 __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, int32_t cnt, int2* jobs,
-                                               int32_t* codes) {
+                                               int32_t* codes, int32_t* later) {
   const int lane = threadIdx.x & (kWave - 1);
   const MapDev& m = f.map;
   const int32_t M = f.max_range, m1 = M + 1;
@@ -801,9 +841,30 @@ __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, i
       if (wb) jobs[jb].x = sb | (pb << 16);
     }
   } else {
+    const bool halves = m.bk && !(Z && m.zp16);  // the same for the whole wave
+    int32_t nlater = 0;
     for (int32_t b = 0; b < njobs; b += kWave) {
       const int32_t j = b + lane;
       const bool w = j < njobs;
+      const int2 jb = w ? jobs[j] : make_int2(0, 0);
+      int32_t rs, rp;
+      if (halves) {
+        const bool done = w && bucket_half(m, jb.x, jb.y, M, rs, rp);
+        const bool defer = w && !done;
+        const uint64_t dm = __ballot(defer);
+        if (defer) later[nlater + __popcll(dm & ((1ull << lane) - 1ull))] = j;
+        nlater += __popcll(dm);
+        if (done) jobs[j].x = rs | (rp << 16);
+      } else {
+        lane_search<Z>(m, w, jb.x, jb.y, M, rs, rp);
+        if (w) jobs[j].x = rs | (rp << 16);
+      }
+    }
+    __threadfence_block();
+    for (int32_t b = 0; b < nlater; b += kWave) {  // the whole line, or the band's search lines
+      const int32_t k = b + lane;
+      const bool w = k < nlater;
+      const int32_t j = w ? later[k] : 0;
       const int2 jb = w ? jobs[j] : make_int2(0, 0);
       int32_t rs, rp;
       lane_search<Z>(m, w, jb.x, jb.y, M, rs, rp);
