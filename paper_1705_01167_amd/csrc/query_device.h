@@ -640,6 +640,64 @@ __device__ __forceinline__ bool bucket_half(const MapDev& m, int32_t row, int32_
   return e[0] != kBucketOverflow && x < e[15];
 }
 
+// One round of first passes over jobs [b, b + 64) by quads of lanes: in step
+// k the 16 quads take jobs b + 16k .. b + 16k + 15, each lane of a quad
+// reading one 16-byte quarter of the first half of the job's bucket line, so
+// one load instruction covers 16 lines.  Each lane reduces its four words to
+// the smallest above-gap and below-gap (unsigned minima as in scan_line; the
+// carried neighbours in words 0 and 1 lie below and above x, so they take
+// part like keys), then the quad combines them with two DPP exchanges.  Lane
+// 4q + s keeps step s's result: job jo = b + 16s + q.  Returns whether jo
+// exists; rs < 0 when the half line cannot settle it (x at or beyond the 14th
+// key, or an overflowing bucket), else the ranges as bucket_half gives them.
+// All 64 lanes call.
+__device__ __forceinline__ bool quad_half_round(const MapDev& m, const int2* jobs, int32_t b, int32_t njobs,
+                                                int32_t max_range, int32_t& jo, int32_t& rs, int32_t& rp) {
+  const int lane = threadIdx.x & (kWave - 1), sub = lane & 3, quad = lane >> 2;
+  int4 v[4];
+  int32_t xs[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int32_t j = b + 16 * k + quad;
+    const int2 jb = j < njobs ? jobs[j] : make_int2(0, 0);
+    xs[k] = jb.y;
+    v[k] = make_int4(INT_MAX, INT_MAX, INT_MAX, INT_MAX);
+    if (j < njobs)
+      v[k] = ldg4(reinterpret_cast<const int4*>(m.bk + ((int64_t)jb.x * m.nbk + bucket_of(m, jb.y)) * kLineInts) +
+                  sub);
+  }
+  uint32_t dn[4], dp[4];
+  int32_t bad[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int32_t x = xs[k], xm = x - 1;
+    uint32_t a = min(min(above_gap(v[k].x, x), above_gap(v[k].y, x)), min(above_gap(v[k].z, x), above_gap(v[k].w, x)));
+    uint32_t c = min(min(below_gap(v[k].x, xm), below_gap(v[k].y, xm)), min(below_gap(v[k].z, xm), below_gap(v[k].w, xm)));
+    int32_t f = (sub == 0 && v[k].x == kBucketOverflow) || (sub == 3 && !(x < v[k].w)) ? 1 : 0;
+    a = min(a, (uint32_t)dpp<kDppQuadXor1>((int32_t)a));
+    c = min(c, (uint32_t)dpp<kDppQuadXor1>((int32_t)c));
+    f = max(f, dpp<kDppQuadXor1>(f));
+    a = min(a, (uint32_t)dpp<kDppQuadXor2>((int32_t)a));
+    c = min(c, (uint32_t)dpp<kDppQuadXor2>((int32_t)c));
+    f = max(f, dpp<kDppQuadXor2>(f));
+    dn[k] = a;
+    dp[k] = c;
+    bad[k] = f;
+  }
+  const uint32_t d1 = sub == 0 ? dn[0] : sub == 1 ? dn[1] : sub == 2 ? dn[2] : dn[3];
+  const uint32_t d2 = sub == 0 ? dp[0] : sub == 1 ? dp[1] : sub == 2 ? dp[2] : dp[3];
+  const int32_t f = sub == 0 ? bad[0] : sub == 1 ? bad[1] : sub == 2 ? bad[2] : bad[3];
+  const int32_t x = sub == 0 ? xs[0] : sub == 1 ? xs[1] : sub == 2 ? xs[2] : xs[3];
+  jo = b + 16 * sub + quad;
+  const int32_t xm = x - 1;
+  const int32_t nxt = has_above(d1, x) ? (int32_t)((uint32_t)x + 1u + d1) : INT_MAX;
+  const int32_t prv = has_below(d2, xm) ? (int32_t)((uint32_t)xm - d2) : INT_MIN;
+  rs = nxt != INT_MAX ? range_of((int64_t)nxt - x, max_range) : max_range;
+  rp = prv != INT_MIN ? range_of((int64_t)x - prv, max_range) : max_range;
+  if (f) rs = -1;
+  return jo < njobs;
+}
+
 // Search strategy: K = 0 one lane per search, K >= 1 eight lanes per search
 // with K searches per group in flight (maps with a bucket index always search
 // one lane per bucket line).
@@ -849,12 +907,14 @@ __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, i
       const int2 jb = w ? jobs[j] : make_int2(0, 0);
       int32_t rs, rp;
       if (halves) {
-        const bool done = w && bucket_half(m, jb.x, jb.y, M, rs, rp);
-        const bool defer = w && !done;
+        int32_t jo;
+        const bool wo = quad_half_round(m, jobs, b, njobs, M, jo, rs, rp);  // this lane's job jo and its result
+        const bool done = wo && rs >= 0;
+        const bool defer = wo && rs < 0;
         const uint64_t dm = __ballot(defer);
-        if (defer) later[nlater + __popcll(dm & ((1ull << lane) - 1ull))] = j;
+        if (defer) later[nlater + __popcll(dm & ((1ull << lane) - 1ull))] = jo;
         nlater += __popcll(dm);
-        if (done) jobs[j].x = rs | (rp << 16);
+        if (done) jobs[jo].x = rs | (rp << 16);
       } else {
         lane_search<Z>(m, w, jb.x, jb.y, M, rs, rp);
         if (w) jobs[j].x = rs | (rp << 16);
