@@ -69,18 +69,27 @@ __global__ __launch_bounds__(kMaxBatchThreads) void k_batch(const FilterDev* __r
   int32_t* codes = reinterpret_cast<int32_t*>(smem_jobs + nw * Q * kWave) + wave * Q * kWave;
   int32_t* later = reinterpret_cast<int32_t*>(smem_jobs + nw * Q * kWave) + (nw + wave) * Q * kWave;
   int part = (int)(blockIdx.x % kTileParts), exhausted = 0;
+  // Tickets: lane 0 claims the next ticket of its part while the current tile
+  // runs, so the atomic's round trip overlaps the tile's own loads.  Every
+  // claimed ticket is used: in range it is the next tile, out of range it
+  // moves the wave to the next part.
+  auto claim = [&](int pt) {
+    unsigned long long v = 0;
+    if (lane == 0) v = atomicAdd(counter + pt * kCounterStride, 1ull);
+    return v;
+  };
+  unsigned long long ticket = claim(part);
   for (;;) {
     const uint64_t part_lo = (uint64_t)total_tiles * part / kTileParts;
     const uint64_t part_hi = (uint64_t)total_tiles * (part + 1) / kTileParts;
-    uint64_t t = 0;
-    if (lane == 0) t = atomicAdd(counter + part * kCounterStride, 1ull);
-    t = __shfl((unsigned long long)t, 0);
-    t = uniform_u64(t) + part_lo;
+    const uint64_t t = uniform_u64(ticket) + part_lo;  // lane 0's ticket (the first active lane)
     if (t >= part_hi) {
       if (++exhausted == kTileParts) break;
       part = (part + 1) % kTileParts;
+      ticket = claim(part);
       continue;
     }
+    ticket = claim(part);
     int32_t lo = 0, hi = n_filters;  // prefix[lo] <= t < prefix[hi]
     while (hi - lo > 1) {
       int32_t mid = (lo + hi) >> 1;
