@@ -31,6 +31,25 @@ __global__ __launch_bounds__(kCastThreads) void k_cast(MapDev m, const float* __
   }
 }
 
+// Casts on maps with 32-bit bucket lines: kCastQ * 64 rays per wave through
+// the search queue (half-line first pass, deferred full searches).
+constexpr int kCastQ = 4;
+template <bool Z>
+__global__ __launch_bounds__(kCastThreads) void k_cast_tiles(MapDev m, const float* __restrict__ x,
+                                                             const float* __restrict__ y,
+                                                             const float* __restrict__ th, int64_t n,
+                                                             int32_t max_range, int32_t* __restrict__ out) {
+  __shared__ int2 jobs[kCastThreads / kWave][kCastQ * kWave];
+  __shared__ int32_t codes[kCastThreads / kWave][kCastQ * kWave];
+  __shared__ int32_t later[kCastThreads / kWave][kCastQ * kWave];
+  const int wave = threadIdx.x >> 6;
+  const int64_t per = (int64_t)kCastQ * kWave;
+  const int64_t tiles = (n + per - 1) / per;
+  const int64_t waves = (int64_t)gridDim.x * (kCastThreads / kWave);
+  for (int64_t t = (int64_t)blockIdx.x * (kCastThreads / kWave) + wave; t < tiles; t += waves)
+    wave_cast_tile<kCastQ, Z>(m, x, y, th, n, t * per, max_range, out, jobs[wave], codes[wave], later[wave]);
+}
+
 // Q particles per wave through the phased tile routine (ray layouts of <= 64 rays).
 constexpr int kWeightQ = 4;
 constexpr int64_t kTileMinParticles = 1 << 17;
@@ -61,6 +80,15 @@ __global__ __launch_bounds__(kWeightThreads) void k_weight(FilterDev f) {
 cddt_status launch_cast(const MapDev& m, const float* x, const float* y, const float* th, int64_t n,
                         int32_t max_range, int32_t* out, hipStream_t st) {
   if (n == 0) return CDDT_OK;
+  if (m.bk && !m.zp16) {
+    const int64_t tiles = (n + (int64_t)kCastQ * kWave - 1) / ((int64_t)kCastQ * kWave);
+    int64_t tb = (tiles + kCastThreads / kWave - 1) / (kCastThreads / kWave);
+    if (tb > (1 << 16)) tb = 1 << 16;
+    hipLaunchKernelGGL(k_cast_tiles<false>, dim3((unsigned)tb), dim3(kCastThreads), 0, st, m, x, y, th, n,
+                       max_range, out);
+    CDDT_HIP(hipGetLastError());
+    return CDDT_OK;
+  }
   int64_t blocks = (n + kCastThreads - 1) / kCastThreads;
   if (blocks > (1 << 16)) blocks = 1 << 16;
   if (m.zp16)

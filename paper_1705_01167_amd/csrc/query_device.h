@@ -802,6 +802,104 @@ __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, f
   return wave_sum(acc);
 }
 
+// Runs one wave's queued searches jobs[0, njobs) (band, Xq), one search per
+// lane per round; each job's first word is replaced by its packed result
+// (successor range | predecessor range << 16).  On maps with 32-bit bucket
+// lines a round reads only the first half of each line (quad_half_round); the
+// searches it cannot settle are queued in `later` and run in full after the
+// last round, so that a round never waits for a second line.  All 64 lanes
+// call.
+template <bool Z>
+__device__ __forceinline__ void drain_jobs(const MapDev& m, int2* jobs, int32_t* later, int32_t njobs, int32_t M) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const bool halves = m.bk && !(Z && m.zp16);  // the same for the whole wave
+  int32_t nlater = 0;
+  for (int32_t b = 0; b < njobs; b += kWave) {
+    const int32_t j = b + lane;
+    const bool w = j < njobs;
+    const int2 jb = w ? jobs[j] : make_int2(0, 0);
+    int32_t rs, rp;
+    if (halves) {
+      int32_t jo;
+      const bool wo = quad_half_round(m, jobs, b, njobs, M, jo, rs, rp);  // this lane's job jo and its result
+      const bool done = wo && rs >= 0;
+      const bool defer = wo && rs < 0;
+      const uint64_t dm = __ballot(defer);
+      if (defer) later[nlater + __popcll(dm & ((1ull << lane) - 1ull))] = jo;
+      nlater += __popcll(dm);
+      if (done) jobs[jo].x = rs | (rp << 16);
+    } else {
+      lane_search<Z>(m, w, jb.x, jb.y, M, rs, rp);
+      if (w) jobs[j].x = rs | (rp << 16);
+    }
+  }
+  __threadfence_block();
+  for (int32_t b = 0; b < nlater; b += kWave) {  // the whole line, or the band's search lines
+    const int32_t k = b + lane;
+    const bool w = k < nlater;
+    const int32_t j = w ? later[k] : 0;
+    const int2 jb = w ? jobs[j] : make_int2(0, 0);
+    int32_t rs, rp;
+    lane_search<Z>(m, w, jb.x, jb.y, M, rs, rp);
+    if (w) jobs[j].x = rs | (rp << 16);
+  }
+}
+
+// Plain casts of rays [base, base + 64 Q) by one wave through the search queue
+// (ray base + 64 q + lane in lane `lane`): the landings of all Q rays per lane
+// are queued, drained by drain_jobs, and each result is picked as wave_cast
+// picks it.  Same results as wave_cast.  jobs / codes / later: this wave's LDS
+// slices of Q * 64 entries.  All 64 lanes call.
+template <int Q, bool Z>
+__device__ __forceinline__ void wave_cast_tile(const MapDev& m, const float* __restrict__ x,
+                                               const float* __restrict__ y, const float* __restrict__ th,
+                                               int64_t n, int64_t base, int32_t max_range, int32_t* __restrict__ out,
+                                               int2* jobs, int32_t* codes, int32_t* later) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int32_t njobs = 0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t i = base + (int64_t)q * kWave + lane;
+    const bool active = i < n;
+    const float xi = active ? ldg(x + i) : 0.0f, yi = active ? ldg(y + i) : 0.0f, ti = active ? ldg(th + i) : 0.0f;
+    bool valid = active && (fabsf(ti) < 1e6f) && pose_inside(m, xi, yi);
+    int32_t xf = 0, yf = 0;
+    if (valid) {
+      xf = quantize16(xi);
+      yf = quantize16(yi);
+      valid = ldg(m.occ + (size_t)(yf >> 16) * (size_t)m.w + (size_t)(xf >> 16)) == 0;
+    }
+    bool fwd = true;
+    Landing l{0, 0};
+    if (valid) {
+      const int32_t k = theta_bin(ti, m.k_scale, m.n);
+      fwd = k < m.half;
+      l = land(m, fwd ? k : k - m.half, xf, yf);
+    }
+    const uint64_t mask = __ballot(valid);
+    const int32_t slot = njobs + __popcll(mask & ((1ull << lane) - 1ull));
+    if (valid) jobs[slot] = make_int2(l.row, l.xq);
+    codes[q * kWave + lane] = valid ? ((slot << 1) | (fwd ? 1 : 0)) : -1;
+    njobs += __popcll(mask);
+  }
+  __threadfence_block();
+  drain_jobs<Z>(m, jobs, later, njobs, max_range);
+  __threadfence_block();
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t i = base + (int64_t)q * kWave + lane;
+    if (i < n) {
+      const int32_t code = codes[q * kWave + lane];
+      int32_t r = 0;
+      if (code >= 0) {
+        const int32_t pk = jobs[code >> 1].x;
+        r = (code & 1) ? (pk & 0xffff) : (int32_t)((uint32_t)pk >> 16);
+      }
+      stg(out + i, r);
+    }
+  }
+}
+
 // Log-weights of `cnt` (<= Q) consecutive particles by one wave, for ray
 // layouts of at most 64 rays.  Same results as wave_particle_logw for each
 // particle, computed in three phases so that one particle's chain of
@@ -899,37 +997,7 @@ __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, i
       if (wb) jobs[jb].x = sb | (pb << 16);
     }
   } else {
-    const bool halves = m.bk && !(Z && m.zp16);  // the same for the whole wave
-    int32_t nlater = 0;
-    for (int32_t b = 0; b < njobs; b += kWave) {
-      const int32_t j = b + lane;
-      const bool w = j < njobs;
-      const int2 jb = w ? jobs[j] : make_int2(0, 0);
-      int32_t rs, rp;
-      if (halves) {
-        int32_t jo;
-        const bool wo = quad_half_round(m, jobs, b, njobs, M, jo, rs, rp);  // this lane's job jo and its result
-        const bool done = wo && rs >= 0;
-        const bool defer = wo && rs < 0;
-        const uint64_t dm = __ballot(defer);
-        if (defer) later[nlater + __popcll(dm & ((1ull << lane) - 1ull))] = jo;
-        nlater += __popcll(dm);
-        if (done) jobs[jo].x = rs | (rp << 16);
-      } else {
-        lane_search<Z>(m, w, jb.x, jb.y, M, rs, rp);
-        if (w) jobs[j].x = rs | (rp << 16);
-      }
-    }
-    __threadfence_block();
-    for (int32_t b = 0; b < nlater; b += kWave) {  // the whole line, or the band's search lines
-      const int32_t k = b + lane;
-      const bool w = k < nlater;
-      const int32_t j = w ? later[k] : 0;
-      const int2 jb = w ? jobs[j] : make_int2(0, 0);
-      int32_t rs, rp;
-      lane_search<Z>(m, w, jb.x, jb.y, M, rs, rp);
-      if (w) jobs[j].x = rs | (rp << 16);
-    }
+    drain_jobs<Z>(m, jobs, later, njobs, M);
   }
   __threadfence_block();
   // C: table gathers, then one fixed-order sum per particle
