@@ -90,30 +90,26 @@ __global__ void k_project(const SliceDev* __restrict__ slices, const uint32_t* _
   }
 }
 
-// Bucket index fill: one wave per band, one lane per bucket (64 buckets per
-// pass), each lane finding its bucket's key range by two binary searches over
-// the band's sorted keys and writing its whole line.  Band t of the list is
-// rows_list[t] (band t when rows_list is null).  With `partial` the old line
-// is read first so that the overflow counter stays exact.
-__device__ __forceinline__ int32_t first_at_least(const int32_t* __restrict__ keys, int32_t len, int64_t v) {
-  int32_t lo = 0, cnt = len;
-  while (cnt > 0) {
-    const int32_t half = cnt >> 1;
-    if ((int64_t)keys[lo + half] < v) {
-      lo += half + 1;
-      cnt -= half + 1;
-    } else {
-      cnt = half;
-    }
-  }
-  return lo;
-}
-
-__global__ void k_bucket_fill(const int32_t* __restrict__ hdr, const int32_t* __restrict__ zeros,
-                              const SliceDev* __restrict__ slices, const int32_t* __restrict__ row_start,
-                              int32_t half, int32_t shift, int32_t nbk, int32_t* __restrict__ bk,
-                              const uint32_t* __restrict__ rows_list, uint64_t n_bands,
-                              unsigned long long* __restrict__ over, int partial, int zp16) {
+// Bucket index fill: one wave per band.  first[b] (LDS) = index of the band's
+// first key at or after the start of bucket b, b = 0..nbk: a pass over the
+// keys in order (coalesced) lets key k claim the buckets after its
+// predecessor's bucket up to its own; then one lane per bucket (64 buckets per
+// pass) writes the bucket's whole line from first[b], first[b + 1].  Band t of
+// the list is rows_list[t] (band t when rows_list is null).  With `partial`
+// the old line is read first so that the overflow counter stays exact.
+// Buckets per band are at most (16384 sqrt(2) cells) / 2^4 + 1 = 1449: the
+// longest slice extent of the largest map at the narrowest bucket width.
+constexpr int kFillMaxBuckets = 1456;
+constexpr int kFillThreads = 256;
+__global__ __launch_bounds__(kFillThreads) void k_bucket_fill(
+    const int32_t* __restrict__ hdr, const int32_t* __restrict__ zeros, const SliceDev* __restrict__ slices,
+    const int32_t* __restrict__ row_start, int32_t half, int32_t shift, int32_t nbk, int32_t* __restrict__ bk,
+    const uint32_t* __restrict__ rows_list, uint64_t n_bands, unsigned long long* __restrict__ over, int partial,
+    int zp16, const uint32_t* __restrict__ rec_off, const int2* __restrict__ recs, uint32_t n_recs) {
+  __shared__ int32_t first_lds[kFillThreads / 64][kFillMaxBuckets + 1];
+  __shared__ uint8_t mark_lds[kFillThreads / 64][kFillMaxBuckets];
+  int32_t* first = first_lds[threadIdx.x >> 6];
+  uint8_t* mark = mark_lds[threadIdx.x >> 6];
   const int lane = threadIdx.x & 63;
   const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   for (uint64_t t = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < n_bands; t += n_waves) {
@@ -132,12 +128,40 @@ __global__ void k_bucket_fill(const int32_t* __restrict__ hdr, const int32_t* __
     const int32_t* node = hdr + (int64_t)band * kNodeInts;
     const int32_t* keys = zeros + (uint32_t)node[0];
     const int32_t len = node[1];
+    for (int32_t b = lane; b <= nbk; b += 64) first[b] = len;
+    __threadfence_block();
+    for (int32_t k0 = 0; k0 < len; k0 += 64) {
+      const int32_t k = k0 + lane;
+      if (k < len) {
+        const int64_t bk_k = min(((int64_t)keys[k] - zlo) >> shift, (int64_t)nbk);
+        const int64_t bk_p = k > 0 ? min(((int64_t)keys[k - 1] - zlo) >> shift, (int64_t)nbk) : -1;
+        for (int64_t b = bk_p + 1; b <= bk_k; ++b) first[b] = k;  // key k is the first at or after bucket b
+      }
+    }
+    __threadfence_block();
+    if (recs) {  // mark the buckets the band's edits can change
+      for (int32_t b = lane; b < nbk; b += 64) mark[b] = 0;
+      __threadfence_block();
+      const uint32_t r0 = rec_off[t], r1 = t + 1 < n_bands ? rec_off[t + 1] : n_recs;
+      for (uint32_t r = r0 + lane; r < r1; r += 64) {
+        const int32_t bz = (int32_t)min(max(((int64_t)recs[r].y - zlo) >> shift, (int64_t)0), (int64_t)nbk - 1);
+        mark[bz] = 1;
+        for (int32_t b = bz - 1; b >= 0; --b) {  // buckets that carry this point as their next key
+          mark[b] = 1;
+          if (first[b] < first[b + 1]) break;
+        }
+        for (int32_t b = bz + 1; b < nbk; ++b) {  // buckets that carry it as their previous key
+          mark[b] = 1;
+          if (first[b] < first[b + 1]) break;
+        }
+      }
+      __threadfence_block();
+    }
     int over_delta = 0;
     for (int32_t b0 = 0; b0 < nbk; b0 += 64) {
       const int32_t b = b0 + lane;
-      if (b >= nbk) continue;
-      const int64_t a0 = (int64_t)zlo + ((int64_t)b << shift), a1 = a0 + ((int64_t)1 << shift);
-      const int32_t i0 = first_at_least(keys, len, a0), i1 = first_at_least(keys, len, a1);
+      if (b >= nbk || (recs && !mark[b])) continue;
+      const int32_t i0 = first[b], i1 = first[b + 1];
       const int32_t n_in = i1 - i0;
       int4* line = reinterpret_cast<int4*>(bk + ((int64_t)band * nbk + b) * kLineInts);
       const int old_over = partial ? (reinterpret_cast<const int32_t*>(line)[0] == kBucketOverflow) : 0;
@@ -548,15 +572,18 @@ cddt_status finalize_bands(int32_t* hdr, int32_t* zeros, int64_t rows, hipStream
   return CDDT_OK;
 }
 
-cddt_status fill_buckets(cddt_map_s* m, const uint32_t* rows_list, int64_t n_rows, hipStream_t st) {
+cddt_status fill_buckets(cddt_map_s* m, const uint32_t* rows_list, int64_t n_rows, hipStream_t st,
+                         const uint32_t* rec_off, const int2* recs, uint32_t n_recs) {
   if (!m->d_bk || n_rows <= 0) return CDDT_OK;
+  if (m->nbk > kFillMaxBuckets) return fail(CDDT_EINTERNAL, "bucket fill: more buckets per band than planned");
   const int partial = rows_list ? 1 : 0;
   if (!partial) CDDT_HIP(hipMemsetAsync(m->d_bk_over, 0, 8, st));
   const uint64_t blocks = std::min<uint64_t>(((uint64_t)n_rows + 3) / 4, 1u << 16);  // 4 bands per block
-  hipLaunchKernelGGL(k_bucket_fill, dim3((unsigned)std::max<uint64_t>(blocks, 1)), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_bucket_fill, dim3((unsigned)std::max<uint64_t>(blocks, 1)), dim3(kFillThreads), 0, st,
                      (const int32_t*)m->d_hdr, (const int32_t*)m->d_zeros, (const SliceDev*)m->d_slices,
                      (const int32_t*)m->d_row_start, m->half, 16 + m->blog2, m->nbk, m->d_bk, rows_list,
-                     (uint64_t)n_rows, m->d_bk_over, partial, (m->flags & CDDT_FLAG_ZP16) ? 1 : 0);
+                     (uint64_t)n_rows, m->d_bk_over, partial, (m->flags & CDDT_FLAG_ZP16) ? 1 : 0,
+                     rows_list ? rec_off : nullptr, rows_list ? recs : nullptr, n_recs);
   CDDT_HIP(hipGetLastError());
   unsigned long long over = 0;
   CDDT_HIP(hipMemcpyAsync(&over, m->d_bk_over, 8, hipMemcpyDeviceToHost, st));

@@ -495,7 +495,8 @@ cddt_status apply_update(cddt_map_s* m, const int32_t* xs_h, const int32_t* ys_h
     } else {
       m->zero_points += hc.delta;  // exact: every applied band reported its length change
       m->stats_stale = true;       // the longest band is recomputed when asked for
-      CDDT_TRY(fill_buckets(m, touched, (int64_t)hc.touched, st));  // buckets of the edited bands
+      // the buckets the edits can change, in the edited bands
+      CDDT_TRY(fill_buckets(m, touched, (int64_t)hc.touched, st, toff, (const int2*)m->upd_grp.ptr, hc.records));
     }
   }
   if (grid_changed) {

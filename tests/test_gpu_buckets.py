@@ -149,6 +149,11 @@ def test_bucket_updates_match_oracle(seed):
         for i in range(k):
             occ[ys[i], xs[i]] = vs[i]
         x, y, th = _queries(rng, w, h, 8000)
+        # plus rays from around the edited cells, in every direction: they read the refreshed buckets
+        near = rng.integers(0, k, 8000)
+        x = np.concatenate([x, (xs[near] + rng.uniform(-3, 4, 8000)).astype(np.float32)])
+        y = np.concatenate([y, (ys[near] + rng.uniform(-3, 4, 8000)).astype(np.float32)])
+        th = np.concatenate([th, rng.uniform(-math.pi, math.pi, 8000).astype(np.float32)])
         want = rm.cast(x, y, th, M, threads=4)
         got = gb.cast(_dev(x), _dev(y), _dev(th), M).cpu().numpy()
         assert (got == want).all(), f"step {step}: {(got != want).sum()} rays differ"
