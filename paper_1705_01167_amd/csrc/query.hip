@@ -31,7 +31,7 @@ __global__ __launch_bounds__(kCastThreads) void k_cast(MapDev m, const float* __
   }
 }
 
-// Casts on maps with 32-bit bucket lines: kCastQ * 64 rays per wave through
+// Casts on maps with a bucket index: kCastQ * 64 rays per wave through
 // the search queue (half-line first pass, deferred full searches).
 constexpr int kCastQ = 4;
 template <bool Z>
@@ -80,12 +80,16 @@ __global__ __launch_bounds__(kWeightThreads) void k_weight(FilterDev f) {
 cddt_status launch_cast(const MapDev& m, const float* x, const float* y, const float* th, int64_t n,
                         int32_t max_range, int32_t* out, hipStream_t st) {
   if (n == 0) return CDDT_OK;
-  if (m.bk && !m.zp16) {
+  if (m.bk) {
     const int64_t tiles = (n + (int64_t)kCastQ * kWave - 1) / ((int64_t)kCastQ * kWave);
     int64_t tb = (tiles + kCastThreads / kWave - 1) / (kCastThreads / kWave);
     if (tb > (1 << 16)) tb = 1 << 16;
-    hipLaunchKernelGGL(k_cast_tiles<false>, dim3((unsigned)tb), dim3(kCastThreads), 0, st, m, x, y, th, n,
-                       max_range, out);
+    if (m.zp16)
+      hipLaunchKernelGGL(k_cast_tiles<true>, dim3((unsigned)tb), dim3(kCastThreads), 0, st, m, x, y, th, n,
+                         max_range, out);
+    else
+      hipLaunchKernelGGL(k_cast_tiles<false>, dim3((unsigned)tb), dim3(kCastThreads), 0, st, m, x, y, th, n,
+                         max_range, out);
     CDDT_HIP(hipGetLastError());
     return CDDT_OK;
   }

@@ -604,42 +604,6 @@ __device__ __forceinline__ void lane_search2(const MapDev& m, bool wa, int32_t r
   finish(wb, st_b, ln_b, cb, nb, vb, xb, sb, pb);
 }
 
-// First pass of a bucket search on the first 64 bytes of the bucket line: the
-// carried neighbours and the bucket's lowest 14 keys (words 2..15).  When x
-// lies below the 14th key, the successor is among those keys (the 14th is
-// above x) and every key below x is among them too (keys come in ascending
-// order), so the results equal the whole line's; returns true.  Otherwise (x at
-// or beyond the 14th key, or an overflowing bucket) returns false and the
-// results are not set: the full search decides.  Reading half a line takes one
-// 64-byte memory request instead of two.
-__device__ __forceinline__ bool bucket_half(const MapDev& m, int32_t row, int32_t x, int32_t max_range,
-                                            int32_t& r_succ, int32_t& r_pred) {
-  const int4* p = reinterpret_cast<const int4*>(m.bk + ((int64_t)row * m.nbk + bucket_of(m, x)) * kLineInts);
-  int32_t e[16];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int4 q = ldg4(p + i);
-    e[4 * i] = q.x;
-    e[4 * i + 1] = q.y;
-    e[4 * i + 2] = q.z;
-    e[4 * i + 3] = q.w;
-  }
-  const int32_t xm = x - 1;  // x >= 0 relative to the bucket origin
-  uint32_t dn = 0xffffffffu, dp = 0xffffffffu;
-#pragma unroll
-  for (int i = 2; i < 16; ++i) {
-    dn = min(dn, above_gap(e[i], x));
-    dp = min(dp, below_gap(e[i], xm));
-  }
-  int32_t nxt = has_above(dn, x) ? (int32_t)((uint32_t)x + 1u + dn) : INT_MAX;
-  nxt = nxt < e[1] ? nxt : e[1];
-  const int32_t prv = has_below(dp, xm) ? (int32_t)((uint32_t)xm - dp) : e[0];
-  r_succ = nxt != INT_MAX ? range_of((int64_t)nxt - x, max_range) : max_range;
-  r_pred = prv != INT_MIN ? range_of((int64_t)x - prv, max_range) : max_range;
-  asm volatile("" : "+v"(r_succ), "+v"(r_pred));  // keeps the four loads ahead of the test below
-  return e[0] != kBucketOverflow && x < e[15];
-}
-
 // One round of first passes over jobs [b, b + 64) by quads of lanes: in step
 // k the 16 quads take jobs b + 16k .. b + 16k + 15, each lane of a quad
 // reading one 16-byte quarter of the first half of the job's bucket line, so
@@ -649,8 +613,12 @@ __device__ __forceinline__ bool bucket_half(const MapDev& m, int32_t row, int32_
 // part like keys), then the quad combines them with two DPP exchanges.  Lane
 // 4q + s keeps step s's result: job jo = b + 16s + q.  Returns whether jo
 // exists; rs < 0 when the half line cannot settle it (x at or beyond the 14th
-// key, or an overflowing bucket), else the ranges as bucket_half gives them.
-// All 64 lanes call.
+// key, or an overflowing bucket), else the ranges.  The first half of a line
+// holds the carried neighbours and the bucket's lowest 14 keys (words 2..15);
+// when x lies below the 14th key, the successor is among those keys (the 14th
+// is above x) and every key below x is among them too (keys ascend), so the
+// half gives the whole line's results.  Half a line halves the loads issued
+// per search (the L2 still fills whole lines from memory).  All 64 lanes call.
 __device__ __forceinline__ bool quad_half_round(const MapDev& m, const int2* jobs, int32_t b, int32_t njobs,
                                                 int32_t max_range, int32_t& jo, int32_t& rs, int32_t& rp) {
   const int lane = threadIdx.x & (kWave - 1), sub = lane & 3, quad = lane >> 2;
@@ -692,6 +660,79 @@ __device__ __forceinline__ bool quad_half_round(const MapDev& m, const int2* job
   const int32_t xm = x - 1;
   const int32_t nxt = has_above(d1, x) ? (int32_t)((uint32_t)x + 1u + d1) : INT_MAX;
   const int32_t prv = has_below(d2, xm) ? (int32_t)((uint32_t)xm - d2) : INT_MIN;
+  rs = nxt != INT_MAX ? range_of((int64_t)nxt - x, max_range) : max_range;
+  rp = prv != INT_MIN ? range_of((int64_t)x - prv, max_range) : max_range;
+  if (f) rs = -1;
+  return jo < njobs;
+}
+
+// quad_half_round for 16-bit bucket lines.  The first half holds the carried
+// neighbours as bin centres (words 0 and 1) and the lowest 28 bin indices of
+// the bucket (words 2..15, two per word).  The successor is the first key of
+// bin >= ts; when the 28th index is >= ts (or is padding), it lies in the half
+// and so do all keys of bin <= tp < ts, and the half settles the search as
+// scan_bucket16 would.  The quad reduces the indices' unsigned gaps and takes
+// the carried centres from its first lane.  All 64 lanes call.
+__device__ __forceinline__ bool quad_half_round16(const MapDev& m, const int2* jobs, int32_t b, int32_t njobs,
+                                                  int32_t max_range, int32_t& jo, int32_t& rs, int32_t& rp) {
+  const int lane = threadIdx.x & (kWave - 1), sub = lane & 3, quad = lane >> 2;
+  int4 v[4];
+  int32_t xs[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int32_t j = b + 16 * k + quad;
+    const int2 jb = j < njobs ? jobs[j] : make_int2(0, 0);
+    xs[k] = jb.y;
+    v[k] = make_int4(-1, -1, -1, -1);
+    if (j < njobs)
+      v[k] = ldg4(reinterpret_cast<const int4*>(m.bk + ((int64_t)jb.x * m.nbk + bucket_of(m, jb.y)) * kLineInts) +
+                  sub);
+  }
+  uint32_t dsk[4], dpk[4];
+  int32_t e0k[4], e1k[4], bad[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int32_t x = xs[k], base = bucket_of(m, x) << (m.bshift - kBinShift);
+    const uint32_t ts = (uint32_t)(bin_min_above(x) - base), tp = (uint32_t)(bin_max_below(x) - base);
+    // words 0 and 1 of the first lane are the carried centres, not indices: read as padding here
+    const uint32_t w0 = sub == 0 ? 0xffffffffu : (uint32_t)v[k].x, w1 = sub == 0 ? 0xffffffffu : (uint32_t)v[k].y;
+    const uint32_t w[4] = {w0, w1, (uint32_t)v[k].z, (uint32_t)v[k].w};
+    uint32_t ds = 0xffffffffu, dp = 0xffffffffu;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t lo = w[q] & 0xffffu, hi = w[q] >> 16;
+      ds = min(ds, min(lo - ts, hi - ts));
+      dp = min(dp, min(tp - lo, tp - hi));
+    }
+    int32_t f = (sub == 0 && v[k].x == kBucketOverflow) ||
+                        (sub == 3 && !((int32_t)((uint32_t)v[k].w >> 16) >= (int32_t)ts))
+                    ? 1
+                    : 0;
+    ds = min(ds, (uint32_t)dpp<kDppQuadXor1>((int32_t)ds));
+    dp = min(dp, (uint32_t)dpp<kDppQuadXor1>((int32_t)dp));
+    f = max(f, dpp<kDppQuadXor1>(f));
+    ds = min(ds, (uint32_t)dpp<kDppQuadXor2>((int32_t)ds));
+    dp = min(dp, (uint32_t)dpp<kDppQuadXor2>((int32_t)dp));
+    f = max(f, dpp<kDppQuadXor2>(f));
+    dsk[k] = ds;
+    dpk[k] = dp;
+    bad[k] = f;
+    e0k[k] = dpp<kDppQuadBcast0>(v[k].x);
+    e1k[k] = dpp<kDppQuadBcast0>(v[k].y);
+  }
+  const uint32_t ds = sub == 0 ? dsk[0] : sub == 1 ? dsk[1] : sub == 2 ? dsk[2] : dsk[3];
+  const uint32_t dp = sub == 0 ? dpk[0] : sub == 1 ? dpk[1] : sub == 2 ? dpk[2] : dpk[3];
+  const int32_t f = sub == 0 ? bad[0] : sub == 1 ? bad[1] : sub == 2 ? bad[2] : bad[3];
+  const int32_t e0 = sub == 0 ? e0k[0] : sub == 1 ? e0k[1] : sub == 2 ? e0k[2] : e0k[3];
+  const int32_t e1 = sub == 0 ? e1k[0] : sub == 1 ? e1k[1] : sub == 2 ? e1k[2] : e1k[3];
+  const int32_t x = sub == 0 ? xs[0] : sub == 1 ? xs[1] : sub == 2 ? xs[2] : xs[3];
+  jo = b + 16 * sub + quad;
+  const int32_t base = bucket_of(m, x) << (m.bshift - kBinShift);
+  const int32_t ts = bin_min_above(x) - base, tp = bin_max_below(x) - base;
+  const int32_t s16 = ds < 0x80000000u ? ts + (int32_t)ds : 0xffff;
+  const int32_t p16 = dp < 0x80000000u ? tp - (int32_t)dp : -1;
+  const int32_t nxt = s16 != 0xffff ? bin_centre(base + s16) : e1;
+  const int32_t prv = p16 >= 0 ? bin_centre(base + p16) : e0;
   rs = nxt != INT_MAX ? range_of((int64_t)nxt - x, max_range) : max_range;
   rp = prv != INT_MIN ? range_of((int64_t)x - prv, max_range) : max_range;
   if (f) rs = -1;
@@ -804,15 +845,15 @@ __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, f
 
 // Runs one wave's queued searches jobs[0, njobs) (band, Xq), one search per
 // lane per round; each job's first word is replaced by its packed result
-// (successor range | predecessor range << 16).  On maps with 32-bit bucket
-// lines a round reads only the first half of each line (quad_half_round); the
-// searches it cannot settle are queued in `later` and run in full after the
-// last round, so that a round never waits for a second line.  All 64 lanes
-// call.
+// (successor range | predecessor range << 16).  On maps with a bucket index
+// a round reads only the first half of each line (quad_half_round, or
+// quad_half_round16 for 16-bit lines); the searches it cannot settle are
+// queued in `later` and run in full after the last round, so that a round
+// never waits for a second line.  All 64 lanes call.
 template <bool Z>
 __device__ __forceinline__ void drain_jobs(const MapDev& m, int2* jobs, int32_t* later, int32_t njobs, int32_t M) {
   const int lane = threadIdx.x & (kWave - 1);
-  const bool halves = m.bk && !(Z && m.zp16);  // the same for the whole wave
+  const bool halves = m.bk != nullptr;  // the same for the whole wave
   int32_t nlater = 0;
   for (int32_t b = 0; b < njobs; b += kWave) {
     const int32_t j = b + lane;
@@ -821,7 +862,11 @@ __device__ __forceinline__ void drain_jobs(const MapDev& m, int2* jobs, int32_t*
     int32_t rs, rp;
     if (halves) {
       int32_t jo;
-      const bool wo = quad_half_round(m, jobs, b, njobs, M, jo, rs, rp);  // this lane's job jo and its result
+      bool wo;  // this lane's job jo and its result
+      if (Z && m.zp16)
+        wo = quad_half_round16(m, jobs, b, njobs, M, jo, rs, rp);
+      else
+        wo = quad_half_round(m, jobs, b, njobs, M, jo, rs, rp);
       const bool done = wo && rs >= 0;
       const bool defer = wo && rs < 0;
       const uint64_t dm = __ballot(defer);
@@ -914,10 +959,8 @@ __device__ __forceinline__ void wave_cast_tile(const MapDev& m, const float* __r
 // jobs / codes / later: this wave's LDS slices of Q * 64 entries (a job's
 // first word is overwritten by its packed result).  With Lanes2 each lane
 // runs two searches of a round side by side (128 searches per round).
-// Otherwise, on maps with 32-bit bucket lines, a round reads only the first
-// half of each line (bucket_half); the searches it cannot settle are queued in
-// `later` and run in full after the last round, so that a round never waits
-// for a second line.
+// Otherwise the queue is drained by drain_jobs (half-line first pass on maps
+// with a bucket index, deferred full searches).
 template <int Q, int Lanes2, bool Z>
 __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, int32_t cnt, int2* jobs,
                                                int32_t* codes, int32_t* later) {
