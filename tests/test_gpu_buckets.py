@@ -196,3 +196,21 @@ def test_bucket_plan_mixed_maps_equal_plain():
         torch.cuda.synchronize()
         for i, (got, want) in enumerate(zip(outs, plain)):
             assert torch.equal(got, want), f"tuning {tuning}: filter {i} differs"
+
+
+@pytest.mark.parametrize("zp16", [False, True])
+def test_bucket_casts_ragged_sizes(zp16):
+    """Queued casts (4 x 64 rays per wave) at sizes around the tile and wave boundaries."""
+    rng = wl.rng_for(705, int(zp16))
+    occ = wl.building_map(rng, 300, 260)
+    n = 108
+    rm = oref.RefCDDT(occ, n, zp16=zp16)
+    gb = _map(occ, n, buckets=6, zp16=zp16)
+    for k in (1, 2, 63, 64, 65, 255, 256, 257, 1023, 4097):
+        _say(f"bucket ragged zp16={zp16} n_rays={k}")
+        x = rng.uniform(-2, 302, k).astype(np.float32)
+        y = rng.uniform(-2, 262, k).astype(np.float32)
+        th = rng.uniform(-7, 7, k).astype(np.float32)
+        want = rm.cast(x, y, th, 400)
+        got = gb.cast(_dev(x), _dev(y), _dev(th), 400).cpu().numpy()
+        assert got.shape == want.shape and (got == want).all(), f"{k} rays"
