@@ -214,3 +214,31 @@ def test_bucket_casts_ragged_sizes(zp16):
         want = rm.cast(x, y, th, 400)
         got = gb.cast(_dev(x), _dev(y), _dev(th), 400).cpu().numpy()
         assert got.shape == want.shape and (got == want).all(), f"{k} rays"
+
+
+@pytest.mark.parametrize("n,lb", [(8, 4), (64, None)])
+def test_largest_map(n, lb):
+    """The largest map (16384^2): with 8 bins and 2^4-cell buckets the 45-degree slice has the most
+    buckets per band any map can have (1449); casts equal the oracle."""
+    side = 16384
+    rng = wl.rng_for(706, n)
+    occ = np.zeros((side, side), np.uint8)
+    occ[0, :] = occ[-1, :] = occ[:, 0] = occ[:, -1] = 1
+    for _ in range(40):
+        x0, y0 = int(rng.integers(1, side - 300)), int(rng.integers(1, side - 300))
+        w, h = int(rng.integers(1, 300)), int(rng.integers(1, 300))
+        occ[y0:y0 + h, x0:x0 + w] = 1
+    _say(f"largest map n={n} buckets={lb}")
+    rm = oref.RefCDDT(occ, n, threads=8)
+    gm = _map(occ, n, buckets=lb)
+    if lb is not None:
+        info = gm.info()
+        assert info["bucket_lines"] == info["rows"] * 1449
+    k = 50000
+    x = rng.uniform(0, side, k).astype(np.float32)
+    y = rng.uniform(0, side, k).astype(np.float32)
+    th = rng.uniform(-math.pi, math.pi, k).astype(np.float32)
+    want = rm.cast(x, y, th, 65535, threads=8)
+    got = gm.cast(_dev(x), _dev(y), _dev(th), 65535).cpu().numpy()
+    assert (got == want).all(), f"{(got != want).sum()} rays differ"
+    gm.close()
