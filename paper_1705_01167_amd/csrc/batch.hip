@@ -50,7 +50,9 @@ cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, in
                          hipStream_t st, bool zp16, bool counter_zeroed) {
   if (!counter_zeroed) hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, d_counter);
   if (total_tiles > 0) {
-    const unsigned blocks = (unsigned)std::max(1, cus * t.blocks_per_cu);
+    // no more blocks than tiles need (small batches): every wave claims at least once per part
+    const int64_t need = (total_tiles + t.waves_per_block - 1) / t.waves_per_block;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * t.blocks_per_cu, need));
     const unsigned threads = (unsigned)(kWave * t.waves_per_block);
     const int32_t ppt = t.particles_per_tile;
     const size_t lds = tile_lds_bytes(t.search_mode, t.waves_per_block);
