@@ -90,16 +90,21 @@ __global__ __launch_bounds__(kMaxBatchThreads) void k_batch(const FilterDev* __r
       continue;
     }
     ticket = claim(part);
-    int32_t lo = 0, hi = n_filters;  // prefix[lo] <= t < prefix[hi]
+    // prefix[lo] <= t < prefix[hi], by scalar loads: they wait on their own
+    // counter, not behind the ticket claim and other vector loads in flight
+    // (the prefix is written before the launch, so the scalar cache is current)
+    const __attribute__((address_space(4))) int64_t* sprefix =
+        (const __attribute__((address_space(4))) int64_t*)prefix;
+    int32_t lo = 0, hi = n_filters;
     while (hi - lo > 1) {
       int32_t mid = (lo + hi) >> 1;
-      if ((uint64_t)ldg(prefix + mid) <= t)
+      if ((uint64_t)sprefix[mid] <= t)
         lo = mid;
       else
         hi = mid;
     }
     const FilterDev f = filters[lo];
-    const int64_t p0 = (int64_t)(t - (uint64_t)ldg(prefix + lo)) * ppt;
+    const int64_t p0 = (int64_t)(t - (uint64_t)sprefix[lo]) * ppt;
     const int64_t p1 = p0 + ppt < f.n_particles ? p0 + ppt : f.n_particles;
     if constexpr (Q > 0) {
       if (f.n_rays <= kWave) {
