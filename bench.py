@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0
 RAYS = 61
 SEARCHES = 40         # 61 rays with radial pairing of rays r and r + 40 (21 pairs)
 MAX_RANGE = 500
-BUCKETS: int | None = 7  # log2 bucket width of the maps' bucket index (None: no index); set by --buckets
+BUCKETS: int | None = 6  # log2 bucket width of the maps' bucket index (None: no index); set by --buckets
 ZP16 = False  # 16-bit zero points in the bucket lines (results then follow the 16-bit reading); set by --zp16
 PRUNE = False  # PCDDT: pruned static maps (exact for grid states only); set by --prune
 
@@ -64,15 +64,22 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def structure_layout() -> dict:
+    """The maps' structure options; HBM traffic depends on them as much as on the kernel."""
+    return {"bucket_log2": BUCKETS, "zp16": ZP16, "pcddt": PRUNE}
+
+
 def measured_traffic(name: str, particles: int):
-    """HBM bytes per launch from committed counter runs, if taken on the current kernel source."""
+    """HBM bytes per launch from committed counter runs, if taken on the current kernel source,
+    the same particle count and the same structure layout."""
     p = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
     try:
         with open(p) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("particles") != particles:
+    if (d.get("kernel_source_hash") != kernel_source_hash() or d.get("particles") != particles
+            or d.get("layout") != structure_layout()):
         return None
     return d.get("bytes_per_launch")
 
@@ -275,7 +282,7 @@ def run_batched(args) -> dict:
             "zero_points": int(sum(s["zero_points"] for s in stats)),
             "bands": int(sum(s["rows"] for s in stats)),
             "structure_bytes": int(sum(s["device_bytes"] for s in stats)),
-            "bucket_index": ({"log2_width_cells": BUCKETS or 7,
+            "bucket_index": ({"log2_width_cells": BUCKETS,
                               "lines": int(sum(s["bucket_lines"] for s in stats)),
                               "overflow_buckets": int(sum(s["bucket_overflow"] for s in stats)),
                               "zero_points_16bit": ZP16}
@@ -584,8 +591,9 @@ def main():
     ap.add_argument("--filters", type=int, default=64)
     ap.add_argument("--buckets", type=str, default="auto",
                     help="log2 bucket width in cells of the maps' bucket index, 'none' for no index, or 'auto': "
-                         "7 for the batched, floor and updates workloads, none for small and serving (measured "
-                         "better there: small maps stay in cache; serving keeps a lower p99 at light load)")
+                         "6 for the batched workload (185 GB of structure), 7 for floor and updates, none for "
+                         "small and serving (measured better there: small maps stay in cache; serving keeps a "
+                         "lower p99 at light load)")
     ap.add_argument("--zp16", action="store_true",
                     help="16-bit zero points in the bucket lines (answers follow the 16-bit reading, not the "
                          "exact one; needs a bucket index)")
@@ -613,7 +621,7 @@ def main():
         args.serve_requests = 20000 if args.workload == "serving" else 3000
     global BUCKETS
     if args.buckets.lower() == "auto":
-        BUCKETS = None if args.workload in ("small", "serving") else 7
+        BUCKETS = {"batched": 6, "floor": 7, "updates": 7}.get(args.workload)
     else:
         BUCKETS = None if args.buckets.lower() == "none" else int(args.buckets)
     global ZP16, PRUNE

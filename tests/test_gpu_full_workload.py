@@ -1,5 +1,6 @@
-"""The 64-filter workload at full size, built and launched as bench.py does (bucket
-index at 2^7 cells, a tuning the autotuner picks, one captured graph replayed):
+"""The 64-filter workload at full size, built and launched as bench.py does (its
+default bucket index of 2^6 cells, a tuning the autotuner picks, one captured
+graph replayed):
 the log-weights of sampled particles of six filters, from the smallest to the
 largest map, equal the oracle's within 1e-5."""
 import sys
@@ -23,6 +24,7 @@ def test_batched_workload_sampled_against_oracle():
     assert torch.cuda.is_available(), "GPU tests need a ROCm device"
     import bench
     from paper_1705_01167_amd import cddt
+    assert bench.BUCKETS == 6
     _say("full workload: building the 64 maps")
     specs, filters, keep, host, off_h, times = bench.build_batched(64)
     stream = torch.cuda.Stream()
