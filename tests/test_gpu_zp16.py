@@ -102,6 +102,60 @@ def test_zp16_updates(seed):
         assert (got == want).all(), f"step {step}: {(got != want).sum()} rays differ"
 
 
+def test_zp16_plan_equals_plain():
+    """A batched plan holding a 16-bit map runs the persistent kernel built for
+    16-bit lines; over 16-bit, 32-bit bucket and plain maps (and an empty filter)
+    it gives the plain per-filter ranges and weights bit for bit at every search
+    mode, and one 16-bit filter's sampled weights equal the oracle's."""
+    import torch
+    from paper_1705_01167_amd import cddt
+    rng = wl.rng_for(705, 0)
+    M = 500
+    filters, keep, plain, outs, host = [], [], [], [], []
+    kinds = [dict(buckets=7, zp16=True), dict(buckets=None), dict(buckets=6), dict(buckets=9, zp16=True),
+             dict(buckets=6, zp16=True), dict(buckets=8)]
+    for f, kw in enumerate(kinds):
+        side = int(rng.integers(200, 700))
+        occ = wl.building_map(rng, side, side + 11)
+        n = int(rng.choice([108, 200, 360]))
+        gm = _map(occ, n, **kw)
+        P = 0 if f == 5 else int(rng.integers(1, 2500))
+        off = wl.ray_offsets(61)
+        px, py, pth = wl.free_poses(rng, occ, P)
+        obs, _ = wl.observations(rng, occ, off, M)
+        table = wl.beam_table(M, wl.beam_params(rng))
+        t = [_dev(px), _dev(py), _dev(pth), _dev(off), _dev(obs), _dev(table)]
+        lw, rr = gm.weight(*t, M, ranges=True)
+        plain.append((lw.clone(), rr.clone()))
+        out = torch.empty_like(lw)
+        out_r = torch.empty_like(rr)
+        filters.append(cddt.make_filter(gm, *t, M, out, out_r))
+        keep += [gm, t]
+        outs.append((out, out_r))
+        host.append((occ, n, px, py, pth, off, obs, table))
+    plan = cddt.Plan(filters, keepalive=keep)
+    for tuning in ((8, 2, 8, 7), (8, 2, 8, 9), (4, 4, 4, 6), (16, 1, 16, 10), (16, 2, 4, 8), (2, 2, 2, 2),
+                   (8, 2, 8, 0), (3, 1, 2, 1), (5, 2, 2, 5)):
+        _say(f"zp16 plan: tuning {tuning}")
+        plan.tuning = tuning
+        for o, r in outs:
+            o.fill_(float("nan"))
+            r.fill_(-1)
+        plan.run()
+        torch.cuda.synchronize()
+        for i, ((got, got_r), (want, want_r)) in enumerate(zip(outs, plain)):
+            assert torch.equal(got_r, want_r), f"tuning {tuning}: filter {i} ranges differ"
+            assert torch.equal(got, want), f"tuning {tuning}: filter {i} weights differ"
+    occ, n, px, py, pth, off, obs, table = host[0]
+    idx = np.sort(rng.choice(px.size, size=min(px.size, 200), replace=False))
+    rm = oref.RefCDDT(occ, n, threads=8, zp16=True)
+    want = rm.weight(px[idx], py[idx], pth[idx], off, obs, table, M, threads=8)
+    got = outs[0][0].cpu().numpy()[idx].astype(np.float64)
+    assert (np.abs(got - want) <= 1e-5 * np.maximum(1.0, np.abs(want))).all()
+    rm.close()
+    plan.close()
+
+
 def test_zp16_needs_buckets():
     from paper_1705_01167_amd import cddt
     with pytest.raises(cddt.CddtError):
