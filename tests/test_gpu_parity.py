@@ -295,23 +295,35 @@ def test_batched_plan_equals_plain():
     plan.close()
 
 
-def test_weight_many_particles_tiled():
-    """Plain weights over >= 2^17 particles take the queued-search path: same results."""
+@pytest.mark.parametrize("layout", [dict(), dict(buckets=6), dict(buckets=7, zp16=True)],
+                         ids=["bands", "buckets6", "buckets7-zp16"])
+def test_weight_many_particles_tiled(layout):
+    """Plain weights over >= 2^17 particles take the queued-search path (on bucket
+    maps with the half-line first pass, 16-bit lines included): same results as the
+    oracle (its 16-bit reading for 16-bit lines) and as the one-particle-per-wave path."""
     torch = _torch()
     rng = wl.rng_for(306, 0)
     occ = wl.building_map(rng, 700, 500)
     n, M = 200, 400
-    rm = oref.RefCDDT(occ, n)
-    gm = _gpu_map(occ, n)
+    rm = oref.RefCDDT(occ, n, zp16=bool(layout.get("zp16")))
+    gm = _gpu_map(occ, n, **layout)
     P = (1 << 17) + 77
     px, py, pth = wl.free_poses(rng, occ, P)
+    # a NaN pose, an off-map pose and poses inside occupied cells, inside the first tiles
+    wall = np.argwhere(occ != 0)
+    px[1], px[2] = np.nan, -3.0
+    for k, (j, i) in enumerate(wall[:: max(1, len(wall) // 5)][:5]):
+        px[5 + 3 * k], py[5 + 3 * k] = np.float32(i + 0.5), np.float32(j + 0.5)
     off = wl.ray_offsets(61)
     obs = rng.integers(0, M + 1, 61).astype(np.int32)
     table = wl.beam_table(M, wl.beam_params(rng))
     ref_lw, ref_r = rm.weight(px, py, pth, off, obs, table, M, threads=16, want_ranges=True)
     lw, rr = _gpu_map_weight(gm, px, py, pth, off, obs, table, M)
+    guarded = [1, 2] + [5 + 3 * k for k in range(5)]
+    assert (np.asarray(rr).reshape(P, -1)[guarded] == 0).all()  # NaN, off-map, occupied: range 0
     assert (rr == ref_r).all()
     assert (np.abs(lw - ref_lw) <= RTOL * np.maximum(1.0, np.abs(ref_lw))).all()
     # the first particles alone (one-particle-per-wave path) give the same bits
     lw_small, _ = _gpu_map_weight(gm, px[:1000], py[:1000], pth[:1000], off, obs, table, M)
     assert (lw_small == lw[:1000]).all()
+    rm.close()
