@@ -15,13 +15,13 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def _setup(seed=0, sides=(300, 500, 800), bins=(108, 200, 360), M=300):
+def _setup(seed=0, sides=(300, 500, 800), bins=(108, 200, 360), M=300, layouts=None):
     from paper_1705_01167_amd import cddt
     rng = wl.rng_for(501, seed)
     maps, offs, tabs, occs = [], [], [], []
     for f, (side, n) in enumerate(zip(sides, bins)):
         occ = wl.building_map(rng, side, side)
-        maps.append(cddt.Map(_dev(occ), n))
+        maps.append(cddt.Map(_dev(occ), n, **(layouts[f] if layouts else {})))
         offs.append(wl.ray_offsets(61))
         tabs.append(_dev(wl.beam_table(M, wl.beam_params(rng))))
         occs.append(occ)
@@ -60,6 +60,24 @@ def test_alone_equals_mix_equals_plain():
     for i in ids:
         s, d = srv.times(i)
         assert 0 <= s <= d
+    srv.close()
+
+
+def test_mixed_map_layouts_equal_plain():
+    """Resident maps with the bucket index, with 16-bit lines and without the index:
+    the server runs the persistent kernel built for 16-bit lines, and every result
+    equals the plain call on its map."""
+    from paper_1705_01167_amd import cddt
+    layouts = [dict(buckets=6), dict(buckets=7, zp16=True), dict()]
+    rng, maps, offs, tabs, occs, M = _setup(seed=3, layouts=layouts)
+    reqs = _requests(rng, occs, M, 90)
+    srv = cddt.Server(maps, offs, tabs, [M] * 3, budget_bytes=8 << 20, n_lanes=1, max_batch=32)
+    ids = [srv.submit(*r) for r in reqs]
+    got = [srv.wait(i) for i in ids]
+    assert srv.stats()["completed"] == 90
+    for a, (m, px, py, pth, obs) in zip(got, reqs):
+        plain = maps[m].weight(_dev(px), _dev(py), _dev(pth), _dev(offs[m]), _dev(obs), tabs[m], M)
+        assert plain.cpu().numpy().tobytes() == a.tobytes(), f"map {m} ({layouts[m]})"
     srv.close()
 
 
