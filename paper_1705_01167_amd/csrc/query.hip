@@ -13,8 +13,8 @@ constexpr int kWeightK = 0;
 
 // One wave takes 64 consecutive rays at a time (lane = ray); the loop bound is
 // the same for every lane of a wave so the cooperative search stays converged.
-// Z: instantiated for maps with 16-bit zero points in their bucket lines.
-template <bool Z>
+// Maps without a bucket index only (those with one go to k_cast_tiles), so
+// never 16-bit lines.
 __global__ __launch_bounds__(kCastThreads) void k_cast(MapDev m, const float* __restrict__ x,
                                                        const float* __restrict__ y,
                                                        const float* __restrict__ th, int64_t n,
@@ -26,7 +26,7 @@ __global__ __launch_bounds__(kCastThreads) void k_cast(MapDev m, const float* __
     const int64_t i = c * kWave + lane;
     const bool active = i < n;
     const float xi = active ? ldg(x + i) : 0.0f, yi = active ? ldg(y + i) : 0.0f, ti = active ? ldg(th + i) : 0.0f;
-    const int32_t r = wave_cast<kCastK, Z>(m, active, xi, yi, ti, max_range);
+    const int32_t r = wave_cast<kCastK, false>(m, active, xi, yi, ti, max_range);
     if (active) stg(out + i, r);
   }
 }
@@ -95,10 +95,7 @@ cddt_status launch_cast(const MapDev& m, const float* x, const float* y, const f
   }
   int64_t blocks = (n + kCastThreads - 1) / kCastThreads;
   if (blocks > (1 << 16)) blocks = 1 << 16;
-  if (m.zp16)
-    hipLaunchKernelGGL(k_cast<true>, dim3((unsigned)blocks), dim3(kCastThreads), 0, st, m, x, y, th, n, max_range, out);
-  else
-    hipLaunchKernelGGL(k_cast<false>, dim3((unsigned)blocks), dim3(kCastThreads), 0, st, m, x, y, th, n, max_range, out);
+  hipLaunchKernelGGL(k_cast, dim3((unsigned)blocks), dim3(kCastThreads), 0, st, m, x, y, th, n, max_range, out);
   CDDT_HIP(hipGetLastError());
   return CDDT_OK;
 }
