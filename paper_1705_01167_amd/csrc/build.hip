@@ -101,30 +101,42 @@ __global__ void k_project(const SliceDev* __restrict__ slices, const uint32_t* _
 // longest slice extent of the largest map at the narrowest bucket width.
 constexpr int kFillMaxBuckets = 1456;
 constexpr int kFillThreads = 256;
+// LDS words of one wave's tables: first[0..nbk] and one mark byte per bucket.
+// Sized per map, so that maps with few buckets per band keep more waves per CU.
+__host__ __device__ constexpr int32_t fill_wave_words(int32_t nbk) { return (nbk + 1) + (nbk + 3) / 4; }
+static_assert((kFillThreads / 64) * fill_wave_words(kFillMaxBuckets) * 4 <= 65536, "fill tables fit in LDS");
+
+// The slice of a band: the last s with row_start[s] <= band (row_start rises
+// from row_start[0] = 0).  A 64-ary search by the whole wave, one candidate
+// per lane and the ballot's count as the answer: two dependent loads instead
+// of log2(half).  `band` is the same on every lane.
+static_assert(kMaxBins / 2 <= 64 * 64, "two levels of 64 candidates cover every slice count");
+__device__ __forceinline__ int32_t band_slice(const int32_t* __restrict__ row_start, int32_t half, uint32_t band) {
+  const int lane = threadIdx.x & 63;
+  const int32_t stride = (half + 63) >> 6;
+  int32_t s = lane * stride;
+  uint64_t m = __ballot(s < half && (uint32_t)row_start[s] <= band);
+  int32_t lo = (__popcll(m) - 1) * stride;
+  if (stride > 1) {
+    s = lo + lane;
+    m = __ballot(lane < stride && s < half && (uint32_t)row_start[s] <= band);
+    lo += __popcll(m) - 1;
+  }
+  return lo;
+}
 __global__ __launch_bounds__(kFillThreads) void k_bucket_fill(
     const int32_t* __restrict__ hdr, const int32_t* __restrict__ zeros, const SliceDev* __restrict__ slices,
     const int32_t* __restrict__ row_start, int32_t half, int32_t shift, int32_t nbk, int32_t* __restrict__ bk,
     const uint32_t* __restrict__ rows_list, uint64_t n_bands, unsigned long long* __restrict__ over, int partial,
     int zp16, const uint32_t* __restrict__ rec_off, const int2* __restrict__ recs, uint32_t n_recs) {
-  __shared__ int32_t first_lds[kFillThreads / 64][kFillMaxBuckets + 1];
-  __shared__ uint8_t mark_lds[kFillThreads / 64][kFillMaxBuckets];
-  int32_t* first = first_lds[threadIdx.x >> 6];
-  uint8_t* mark = mark_lds[threadIdx.x >> 6];
+  extern __shared__ int32_t fill_lds[];
+  int32_t* first = fill_lds + (threadIdx.x >> 6) * fill_wave_words(nbk);
+  uint8_t* mark = reinterpret_cast<uint8_t*>(first + nbk + 1);
   const int lane = threadIdx.x & 63;
   const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   for (uint64_t t = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < n_bands; t += n_waves) {
     const uint32_t band = rows_list ? rows_list[t] : (uint32_t)t;
-    int32_t lo = 0, cnt = half;  // slice: last row_start <= band
-    while (cnt > 1) {
-      const int32_t h2 = cnt >> 1;
-      if ((uint32_t)row_start[lo + h2] <= band) {
-        lo += h2;
-        cnt -= h2;
-      } else {
-        cnt = h2;
-      }
-    }
-    const int32_t zlo = slices[lo].zlo;
+    const int32_t zlo = slices[band_slice(row_start, half, band)].zlo;
     const int32_t* node = hdr + (int64_t)band * kNodeInts;
     const int32_t* keys = zeros + (uint32_t)node[0];
     const int32_t len = node[1];
@@ -579,7 +591,8 @@ cddt_status fill_buckets(cddt_map_s* m, const uint32_t* rows_list, int64_t n_row
   const int partial = rows_list ? 1 : 0;
   if (!partial) CDDT_HIP(hipMemsetAsync(m->d_bk_over, 0, 8, st));
   const uint64_t blocks = std::min<uint64_t>(((uint64_t)n_rows + 3) / 4, 1u << 16);  // 4 bands per block
-  hipLaunchKernelGGL(k_bucket_fill, dim3((unsigned)std::max<uint64_t>(blocks, 1)), dim3(kFillThreads), 0, st,
+  const size_t lds = (size_t)(kFillThreads / 64) * fill_wave_words(m->nbk) * sizeof(int32_t);
+  hipLaunchKernelGGL(k_bucket_fill, dim3((unsigned)std::max<uint64_t>(blocks, 1)), dim3(kFillThreads), lds, st,
                      (const int32_t*)m->d_hdr, (const int32_t*)m->d_zeros, (const SliceDev*)m->d_slices,
                      (const int32_t*)m->d_row_start, m->half, 16 + m->blog2, m->nbk, m->d_bk, rows_list,
                      (uint64_t)n_rows, m->d_bk_over, partial, (m->flags & CDDT_FLAG_ZP16) ? 1 : 0,
