@@ -77,3 +77,15 @@ def test_pair_offset_host_helper():
     assert cddt.pair_offset(wl.ray_offsets(7, fov=np.pi / 2)) == 0
     assert cddt.pair_offset(np.array([0.0, np.pi], np.float32)) == 1
     assert cddt.pair_offset(np.array([0.5], np.float32)) == 0
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No CPU fallback: every call path goes through lib(), which raises when the
+    compiled library is absent."""
+    from paper_1705_01167_amd import cddt
+    monkeypatch.setattr(cddt, "_lib", None)
+    monkeypatch.setattr(cddt, "LIB_PATH", str(tmp_path / "libcddt.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        cddt.lib()
+    with pytest.raises(RuntimeError, match="missing"):
+        cddt.pair_offset(np.zeros(4, np.float32))
