@@ -111,7 +111,11 @@ def timed(fn, steps: int, warmup: int, stream):
 # ---------------------------------------------------------------------------
 # Batched filters (default workload)
 # ---------------------------------------------------------------------------
-def build_batched(n_filters: int):
+def build_batched(n_filters: int, with_ranges: bool = False):
+    """The many-filter workload's maps, particles, observations and tables on the device.
+
+    with_ranges: every filter also gets an int32 [particle][ray] ranges output (kept in its entry of
+    `keep` under "ranges"); the timed benchmark runs without them."""
     import torch
     from paper_1705_01167_amd import cddt
     from paper_1705_01167_amd import workloads as wl
@@ -145,8 +149,11 @@ def build_batched(n_filters: int):
             d[k].copy_(torch.from_numpy(v))
         p_off += P
         lw = torch.zeros(sp["particles"], dtype=torch.float32, device="cuda")
+        if with_ranges:
+            d["ranges"] = torch.empty((P, RAYS), dtype=torch.int32, device="cuda")
+        d["off"] = off
         filters.append(cddt.make_filter(m, d["px"], d["py"], d["pth"], off, d["obs"], d["table"], MAX_RANGE,
-                                        lw, pair=pair))
+                                        lw, ranges=d.get("ranges"), pair=pair))
         keep.append((m, d, lw))
         host.append(dict(occ=occ, px=px, py=py, pth=pth, obs=obs, table=table, n=sp["theta_bins"]))
         t_gen += t1 - t0

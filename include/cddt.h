@@ -207,11 +207,16 @@ cddt_status cddt_info(cddt_map m, cddt_stats* out_h);
 cddt_status cddt_slice_table(cddt_map m, int32_t* c_h, int32_t* s_h, int32_t* row_min_h,
                              int32_t* nrows_h, float* k_scale_h);
 
-/* Canonical copy of the structure: band lengths (host int32[rows]) in
- * (slice, band) order and the zero points (host int32[zero_points]) of all
- * bands concatenated in that order, each band ascending; slack removed.
- * Either array may be NULL.  Blocks.  Errors: EINVAL, EDEVICE. */
-cddt_status cddt_export(cddt_map m, int32_t* row_len_h, int32_t* zeros_h);
+/* Canonical copy of the structure (Sec. IV-A: per stored slice, per band,
+ * the ascending zero points) as compressed rows with the slack removed:
+ *   row_start_h  host int64[rows + 1]: offset of each band's first zero point
+ *                in zeros_h, in (slice, band) order; row_start_h[rows] is the
+ *                total (int64: a structure may hold more than 2^31 points);
+ *   row_len_h    host int32[rows]: band lengths;
+ *   zeros_h      host int32[zero_points]: all bands concatenated, each band
+ *                ascending (duplicates kept).
+ * Any of the three may be NULL.  Blocks.  Errors: EINVAL, EDEVICE. */
+cddt_status cddt_export(cddt_map m, int64_t* row_start_h, int32_t* row_len_h, int32_t* zeros_h);
 
 /* Current occupancy grid (host uint8[W*H]).  Blocks. */
 cddt_status cddt_export_grid(cddt_map m, uint8_t* occ_h);
@@ -225,6 +230,15 @@ cddt_status cddt_export_grid(cddt_map m, uint8_t* occ_h);
  * cddt_weight per filter.  Running is capture-safe (kernel launches only, no
  * allocation, memset or synchronisation), so a run can be recorded into a
  * hipGraph and replayed each filter step with new data in the same buffers.
+ * Maps of a plan may be updated between runs (cddt_update on the plan's
+ * stream, or synchronised with it).  An update that re-lays a map's whole
+ * structure (static and pruned maps, or a full spare area) moves its band
+ * arrays; cddt_plan_run, cddt_plan_run_mcl, cddt_plan_replay, cddt_plan_time
+ * and cddt_plan_run_plain notice this and upload the plan's descriptors again
+ * on their stream before launching, so a captured graph keeps working (its
+ * kernels read the descriptors from device memory).  Only the plan calls do
+ * this: a graph replayed with hipGraphLaunch directly after such an update
+ * reads freed memory.
  * ------------------------------------------------------------------------- */
 typedef struct {
   cddt_map map;
@@ -274,6 +288,17 @@ cddt_status cddt_plan_time(cddt_plan p, const cddt_tuning* tuning_h, int32_t rep
 /* The same filters as plain launches: one cddt_weight per filter, in order. */
 cddt_status cddt_plan_run_plain(cddt_plan p, void* stream);
 cddt_status cddt_plan_destroy(cddt_plan p);
+
+/* Tunings found by an autotuner, kept in the library for the rest of the
+ * process and keyed by a signature of the filter set (device, filter count,
+ * particle total to the nearest power of two, the set of theta bin counts and
+ * of structure layouts).  cddt_plan_create and cddt_batch_weight called
+ * without a tuning use the tuning recorded for their filter set, else the
+ * library default.  get returns that tuning and found_h = 1 if one was
+ * recorded (found_h may be NULL).  Errors: EINVAL. */
+cddt_status cddt_tuning_cache_put(const cddt_filter* filters_h, int32_t n_filters, const cddt_tuning* tuning_h);
+cddt_status cddt_tuning_cache_get(const cddt_filter* filters_h, int32_t n_filters, cddt_tuning* tuning_h,
+                                  int32_t* found_h);
 
 /* ---------------------------------------------------------------------------
  * The particle-filter steps around the sensor model.  The paper's Monte

@@ -99,7 +99,7 @@ SIGNATURES = {
     "cddt_pair_offset": (_i32, [_vp, _i32]),
     "cddt_info": (_i32, [_vp, C.POINTER(Stats)]),
     "cddt_slice_table": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
-    "cddt_export": (_i32, [_vp, _vp, _vp]),
+    "cddt_export": (_i32, [_vp, _vp, _vp, _vp]),
     "cddt_export_grid": (_i32, [_vp, _vp]),
     "cddt_plan_create": (_i32, [_vp, _i32, _vp, _vp, C.POINTER(_vp)]),
     "cddt_plan_set_tuning": (_i32, [_vp, C.POINTER(Tuning)]),
@@ -110,6 +110,8 @@ SIGNATURES = {
     "cddt_plan_time": (_i32, [_vp, C.POINTER(Tuning), _i32, _vp, C.POINTER(C.c_float)]),
     "cddt_plan_run_plain": (_i32, [_vp, _vp]),
     "cddt_plan_destroy": (_i32, [_vp]),
+    "cddt_tuning_cache_put": (_i32, [_vp, _i32, C.POINTER(Tuning)]),
+    "cddt_tuning_cache_get": (_i32, [_vp, _i32, C.POINTER(Tuning), C.POINTER(_i32)]),
     "cddt_device_cus": (_i32, []),
     "cddt_probe_gather": (_i32, [_vp, _i64, _i32, _i32, _i32, _u32, _vp, _vp]),
     "cddt_server_create": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, C.POINTER(ServerConfig), C.POINTER(_vp)]),
@@ -294,13 +296,17 @@ class Map:
         _check(lib().cddt_slice_table(self.handle, *(a.ctypes.data_as(C.c_void_p) for a in (c, s, rmin, nrows, k))))
         return c, s, rmin, nrows, k[0]
 
-    def export(self):
-        """(nrows per slice, band lengths, zero points) in canonical order (host numpy)."""
+    def export(self, with_starts: bool = False):
+        """(nrows per slice, band lengths, zero points) in canonical order (host numpy); with_starts
+        adds the compressed-row offsets (int64[rows + 1]) as a fourth element."""
         st = self.info()
         rl = np.zeros(st["rows"], np.int32)
         zz = np.zeros(max(st["zero_points"], 1), np.int32)
-        _check(lib().cddt_export(self.handle, rl.ctypes.data_as(C.c_void_p), zz.ctypes.data_as(C.c_void_p)))
-        return self.slice_table()[3], rl, zz[:st["zero_points"]]
+        rs = np.zeros(st["rows"] + 1, np.int64)
+        _check(lib().cddt_export(self.handle, rs.ctypes.data_as(C.c_void_p), rl.ctypes.data_as(C.c_void_p),
+                                 zz.ctypes.data_as(C.c_void_p)))
+        out = (self.slice_table()[3], rl, zz[:st["zero_points"]])
+        return out + (rs,) if with_starts else out
 
     def grid(self) -> np.ndarray:
         g = np.zeros((self.height, self.width), np.uint8)
@@ -356,6 +362,7 @@ class Plan:
                                       C.byref(t) if t is not None else None, _stream(stream), C.byref(h)))
         self.handle = h
         self.n_filters = len(filters)
+        self._arr = arr
         self._keep = keepalive
 
     def close(self):
@@ -409,6 +416,22 @@ class Plan:
         ms = C.c_float()
         _check(lib().cddt_plan_time(self.handle, C.byref(t), int(reps), _stream(stream), C.byref(ms)))
         return float(ms.value)
+
+
+def tuning_cache_put(filters, tuning) -> None:
+    """Record `tuning` in the library for this filter set (used when no tuning is given)."""
+    arr = (Filter * len(filters))(*filters)
+    t = Tuning(*tuning)
+    _check(lib().cddt_tuning_cache_put(C.cast(arr, C.c_void_p), len(filters), C.byref(t)))
+
+
+def tuning_cache_get(filters):
+    """(tuning the library uses for this filter set when none is given, whether one was recorded)."""
+    arr = (Filter * len(filters))(*filters)
+    t = Tuning()
+    found = C.c_int32()
+    _check(lib().cddt_tuning_cache_get(C.cast(arr, C.c_void_p), len(filters), C.byref(t), C.byref(found)))
+    return t.as_tuple(), bool(found.value)
 
 
 def device_cus() -> int:

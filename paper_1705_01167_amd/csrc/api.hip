@@ -351,24 +351,29 @@ cddt_status cddt_slice_table(cddt_map m, int32_t* c_h, int32_t* s_h, int32_t* ro
   return CDDT_OK;
 }
 
-cddt_status cddt_export(cddt_map m, int32_t* row_len_h, int32_t* zeros_h) {
+cddt_status cddt_export(cddt_map m, int64_t* row_start_h, int32_t* row_len_h, int32_t* zeros_h) {
   if (!m) return fail(CDDT_EINVAL, "cddt_export: map is NULL");
   CDDT_HIP(hipDeviceSynchronize());
   std::vector<int32_t> hdr((size_t)m->rows * kNodeInts);
   CDDT_HIP(hipMemcpy(hdr.data(), m->d_hdr, 4 * hdr.size(), hipMemcpyDeviceToHost));
-  std::vector<int32_t> z((size_t)std::max<int64_t>(m->capacity, 1));
-  if (m->capacity) CDDT_HIP(hipMemcpy(z.data(), m->d_zeros, 4 * (size_t)m->capacity, hipMemcpyDeviceToHost));
   int64_t total = 0;
   for (int64_t r = 0; r < m->rows; ++r) total += hdr[r * kNodeInts + 1];
   if (total != m->zero_points) return fail(CDDT_EINTERNAL, "cddt_export: band lengths do not add up");
+  std::vector<int32_t> z;
+  if (zeros_h && m->capacity) {
+    z.resize((size_t)m->capacity);
+    CDDT_HIP(hipMemcpy(z.data(), m->d_zeros, 4 * (size_t)m->capacity, hipMemcpyDeviceToHost));
+  }
   int64_t o = 0;
   for (int64_t r = 0; r < m->rows; ++r) {
     const uint32_t start = (uint32_t)hdr[r * kNodeInts];
     const int32_t len = hdr[r * kNodeInts + 1];
+    if (row_start_h) row_start_h[r] = o;
     if (row_len_h) row_len_h[r] = len;
-    if (zeros_h) std::memcpy(zeros_h + o, z.data() + start, 4 * (size_t)len);
+    if (zeros_h && len) std::memcpy(zeros_h + o, z.data() + start, 4 * (size_t)len);
     o += len;
   }
+  if (row_start_h) row_start_h[m->rows] = o;
   return CDDT_OK;
 }
 

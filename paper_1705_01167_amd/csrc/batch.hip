@@ -19,6 +19,7 @@
 struct cddt_plan_s {
   std::vector<cddt_filter> filters;
   std::vector<cddt::FilterDev> fdev;
+  std::vector<uint64_t> gen;  // each filter's map generation when fdev was taken
   std::vector<int64_t> prefix;  // n_filters + 1 tile offsets for the current tuning
   cddt::FilterDev* d_filters = nullptr;
   int64_t* d_prefix = nullptr;
@@ -124,6 +125,24 @@ cddt_status apply_tuning(cddt_plan_s* p, const cddt_tuning& t, hipStream_t st) {
   return CDDT_OK;
 }
 
+// A map whose structure was re-laid since the plan took its descriptor (an
+// update that rebuilt it) has new band arrays: take the descriptors again and
+// upload them in stream order before the next launch or graph replay, which
+// read them from d_filters.
+cddt_status refresh_descriptors(cddt_plan_s* p, hipStream_t st) {
+  bool stale = false;
+  for (size_t f = 0; f < p->filters.size(); ++f) {
+    if (p->filters[f].map->generation == p->gen[f]) continue;
+    p->fdev[f] = filter_dev(p->filters[f]);
+    p->gen[f] = p->filters[f].map->generation;
+    stale = true;
+  }
+  if (stale)
+    CDDT_HIP(hipMemcpyAsync(p->d_filters, p->fdev.data(), sizeof(FilterDev) * p->fdev.size(), hipMemcpyHostToDevice,
+                            st));
+  return CDDT_OK;
+}
+
 cddt_status launch_plan(cddt_plan_s* p, hipStream_t st) {
   return launch_batch(p->d_filters, p->d_prefix, (int32_t)p->filters.size(), p->total_tiles, p->tuning,
                       p->d_counter, p->cus, st, p->zp16);
@@ -177,12 +196,15 @@ cddt_status cddt_plan_create(const cddt_filter* filters_h, int32_t n_filters, co
   if (!filters_h || n_filters < 1 || n_filters > 65536)
     return fail(CDDT_EINVAL, "cddt_plan_create: need 1..65536 filters");
   for (int32_t f = 0; f < n_filters; ++f) CDDT_TRY(validate_filter(filters_h[f], "cddt_plan_create"));
-  cddt_tuning t = tuning_h ? *tuning_h : default_tuning();
+  cddt_tuning t = tuning_h ? *tuning_h : cached_tuning(filters_h, n_filters);
   CDDT_TRY(check_tuning(t));
   hipStream_t st = (hipStream_t)stream;
   cddt_plan_s* p = new cddt_plan_s();
   p->filters.assign(filters_h, filters_h + n_filters);
-  for (auto& f : p->filters) p->fdev.push_back(filter_dev(f));
+  for (auto& f : p->filters) {
+    p->fdev.push_back(filter_dev(f));
+    p->gen.push_back(f.map->generation);
+  }
   for (auto& f : p->fdev) p->zp16 = p->zp16 || f.map.zp16;
   p->cus = cddt_device_cus();
   if (p->cus <= 0) {
@@ -230,6 +252,7 @@ cddt_status cddt_plan_get_tuning(cddt_plan p, cddt_tuning* tuning_h) {
 
 cddt_status cddt_plan_run(cddt_plan p, void* stream) {
   if (!p) return fail(CDDT_EINVAL, "cddt_plan_run: plan is NULL");
+  CDDT_TRY(refresh_descriptors(p, (hipStream_t)stream));
   return launch_plan(p, (hipStream_t)stream);
 }
 
@@ -237,6 +260,7 @@ cddt_status cddt_plan_capture(cddt_plan p, void* stream) {
   if (!p) return fail(CDDT_EINVAL, "cddt_plan_capture: plan is NULL");
   if (!stream) return fail(CDDT_EINVAL, "cddt_plan_capture: capture needs a non-default stream");
   hipStream_t st = (hipStream_t)stream;
+  CDDT_TRY(refresh_descriptors(p, st));
   return capture_into(p, st, [&] { return launch_plan(p, st); });
 }
 
@@ -292,6 +316,7 @@ cddt_status cddt_plan_set_mcl(cddt_plan p, const float* odom, const uint32_t* u,
 cddt_status cddt_plan_run_mcl(cddt_plan p, void* stream) {
   if (!p) return fail(CDDT_EINVAL, "cddt_plan_run_mcl: plan is NULL");
   if (!p->mcl_odom) return fail(CDDT_EINVAL, "cddt_plan_run_mcl: call cddt_plan_set_mcl first");
+  CDDT_TRY(refresh_descriptors(p, (hipStream_t)stream));
   return launch_mcl(p, (hipStream_t)stream);
 }
 
@@ -300,12 +325,14 @@ cddt_status cddt_plan_capture_mcl(cddt_plan p, void* stream) {
   if (!stream) return fail(CDDT_EINVAL, "cddt_plan_capture_mcl: capture needs a non-default stream");
   if (!p->mcl_odom) return fail(CDDT_EINVAL, "cddt_plan_capture_mcl: call cddt_plan_set_mcl first");
   hipStream_t st = (hipStream_t)stream;
+  CDDT_TRY(refresh_descriptors(p, st));
   return capture_into(p, st, [&] { return launch_mcl(p, st); });
 }
 
 cddt_status cddt_plan_replay(cddt_plan p, void* stream) {
   if (!p) return fail(CDDT_EINVAL, "cddt_plan_replay: plan is NULL");
   if (!p->exec) return fail(CDDT_EINVAL, "cddt_plan_replay: no captured graph");
+  CDDT_TRY(refresh_descriptors(p, (hipStream_t)stream));
   CDDT_HIP(hipGraphLaunch(p->exec, (hipStream_t)stream));
   return CDDT_OK;
 }
@@ -314,6 +341,7 @@ cddt_status cddt_plan_time(cddt_plan p, const cddt_tuning* tuning_h, int32_t rep
   if (!p || !ms_h || reps < 1) return fail(CDDT_EINVAL, "cddt_plan_time: bad argument");
   hipStream_t st = (hipStream_t)stream;
   cddt_tuning keep = p->tuning;
+  CDDT_TRY(refresh_descriptors(p, st));
   if (tuning_h) CDDT_TRY(apply_tuning(p, *tuning_h, st));
   hipEvent_t a, b;
   CDDT_HIP(hipEventCreate(&a));
@@ -336,6 +364,7 @@ cddt_status cddt_plan_time(cddt_plan p, const cddt_tuning* tuning_h, int32_t rep
 
 cddt_status cddt_plan_run_plain(cddt_plan p, void* stream) {
   if (!p) return fail(CDDT_EINVAL, "cddt_plan_run_plain: plan is NULL");
+  CDDT_TRY(refresh_descriptors(p, (hipStream_t)stream));
   for (auto& f : p->fdev) CDDT_TRY(launch_weight(f, (hipStream_t)stream));
   return CDDT_OK;
 }

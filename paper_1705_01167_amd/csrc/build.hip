@@ -3,7 +3,8 @@
 //
 // Pipeline (one stream):
 //   k_edges    (x2)  8-neighbour erosion test per cell; a count pass, then a
-//                    compaction pass (wave ballot + one atomic per wave).
+//                    compaction pass (wave ballots, one atomic per block of
+//                    4096 cells).
 //   k_project  (count) per (slice, edge cell): the bands its rotated square
 //                    covers; atomic per-band counters.
 //   scan             per-band region = key capacity (length + slack, whole
@@ -42,25 +43,49 @@ struct BuildCounters {
   uint64_t max_len;
 };
 
-// Edge cells are packed as i | j << 16 (both < 2^14).
-__global__ void k_edges(const uint8_t* __restrict__ occ, int w, int h, int full,
-                        uint32_t* __restrict__ list, BuildCounters* ctr, int write) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool e = false;
-  int i = 0, j = 0;
-  if (idx < (int64_t)w * h) {
+// Edge cells are packed as i | j << 16 (both < 2^14).  A block covers
+// kEdgeThreads * kEdgeSweeps consecutive cells: it counts its edge cells
+// (wave ballots summed in LDS), takes its place in the list with one atomic
+// and, in the write pass, sweeps its cells again to store them.  The list
+// order is arbitrary; the build does not depend on it.
+constexpr int kEdgeThreads = 256;
+constexpr int kEdgeSweeps = 16;
+__global__ __launch_bounds__(kEdgeThreads) void k_edges(const uint8_t* __restrict__ occ, int w, int h, int full,
+                                                        uint32_t* __restrict__ list, BuildCounters* ctr, int write) {
+  __shared__ uint32_t wave_cnt[kEdgeThreads / 64];
+  __shared__ uint32_t block_base;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t cells = (int64_t)w * h;
+  const int64_t first = (int64_t)blockIdx.x * (kEdgeThreads * kEdgeSweeps);
+  auto test = [&](int k, int& i, int& j) {
+    const int64_t idx = first + (int64_t)k * kEdgeThreads + threadIdx.x;
+    if (idx >= cells) return false;
     j = (int)(idx / w);
     i = (int)(idx - (int64_t)j * w);
-    e = edge_cell(occ, w, h, i, j, full);
+    return edge_cell(occ, w, h, i, j, full);
+  };
+  uint32_t mine = 0;
+  for (int k = 0; k < kEdgeSweeps; ++k) {
+    int i = 0, j = 0;
+    mine += (uint32_t)__popcll(__ballot(test(k, i, j)));
   }
-  uint64_t mask = __ballot(e);
-  int lane = threadIdx.x & 63;
-  uint32_t base = 0;
-  if (lane == 0 && mask) base = atomicAdd(&ctr->edges, (uint32_t)__popcll(mask));
-  base = __shfl(base, 0);
-  if (write && e) {
-    uint64_t below = mask & ((1ull << lane) - 1ull);
-    list[base + (uint32_t)__popcll(below)] = (uint32_t)i | ((uint32_t)j << 16);
+  if (lane == 0) wave_cnt[wave] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t total = 0;
+    for (int q = 0; q < kEdgeThreads / 64; ++q) total += wave_cnt[q];
+    block_base = total ? atomicAdd(&ctr->edges, total) : 0u;
+  }
+  __syncthreads();
+  if (!write) return;
+  uint32_t off = block_base;
+  for (int q = 0; q < wave; ++q) off += wave_cnt[q];
+  for (int k = 0; k < kEdgeSweeps; ++k) {
+    int i = 0, j = 0;
+    const bool e = test(k, i, j);
+    const uint64_t mask = __ballot(e);
+    if (e) list[off + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)i | ((uint32_t)j << 16);
+    off += (uint32_t)__popcll(mask);
   }
 }
 
@@ -474,6 +499,7 @@ cddt_status refresh_stats(cddt_map_s* m, hipStream_t st) {
 // Blocks on `st`.
 cddt_status build_structure(cddt_map_s* m, hipStream_t st) {
   free_structure(m);
+  ++m->generation;
   const int64_t cells = (int64_t)m->w * m->h;
   const int64_t R = m->rows;
   Temp ctr_t(&m->alloc), edges_t(&m->alloc), cnt_t(&m->alloc), big_t(&m->alloc);
@@ -484,7 +510,8 @@ cddt_status build_structure(cddt_map_s* m, hipStream_t st) {
   const int no_slack = (m->flags & CDDT_FLAG_STATIC) ? 1 : 0;
 
   // 1. edge map: count, then compact
-  hipLaunchKernelGGL(k_edges, dim3(grid_for(cells, 256)), dim3(256), 0, st, m->d_occ, m->w, m->h, full,
+  const unsigned edge_blocks = grid_for(cells, kEdgeThreads * kEdgeSweeps);
+  hipLaunchKernelGGL(k_edges, dim3(edge_blocks), dim3(kEdgeThreads), 0, st, m->d_occ, m->w, m->h, full,
                      (uint32_t*)nullptr, ctr, 0);
   CDDT_HIP(hipGetLastError());
   BuildCounters hc{};
@@ -495,7 +522,7 @@ cddt_status build_structure(cddt_map_s* m, hipStream_t st) {
   CDDT_TRY(edges_t.get((size_t)n_edges * 4, "edge list"));
   CDDT_HIP(hipMemsetAsync(ctr, 0, sizeof(BuildCounters), st));
   if (n_edges)
-    hipLaunchKernelGGL(k_edges, dim3(grid_for(cells, 256)), dim3(256), 0, st, m->d_occ, m->w, m->h, full,
+    hipLaunchKernelGGL(k_edges, dim3(edge_blocks), dim3(kEdgeThreads), 0, st, m->d_occ, m->w, m->h, full,
                        (uint32_t*)edges_t.p, ctr, 1);
 
   // 2. per-band counts

@@ -65,6 +65,9 @@ struct cddt_map_s {
   int32_t* d_zeros = nullptr;    // band regions
   int64_t capacity = 0, zero_points = 0, edge_cells = 0, max_row_len = 0, rebuilds = 0;
   bool stats_stale = false;  // max_row_len not recomputed since the last update
+  // bumped whenever the band arrays are (re)allocated (build_structure):
+  // device descriptors taken before then hold freed pointers
+  uint64_t generation = 0;
   // spare area at the end of the zero-point array, for bands that outgrow
   // their region during updates: [capacity - spare, capacity); cursor on device
   unsigned long long* d_spare = nullptr;
@@ -154,6 +157,8 @@ struct ResampleSegs {
 cddt_status launch_resample_many(const FilterDev* d_filters, const int64_t* d_pre, const uint32_t* d_u,
                                  float* d_stage, int32_t* d_idx, const ResampleSegs& segs, hipStream_t st);
 cddt_tuning default_tuning();
+// onecall.hip: the autotuned tuning recorded for this filter set, else default_tuning().
+cddt_tuning cached_tuning(const cddt_filter* filters_h, int32_t n_filters);
 // api.hip
 FilterDev filter_dev(const cddt_filter& f);
 cddt_status validate_filter(const cddt_filter& f, const char* who);

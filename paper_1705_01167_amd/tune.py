@@ -60,6 +60,7 @@ def autotune(plan: "cddt.Plan", sig: str, reps: int = 3, use_cache: bool = True,
     if use_cache and sig in cache:
         t = tuple(cache[sig]["tuning"])
         plan.tuning = t
+        _record(plan, t)
         return t, cache[sig]["ms"], []
     results = []
     for t in itertools.product(SPACE_PPT, SPACE_WAVES, SPACE_BLOCKS, SPACE_K):
@@ -77,7 +78,16 @@ def autotune(plan: "cddt.Plan", sig: str, reps: int = 3, use_cache: bool = True,
     confirm.sort()
     best_ms, best = confirm[0]
     plan.tuning = best
+    _record(plan, best)
     cache = _load()
     cache[sig] = {"tuning": list(best), "ms": best_ms}
     _store(cache)
     return best, best_ms, results
+
+
+def _record(plan: "cddt.Plan", tuning) -> None:
+    """Keep the tuning in the library too: plans and one-call launches of the same filter set made
+    without a tuning then use it."""
+    arr = getattr(plan, "_arr", None)
+    if arr is not None:
+        cddt.tuning_cache_put(list(arr), tuning)

@@ -1,9 +1,11 @@
-"""Serving loop: results are the same alone and in the mix, under budget admission."""
+"""Serving loop: results are the same alone and in the mix, under budget admission,
+and every served log-weight equals the oracle's within 1e-5 * max(1, |L|)."""
 import sys
 
 import numpy as np
 import pytest
 
+from oracle import ref as oref
 from paper_1705_01167_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -26,6 +28,20 @@ def _setup(seed=0, sides=(300, 500, 800), bins=(108, 200, 360), M=300, layouts=N
         tabs.append(_dev(wl.beam_table(M, wl.beam_params(rng))))
         occs.append(occ)
     return rng, maps, offs, tabs, occs, M
+
+
+def _check_oracle(reqs, outs, maps, offs, tabs, occs, M, zp16=()):
+    """Every served result against the plain C++ oracle's double log-sum (Sec. VI)."""
+    refs = {}
+    for out, (m, px, py, pth, obs) in zip(outs, reqs):
+        if m not in refs:
+            refs[m] = oref.RefCDDT(occs[m], maps[m].theta_bins, zp16=m in zp16)
+        want = refs[m].weight(px, py, pth, offs[m], obs, tabs[m].cpu().numpy(), M)
+        got = np.asarray(out, np.float64)
+        assert np.isfinite(got).all()
+        assert (np.abs(got - want) <= 1e-5 * np.maximum(1.0, np.abs(want))).all(), f"map {m}"
+    for r in refs.values():
+        r.close()
 
 
 def _requests(rng, occs, M, k):
@@ -61,6 +77,7 @@ def test_alone_equals_mix_equals_plain():
         s, d = srv.times(i)
         assert 0 <= s <= d
     srv.close()
+    _check_oracle(reqs, mixed, maps, offs, tabs, occs, M)
 
 
 def test_mixed_map_layouts_equal_plain():
@@ -79,6 +96,7 @@ def test_mixed_map_layouts_equal_plain():
         plain = maps[m].weight(_dev(px), _dev(py), _dev(pth), _dev(offs[m]), _dev(obs), tabs[m], M)
         assert plain.cpu().numpy().tobytes() == a.tobytes(), f"map {m} ({layouts[m]})"
     srv.close()
+    _check_oracle(reqs, got, maps, offs, tabs, occs, M, zp16=(1,))
 
 
 def test_replay_equals_submit():
@@ -92,8 +110,10 @@ def test_replay_equals_submit():
     ids = srv.replay(reqs, at)
     assert (ids >= 0).all()
     arrive = []
+    replayed = []
     for rid, r in zip(ids.tolist(), ref):
-        assert srv.wait(rid).tobytes() == r.tobytes()
+        replayed.append(srv.wait(rid))
+        assert replayed[-1].tobytes() == r.tobytes()
         s, d = srv.times(rid)
         assert s <= d
         arrive.append(s)
@@ -103,6 +123,7 @@ def test_replay_equals_submit():
         srv.replay(reqs[:2], [1e-3, 0.0])           # decreasing offsets: refused, nothing submitted
     assert srv.stats()["submitted"] == 120
     srv.close()
+    _check_oracle(reqs, replayed, maps, offs, tabs, occs, M)
 
 
 def test_budget_admission_and_reject():
@@ -119,6 +140,7 @@ def test_budget_admission_and_reject():
     for o, (m, px, py, pth, obs) in zip(outs, reqs):
         plain = maps[m].weight(_dev(px), _dev(py), _dev(pth), _dev(offs[m]), _dev(obs), tabs[m], M)
         assert plain.cpu().numpy().tobytes() == o.tobytes()
+    _check_oracle(reqs, outs, maps, offs, tabs, occs, M)
     big = wl.free_poses(rng, occs[0], 20000)
     with pytest.raises(cddt.CddtError) as e:
         srv.submit(0, *big, reqs[0][4])

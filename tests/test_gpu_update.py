@@ -162,28 +162,47 @@ def test_reveal_and_hide_interior():
     assert _same_export(gm.export(), oref.RefCDDT(occ, 200).export())
 
 
+@pytest.mark.timeout(600)
 def test_toggle_workload_4000():
-    """4000^2 floor, 200 bins, 1000 random toggles per step: update == GPU rebuild == oracle rays."""
+    """The updates workload as bench.py runs it: 4000^2 floor, 200 bins, bucket index at 2^7 cells,
+    1000 random toggles per step.  After every step the GPU structure equals the oracle's incrementally
+    updated structure (Sec. IV-D) band for band; 244,000 casts from free poses plus 50,000 from anywhere
+    equal the oracle's; the bucket lines give the same casts and overflow count as a fresh GPU build."""
     import torch
+    from paper_1705_01167_amd import cddt
     _say("toggles 4000: build")
     occ = wl.building_map(wl.rng_for(wl.UPDATES, wl.S_MAP), 4000, 4000)
-    n, M = 200, 500
-    gm = _map(occ, n)
+    n, M, B = 200, 500, 7
+    th = oref.default_threads()
+    gm = _map(occ, n, buckets=B)
+    rm = oref.RefCDDT(occ, n, threads=th)
     cur = occ.copy()
     rng = wl.rng_for(wl.UPDATES, wl.S_OPS)
-    for step in range(3):
+    off = wl.ray_offsets(61)
+    q = wl.rng_for(407, 0)
+    for step in range(5):
         xs, ys, vals = wl.toggle_ops(rng, cur, 1000)
         gm.update(xs, ys, vals)
+        rm.update(xs, ys, vals)
         wl.apply_ops(cur, xs, ys, vals)
-        _say(f"toggles 4000: step {step} rebuild compare")
-        fresh = _map(cur, n)
-        assert _same_export(gm.export(), fresh.export())
+        _say(f"toggles 4000: step {step} structure vs oracle")
+        assert (gm.grid() == cur).all()
+        assert _same_export(gm.export(), rm.export()), f"step {step}: GPU update != oracle update"
+        px, py, pth = wl.free_poses(wl.rng_for(wl.UPDATES, wl.S_POSES, step), cur, 4000)
+        x, y = np.repeat(px, 61), np.repeat(py, 61)
+        t = (np.repeat(pth, 61) + np.tile(off, px.size)).astype(np.float32)
+        xa, ya, ta = _random_queries(q, 4000, 4000, 50000)
+        x, y, t = np.concatenate([x, xa]), np.concatenate([y, ya]), np.concatenate([t, ta])
+        got = gm.cast(_dev(x), _dev(y), _dev(t), M).cpu().numpy()
+        want = rm.cast(x, y, t, M, threads=th)
+        assert (got == want).all(), f"step {step}: {(got != want).sum()} of {got.size} casts differ"
+        # the bucket lines after the targeted refill equal those of a fresh build
+        fresh = cddt.Map(_dev(cur), n, buckets=B)
+        assert gm.info()["bucket_overflow"] == fresh.info()["bucket_overflow"]
+        assert (fresh.cast(_dev(x), _dev(y), _dev(t), M).cpu().numpy() == got).all()
         fresh.close()
         torch.cuda.empty_cache()
-    _say("toggles 4000: oracle brute-force sample")
-    rm = oref.RefCDDT(cur, n, threads=16)
-    px, py, pth = wl.free_poses(wl.rng_for(wl.UPDATES, wl.S_POSES), cur, 4000)
-    got = gm.cast(_dev(px), _dev(py), _dev(pth), M).cpu().numpy()
-    assert (got == rm.cast(px, py, pth, M, threads=16)).all()
+    _say("toggles 4000: brute-force sample")
     sel = slice(0, 400)
-    assert (got[sel] == rm.cast(px[sel], py[sel], pth[sel], M, threads=16, brute=True)).all()
+    got = gm.cast(_dev(x[sel]), _dev(y[sel]), _dev(t[sel]), M).cpu().numpy()
+    assert (got == rm.cast(x[sel], y[sel], t[sel], M, threads=th, brute=True)).all()
