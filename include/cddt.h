@@ -300,6 +300,31 @@ cddt_status cddt_tuning_cache_put(const cddt_filter* filters_h, int32_t n_filter
 cddt_status cddt_tuning_cache_get(const cddt_filter* filters_h, int32_t n_filters, cddt_tuning* tuning_h,
                                   int32_t* found_h);
 
+/* The batched step in one call, without a plan: the sensor-model weights of
+ * every filter (each the cddt_weight of Sec. VI's beam model over Sec. IV-B
+ * casts) in one persistent launch, bit-identical to one cddt_weight per
+ * filter and to a plan over the same filters and tuning.
+ *   filters_h  host array of n_filters (1..65536) descriptors, read during
+ *              the call only.
+ *   tuning_h   nullable: NULL takes the tuning recorded for this filter set
+ *              by cddt_tuning_cache_put (the autotuner's), else the library
+ *              default.
+ * The descriptors reach the device as kernel arguments, so a call enqueues
+ * kernel launches only (one short launch per 20 filters, then the persistent
+ * kernel): no copy, no synchronisation, and no allocation once the stream's
+ * workspace holds n_filters descriptors.  A call can therefore be captured
+ * into a hipGraph; its replays use the descriptors of the capture (update a
+ * map that re-lays its structure, then capture again).
+ * Workspace: library-owned device memory per (device, stream), counters plus
+ * 168 bytes per filter, grown to the next power of two of at least 64
+ * filters by the first call that needs more; growing synchronises the stream
+ * first and is refused (EINVAL) while the stream is capturing.  Calls on one
+ * stream are ordered; calls on different streams have separate workspaces.
+ * A graph captured before the stream's workspace grew must not be replayed.
+ * Errors: EINVAL (filters, tuning, capture), ENOMEM, EDEVICE. */
+cddt_status cddt_batch_weight(const cddt_filter* filters_h, int32_t n_filters, const cddt_tuning* tuning_h,
+                              void* stream);
+
 /* ---------------------------------------------------------------------------
  * The particle-filter steps around the sensor model.  The paper's Monte
  * Carlo localization update moves every particle by the odometry, weighs it

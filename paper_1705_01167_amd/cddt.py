@@ -112,6 +112,7 @@ SIGNATURES = {
     "cddt_plan_destroy": (_i32, [_vp]),
     "cddt_tuning_cache_put": (_i32, [_vp, _i32, C.POINTER(Tuning)]),
     "cddt_tuning_cache_get": (_i32, [_vp, _i32, C.POINTER(Tuning), C.POINTER(_i32)]),
+    "cddt_batch_weight": (_i32, [_vp, _i32, _vp, _vp]),
     "cddt_device_cus": (_i32, []),
     "cddt_probe_gather": (_i32, [_vp, _i64, _i32, _i32, _i32, _u32, _vp, _vp]),
     "cddt_server_create": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, C.POINTER(ServerConfig), C.POINTER(_vp)]),
@@ -432,6 +433,17 @@ def tuning_cache_get(filters):
     found = C.c_int32()
     _check(lib().cddt_tuning_cache_get(C.cast(arr, C.c_void_p), len(filters), C.byref(t), C.byref(found)))
     return t.as_tuple(), bool(found.value)
+
+
+def batch_weight(filters, tuning: tuple | None = None, stream=None) -> None:
+    """All filters' log-weights in one persistent launch (cddt_batch_weight).
+
+    tuning None: the tuning recorded for this filter set (tuning_cache_put), else
+    the library default."""
+    arr = (Filter * len(filters))(*filters)
+    t = Tuning(*tuning) if tuning is not None else None
+    _check(lib().cddt_batch_weight(C.cast(arr, C.c_void_p), len(filters), C.byref(t) if t is not None else None,
+                                   _stream(stream)))
 
 
 def device_cus() -> int:

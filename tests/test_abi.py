@@ -68,6 +68,11 @@ def test_validation_needs_no_gpu():
     assert L.cddt_update(None, None, None, None, 1, None) == cddt.EINVAL
     assert L.cddt_destroy(None) == cddt.OK
     assert L.cddt_plan_create(None, 0, None, None, C.byref(out)) == cddt.EINVAL
+    assert L.cddt_batch_weight(None, 1, None, None) == cddt.EINVAL
+    f = cddt.Filter()   # map NULL: refused before any device call
+    assert L.cddt_batch_weight(C.byref(f), 0, None, None) == cddt.EINVAL
+    assert L.cddt_batch_weight(C.byref(f), 1, None, None) == cddt.EINVAL
+    assert b"map is NULL" in L.cddt_last_error()
 
 
 def test_pair_offset_host_helper():
