@@ -325,6 +325,21 @@ cddt_status cddt_tuning_cache_get(const cddt_filter* filters_h, int32_t n_filter
 cddt_status cddt_batch_weight(const cddt_filter* filters_h, int32_t n_filters, const cddt_tuning* tuning_h,
                               void* stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as cddt_batch_weight, same arguments and bit-identical results, with
+ * its workspace (tile counters, prefix sums, descriptors) in a fixed device
+ * array of the library, about 170 KiB per device, held from the first call
+ * on a device until the process ends.  The call allocates nothing and does
+ * not synchronise.  n_filters at most 1024 (EINVAL beyond).  Every call on a
+ * device shares that array: calls that overlap on one device (different
+ * streams, or graphs replayed concurrently) race and give wrong results;
+ * order them on one stream.  The array keeps the last call's contents; each
+ * call rewrites all it reads (its first kernel clears the counters).
+ * Errors: EINVAL (filters, tuning, more than 1024 filters), EDEVICE. */
+cddt_status cddt_batch_weight_noalloc(const cddt_filter* filters_h, int32_t n_filters,
+                                      const cddt_tuning* tuning_h, void* stream);
+
 /* ---------------------------------------------------------------------------
  * The particle-filter steps around the sensor model.  The paper's Monte
  * Carlo localization update moves every particle by the odometry, weighs it

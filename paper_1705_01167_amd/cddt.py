@@ -113,6 +113,7 @@ SIGNATURES = {
     "cddt_tuning_cache_put": (_i32, [_vp, _i32, C.POINTER(Tuning)]),
     "cddt_tuning_cache_get": (_i32, [_vp, _i32, C.POINTER(Tuning), C.POINTER(_i32)]),
     "cddt_batch_weight": (_i32, [_vp, _i32, _vp, _vp]),
+    "cddt_batch_weight_noalloc": (_i32, [_vp, _i32, _vp, _vp]),
     "cddt_device_cus": (_i32, []),
     "cddt_probe_gather": (_i32, [_vp, _i64, _i32, _i32, _i32, _u32, _vp, _vp]),
     "cddt_server_create": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, C.POINTER(ServerConfig), C.POINTER(_vp)]),
@@ -444,6 +445,15 @@ def batch_weight(filters, tuning: tuple | None = None, stream=None) -> None:
     t = Tuning(*tuning) if tuning is not None else None
     _check(lib().cddt_batch_weight(C.cast(arr, C.c_void_p), len(filters), C.byref(t) if t is not None else None,
                                    _stream(stream)))
+
+
+def batch_weight_noalloc(filters, tuning: tuple | None = None, stream=None) -> None:
+    """batch_weight with the library's fixed device workspace (cddt_batch_weight_noalloc):
+    allocates nothing; at most 1024 filters; calls that overlap on one GPU race."""
+    arr = (Filter * len(filters))(*filters)
+    t = Tuning(*tuning) if tuning is not None else None
+    _check(lib().cddt_batch_weight_noalloc(C.cast(arr, C.c_void_p), len(filters),
+                                           C.byref(t) if t is not None else None, _stream(stream)))
 
 
 def device_cus() -> int:

@@ -132,17 +132,24 @@ void slice_tables(cddt_map_s* m) {
 
 using namespace cddt;
 
+// The message is only built on failure: a valid filter costs no host allocation.
 static cddt_status check_filter(const cddt_filter& f, const char* who) {
-  std::string w(who);
-  if (!f.map) return fail(CDDT_EINVAL, w + ": map is NULL");
-  if (f.n_particles < 0) return fail(CDDT_EINVAL, w + ": n_particles < 0");
-  if (f.n_rays < 1 || f.n_rays > kMaxRays) return fail(CDDT_EINVAL, w + ": n_rays must be in 1..1024");
-  if (f.pair_offset < 0 || f.pair_offset >= f.n_rays) return fail(CDDT_EINVAL, w + ": pair_offset must be in 0..n_rays-1");
-  if (f.max_range < 0 || f.max_range > 65535) return fail(CDDT_EINVAL, w + ": max_range must be in 0..65535");
-  if (!f.ray_offsets || !f.obs_ranges || !f.log_table) return fail(CDDT_EINVAL, w + ": NULL ray/obs/table array");
-  if (f.n_particles > 0 && (!f.px || !f.py || !f.ptheta || !f.logw_out))
-    return fail(CDDT_EINVAL, w + ": NULL particle array");
-  return CDDT_OK;
+  const char* why = nullptr;
+  if (!f.map)
+    why = ": map is NULL";
+  else if (f.n_particles < 0)
+    why = ": n_particles < 0";
+  else if (f.n_rays < 1 || f.n_rays > kMaxRays)
+    why = ": n_rays must be in 1..1024";
+  else if (f.pair_offset < 0 || f.pair_offset >= f.n_rays)
+    why = ": pair_offset must be in 0..n_rays-1";
+  else if (f.max_range < 0 || f.max_range > 65535)
+    why = ": max_range must be in 0..65535";
+  else if (!f.ray_offsets || !f.obs_ranges || !f.log_table)
+    why = ": NULL ray/obs/table array";
+  else if (f.n_particles > 0 && (!f.px || !f.py || !f.ptheta || !f.logw_out))
+    why = ": NULL particle array";
+  return why ? fail(CDDT_EINVAL, std::string(who) + why) : CDDT_OK;
 }
 
 namespace cddt {

@@ -11,6 +11,8 @@
 //
 // The workspace belongs to the (device, stream) pair of the call, so calls
 // on one stream are ordered and calls on different streams do not share it.
+// The variant for callers that cannot allocate takes its workspace from a
+// fixed device array instead (one copy per device, shared by every call).
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -52,7 +54,7 @@ struct Workspace {
   void* mem = nullptr;
   int32_t cap = 0;
 };
-size_t workspace_bytes(int32_t cap) {
+constexpr size_t workspace_bytes(int32_t cap) {
   return kBatchCounterBytes + sizeof(int64_t) * (size_t)(cap + 1 + 1) + sizeof(FilterDev) * (size_t)cap;
 }
 struct Parts {
@@ -72,6 +74,31 @@ Parts carve(void* mem, int32_t cap) {
 
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+// Workspace of cddt_batch_weight_noalloc: at most kNoAllocFilters filters
+// (about 170 KiB), held by every device the library runs on until the
+// process ends.  Host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (g_scratch_ptr).
+constexpr int32_t kNoAllocFilters = 1024;
+constexpr size_t kNoAllocBytes = workspace_bytes(kNoAllocFilters);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on device `dev` (current), taken once.
+cddt_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(CDDT_EDEVICE, "cddt_batch_weight_noalloc: device index out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    CDDT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(CDDT_EDEVICE, "cddt_batch_weight_noalloc: no device address for the workspace");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CDDT_OK;
+}
 
 // Host side of one call: check, take descriptors, upload by kernel
 // arguments into `parts`, launch.  `cus` compute units.
@@ -153,6 +180,22 @@ cddt_status cddt_batch_weight(const cddt_filter* filters_h, int32_t n_filters, c
     ws.cap = cap;
   }
   return enqueue_batch(filters_h, n_filters, t, carve(ws.mem, ws.cap), cus, st);
+}
+
+cddt_status cddt_batch_weight_noalloc(const cddt_filter* filters_h, int32_t n_filters, const cddt_tuning* tuning_h,
+                                      void* stream) {
+  if (n_filters > kNoAllocFilters)
+    return fail(CDDT_EINVAL, "cddt_batch_weight_noalloc: at most 1024 filters (the fixed workspace's size)");
+  cddt_tuning t;
+  CDDT_TRY(check_call(filters_h, n_filters, tuning_h, "cddt_batch_weight_noalloc", &t));
+  int dev = 0;
+  CDDT_HIP(hipGetDevice(&dev));
+  void* ws = nullptr;
+  CDDT_TRY(scratch_address(dev, &ws));
+  const int32_t cus = cddt_device_cus();
+  if (cus <= 0) return fail(CDDT_EDEVICE, "cddt_batch_weight_noalloc: cannot query the device");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return enqueue_batch(filters_h, n_filters, t, carve(ws, kNoAllocFilters), cus, (hipStream_t)stream);
 }
 
 }  // extern "C"
