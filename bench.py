@@ -47,6 +47,12 @@ PRUNE = False  # PCDDT: pruned static maps (exact for grid states only); set by 
 # 21 pairs 4 + one table entry per ray 4.  The same figure is used with the
 # bucket index, which reads no band header.
 BYTES_PER_PARTICLE = 12 + 1 + 4 + SEARCHES * (8 + 4) + (RAYS - SEARCHES) * 4 + RAYS * 4
+# Useful bytes per ray of the fused step, the figure the roofline fraction is
+# taken on: band header 8 + both bracketing zero points 8 + one table entry 4 +
+# the particle's pose 12, occupancy byte 1 and log-weight out 4 shared by its
+# 61 rays (20.28 bytes).  It counts both neighbours of every ray, so it exceeds
+# BYTES_PER_PARTICLE / 61 (13.5), which counts one zero point per search.
+BYTES_PER_RAY_FUSED = 8 + 8 + 4 + (12 + 1 + 4) / RAYS
 # Algorithmic bytes per plain cast: pose 12 + occupancy 1 + header 8 + zero point 4 + range out 4.
 BYTES_PER_CAST = 12 + 1 + 8 + 4 + 4
 
@@ -259,7 +265,7 @@ def run_batched(args) -> dict:
     mcl = None if args.no_mcl else run_mcl_step(args, plan, pose_buf, specs, stream, batched_ms)
 
     value = rays_per_step / (wall / args.steps)
-    algo_bytes = particles * BYTES_PER_PARTICLE
+    algo_bytes = rays_per_step * BYTES_PER_RAY_FUSED
     achieved = algo_bytes / (batched_ms * 1e-3) / 1e9
     traffic = measured_traffic("k_batch", particles)
     probe = cddt.probe_gather() if not args.no_probe else None
@@ -312,8 +318,11 @@ def run_batched(args) -> dict:
             "frac": achieved / PEAK_HBM_GBS,
             "traffic": traffic,
             "kernel": "k_batch",
-            "bytes_per_particle": BYTES_PER_PARTICLE,
+            "bytes_per_ray": BYTES_PER_RAY_FUSED,
+            "bytes_per_launch": algo_bytes,
             "kernel_ms": batched_ms,
+            "frac_at_one_zero_point_per_search": particles * BYTES_PER_PARTICLE / (batched_ms * 1e-3) / 1e9
+            / PEAK_HBM_GBS,
         },
         "mcl_step": mcl,
         "gather_probe": probe,
@@ -420,7 +429,7 @@ def run_floor(args) -> dict:
                        "occupancy": float(occ.mean()), **{k: v for k, v in m.info().items()
                                                           if k in ("zero_points", "rows", "edge_cells")}},
             "roofline": {"bound": "latency (MALL-resident structure)",
-                         "algorithmic_GBps": 2500 * BYTES_PER_PARTICLE / (ms * 1e-3) / 1e9}}
+                         "algorithmic_GBps": 2500 * RAYS * BYTES_PER_RAY_FUSED / (ms * 1e-3) / 1e9}}
 
 
 def run_updates(args) -> dict:

@@ -19,6 +19,9 @@ def test_algorithmic_bytes():
     assert bench.BYTES_PER_PARTICLE == 12 + 1 + 4 + 40 * 12 + 21 * 4 + 61 * 4 == 825
     assert bench.BYTES_PER_CAST == 29
     assert bench.SEARCHES == 40 and bench.RAYS == 61
+    # useful bytes per fused ray: header 8 + both bracketing zero points 8 + table entry 4
+    # + (pose 12 + occupancy 1 + log-weight 4) / 61
+    assert abs(bench.BYTES_PER_RAY_FUSED - 20.2787) < 1e-4
 
 
 def test_stored_traffic_needs_same_source_particles_and_layout(monkeypatch):
