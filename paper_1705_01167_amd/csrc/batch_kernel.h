@@ -14,7 +14,8 @@ namespace {
 // bytes apart: blocks are dispatched to the 8 XCDs in turn, so block b starts
 // on part b % 8, and the device-scope increments of one launch spread over
 // eight addresses instead of queueing on one.  A wave whose part is used up
-// moves on to the next part; it leaves after finding all of them used up.
+// reads all eight counters at once and moves on to the next part that still
+// has tiles; it leaves when none has.
 constexpr int kTileParts = 8;
 constexpr int kCounterStride = 32;  // 64-bit words between counters
 static_assert(kTileParts * kCounterStride * sizeof(unsigned long long) == kBatchCounterBytes, "counter block size");
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(kMaxBatchThreads) void k_batch(const FilterDev* __r
   int2* jobs = smem_jobs + wave * Q * kWave;
   int32_t* codes = reinterpret_cast<int32_t*>(smem_jobs + nw * Q * kWave) + wave * Q * kWave;
   int32_t* later = reinterpret_cast<int32_t*>(smem_jobs + nw * Q * kWave) + (nw + wave) * Q * kWave;
-  int part = (int)(blockIdx.x % kTileParts), exhausted = 0;
+  int part = (int)(blockIdx.x % kTileParts);
   // Tickets: lane 0 claims the next ticket of its part while the current tile
   // runs, so the atomic's round trip overlaps the tile's own loads.  Every
   // claimed ticket is used: in range it is the next tile, out of range it
@@ -84,8 +85,23 @@ __global__ __launch_bounds__(kMaxBatchThreads) void k_batch(const FilterDev* __r
     const uint64_t part_hi = (uint64_t)total_tiles * (part + 1) / kTileParts;
     const uint64_t t = uniform_u64(ticket) + part_lo;  // lane 0's ticket (the first active lane)
     if (t >= part_hi) {
-      if (++exhausted == kTileParts) break;
-      part = (part + 1) % kTileParts;
+      // This part is used up.  Read every part's counter at once (lane k reads
+      // part k) and move to the next part in turn that still has tiles; leave
+      // when none has.  Counters only grow, so a part seen used up stays used
+      // up, and every tile is still handed out by exactly one claim.
+      bool left = false;
+      if (lane < kTileParts) {
+        const uint64_t lo = (uint64_t)total_tiles * lane / kTileParts;
+        const uint64_t hi = (uint64_t)total_tiles * (lane + 1) / kTileParts;
+        const unsigned long long c =
+            __hip_atomic_load(counter + lane * kCounterStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        left = c < hi - lo;
+      }
+      const uint32_t have = (uint32_t)__ballot(left) & ((1u << kTileParts) - 1u);
+      if (have == 0) break;
+      // the first part with tiles at or after part + 1, cyclically
+      const uint32_t rot = ((have >> (part + 1)) | (have << (kTileParts - part - 1))) & ((1u << kTileParts) - 1u);
+      part = (part + 1 + __builtin_ctz(rot)) % kTileParts;
       ticket = claim(part);
       continue;
     }

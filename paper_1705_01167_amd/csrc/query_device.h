@@ -622,18 +622,25 @@ __device__ __forceinline__ void lane_search2(const MapDev& m, bool wa, int32_t r
 __device__ __forceinline__ bool quad_half_round(const MapDev& m, const int2* jobs, int32_t b, int32_t njobs,
                                                 int32_t max_range, int32_t& jo, int32_t& rs, int32_t& rp) {
   const int lane = threadIdx.x & (kWave - 1), sub = lane & 3, quad = lane >> 2;
+  // Slots b .. b + 63 all lie inside the wave's queue (b < njobs <= the
+  // queue's size, a multiple of 64), so the four job reads need no condition;
+  // slots at or past njobs read stale entries, which load band 0's first line
+  // instead (a valid address) and whose results are dropped.
+  int2 jb[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) jb[k] = jobs[b + 16 * k + quad];
+  const int4* lines = reinterpret_cast<const int4*>(m.bk) + sub;
   int4 v[4];
   int32_t xs[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int32_t j = b + 16 * k + quad;
-    const int2 jb = j < njobs ? jobs[j] : make_int2(0, 0);
-    xs[k] = jb.y;
-    v[k] = make_int4(INT_MAX, INT_MAX, INT_MAX, INT_MAX);
-    if (j < njobs)
-      v[k] = ldg4(reinterpret_cast<const int4*>(m.bk + ((int64_t)jb.x * m.nbk + bucket_of(m, jb.y)) * kLineInts) +
-                  sub);
+    const bool ok = b + 16 * k + quad < njobs;
+    const int32_t row = ok ? jb[k].x : 0, x = ok ? jb[k].y : 0;
+    xs[k] = x;
+    const int32_t bkt = min(max(x >> m.bshift, 0), m.nbk - 1);
+    v[k] = ldg4(lines + ((int64_t)row * m.nbk + bkt) * (kLineInts / 4));
   }
+  const bool first = sub == 0, last = sub == 3;
   uint32_t dn[4], dp[4];
   int32_t bad[4];
 #pragma unroll
@@ -641,7 +648,7 @@ __device__ __forceinline__ bool quad_half_round(const MapDev& m, const int2* job
     const int32_t x = xs[k], xm = x - 1;
     uint32_t a = min(min(above_gap(v[k].x, x), above_gap(v[k].y, x)), min(above_gap(v[k].z, x), above_gap(v[k].w, x)));
     uint32_t c = min(min(below_gap(v[k].x, xm), below_gap(v[k].y, xm)), min(below_gap(v[k].z, xm), below_gap(v[k].w, xm)));
-    int32_t f = (sub == 0 && v[k].x == kBucketOverflow) || (sub == 3 && !(x < v[k].w)) ? 1 : 0;
+    int32_t f = (int32_t)((first & (v[k].x == kBucketOverflow)) | (last & (x >= v[k].w)));
     a = min(a, (uint32_t)dpp<kDppQuadXor1>((int32_t)a));
     c = min(c, (uint32_t)dpp<kDppQuadXor1>((int32_t)c));
     f = max(f, dpp<kDppQuadXor1>(f));
@@ -652,10 +659,11 @@ __device__ __forceinline__ bool quad_half_round(const MapDev& m, const int2* job
     dp[k] = c;
     bad[k] = f;
   }
-  const uint32_t d1 = sub == 0 ? dn[0] : sub == 1 ? dn[1] : sub == 2 ? dn[2] : dn[3];
-  const uint32_t d2 = sub == 0 ? dp[0] : sub == 1 ? dp[1] : sub == 2 ? dp[2] : dp[3];
-  const int32_t f = sub == 0 ? bad[0] : sub == 1 ? bad[1] : sub == 2 ? bad[2] : bad[3];
-  const int32_t x = sub == 0 ? xs[0] : sub == 1 ? xs[1] : sub == 2 ? xs[2] : xs[3];
+  const bool s1 = sub == 1, s2 = sub == 2;
+  const uint32_t d1 = first ? dn[0] : s1 ? dn[1] : s2 ? dn[2] : dn[3];
+  const uint32_t d2 = first ? dp[0] : s1 ? dp[1] : s2 ? dp[2] : dp[3];
+  const int32_t f = first ? bad[0] : s1 ? bad[1] : s2 ? bad[2] : bad[3];
+  const int32_t x = first ? xs[0] : s1 ? xs[1] : s2 ? xs[2] : xs[3];
   jo = b + 16 * sub + quad;
   const int32_t xm = x - 1;
   const int32_t nxt = has_above(d1, x) ? (int32_t)((uint32_t)x + 1u + d1) : INT_MAX;
@@ -855,13 +863,9 @@ __device__ __forceinline__ void drain_jobs(const MapDev& m, int2* jobs, int32_t*
   const int lane = threadIdx.x & (kWave - 1);
   const bool halves = m.bk != nullptr;  // the same for the whole wave
   int32_t nlater = 0;
-  for (int32_t b = 0; b < njobs; b += kWave) {
-    const int32_t j = b + lane;
-    const bool w = j < njobs;
-    const int2 jb = w ? jobs[j] : make_int2(0, 0);
-    int32_t rs, rp;
-    if (halves) {
-      int32_t jo;
+  if (halves) {
+    for (int32_t b = 0; b < njobs; b += kWave) {
+      int32_t jo, rs, rp;
       bool wo;  // this lane's job jo and its result
       if (Z && m.zp16)
         wo = quad_half_round16(m, jobs, b, njobs, M, jo, rs, rp);
@@ -873,7 +877,13 @@ __device__ __forceinline__ void drain_jobs(const MapDev& m, int2* jobs, int32_t*
       if (defer) later[nlater + __popcll(dm & ((1ull << lane) - 1ull))] = jo;
       nlater += __popcll(dm);
       if (done) jobs[jo].x = rs | (rp << 16);
-    } else {
+    }
+  } else {
+    for (int32_t b = 0; b < njobs; b += kWave) {
+      const int32_t j = b + lane;
+      const bool w = j < njobs;
+      const int2 jb = w ? jobs[j] : make_int2(0, 0);
+      int32_t rs, rp;
       lane_search<Z>(m, w, jb.x, jb.y, M, rs, rp);
       if (w) jobs[j].x = rs | (rp << 16);
     }
