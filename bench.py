@@ -337,7 +337,7 @@ def run_batched(args) -> dict:
     torch.cuda.empty_cache()
     if not args.no_serving:
         log("bench: serving summary")
-        out["serving"] = run_serving(args, summary=True)
+        out["serving"] = run_serving(args, ref_rays_per_s=rays_per_step / (batched_ms * 1e-3))
     if not args.no_cpu:
         log("bench: timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(specs, host, off_h, args.cpu_budget)
@@ -493,8 +493,10 @@ def run_updates(args) -> dict:
 # Serving
 # ---------------------------------------------------------------------------
 SERVE_SIDES = (1000, 1500, 2000, 2500, 3000, 3500, 4000, 4000)
-SERVE_RATES = (10000, 25000, 50000, 100000, 200000, 300000, 400000, 500000, 600000)   # offered requests/s
-SERVE_RATES_SUMMARY = (50000, 200000)
+# offered load as fractions of the batched capacity (the many-filter step's rays/s, or a plan over one
+# request per robot on the serving maps), converted to requests/s with the requests' mean ray count
+SERVE_FRACTIONS = (0.10, 0.25, 0.40, 0.55, 0.70, 0.85, 1.00, 1.20)
+SERVE_TIGHT_BUDGET = 2 << 20  # bytes: lanes share it, so each batch holds a few dozen requests at most
 
 
 def build_serving(buckets):
@@ -553,36 +555,74 @@ def serve_at(srv, reqs, rate: float | None, seed: int):
             "requests": k}
 
 
-def run_serving(args, summary: bool = False) -> dict:
+def serving_plan_capacity(maps, offs, tabs, pools, obs) -> float:
+    """Batched capacity on the serving maps: rays/s of one persistent launch over one request per robot."""
+    import torch
+    from paper_1705_01167_amd import cddt
+    reqs = make_requests(256, 7, pools, obs)
+    off = [t_dev(o) for o in offs]
+    keep, filters = [], []
+    for m, px, py, pth, ob, n in reqs:
+        d = {"px": t_dev(px), "py": t_dev(py), "pth": t_dev(pth), "obs": t_dev(ob)}
+        lw = torch.empty(n, dtype=torch.float32, device="cuda")
+        filters.append(cddt.make_filter(maps[m], d["px"], d["py"], d["pth"], off[m], d["obs"], tabs[m], MAX_RANGE,
+                                        lw))
+        keep.append((d, lw))
+    st = torch.cuda.Stream()
+    plan = cddt.Plan(filters, stream=st, keepalive=(keep, off))
+    plan.time(plan.tuning, reps=3, stream=st)
+    ms = min(plan.time(plan.tuning, reps=20, stream=st) for _ in range(3))
+    plan.close()
+    return sum(r[5] for r in reqs) * RAYS / (ms * 1e-3)
+
+
+def run_serving(args, ref_rays_per_s: float | None = None, lanes: int | None = None) -> dict:
+    """Open-loop Poisson arrivals at SERVE_FRACTIONS of the batched capacity, args.serve_requests each."""
     from paper_1705_01167_amd import cddt
     # the serving maps have no bucket index unless one is asked for explicitly
     buckets = None if args.buckets.lower() == "auto" else BUCKETS
+    lanes = lanes or int(str(args.serve_lanes).split(",")[0])
     maps, offs, tabs, pools, obs = build_serving(buckets)
+    ref_kind = "the many-filter step's kernel rays/s in this run"
+    if ref_rays_per_s is None:
+        ref_rays_per_s = serving_plan_capacity(maps, offs, tabs, pools, obs)
+        ref_kind = "one persistent launch over one request per robot on the serving maps"
     srv = cddt.Server(maps, offs, tabs, [MAX_RANGE] * len(maps), budget_bytes=args.serve_budget,
-                      n_lanes=args.serve_lanes, max_batch=args.serve_batch)
+                      n_lanes=lanes, max_batch=args.serve_batch)
     warm = make_requests(500, 0, pools, obs)
     serve_at(srv, warm, None, 0)
     # burst capacity: median of three bursts (every request arrives at once, so batches are as large as the
-    # lanes allow); latency is then measured at fixed offered rates, which stay comparable between runs
+    # lanes allow)
     caps = sorted((serve_at(srv, make_requests(args.serve_requests, 1 + b, pools, obs), None, 1 + b)
                    for b in range(3)), key=lambda c: c["completed_rps"])
     cap = caps[1]
-    capacity = cap["completed_rps"]
-    rates = SERVE_RATES_SUMMARY if summary else SERVE_RATES
     points = []
-    for j, rate in enumerate(rates):
+    for j, frac in enumerate(SERVE_FRACTIONS):
         reqs = make_requests(args.serve_requests, 10 + j, pools, obs)
-        points.append(serve_at(srv, reqs, float(rate), 10 + j))
-        log(f"bench: serving at {rate} requests/s: {points[-1]}")
+        mean_rays = sum(r[5] for r in reqs) * RAYS / len(reqs)
+        rate = frac * ref_rays_per_s / mean_rays
+        points.append({"fraction_of_batched_capacity": frac, **serve_at(srv, reqs, float(rate), 10 + j)})
+        log(f"bench: serving ({lanes} lanes) at {frac:.0%} of batched capacity: {points[-1]}")
     st = srv.stats()
     srv.close()
-    res = {"burst_capacity_rps": capacity, "burst_capacity_rays_per_s": cap["rays_per_s"], "points": points,
-           "stats": st, "config": {"maps": list(SERVE_SIDES), "theta_bins": [m.theta_bins for m in maps],
-                                   "robots": 256, "request_particles": "log-uniform 17..1639",
-                                   "bucket_log2": buckets,
-                                   "budget_bytes": args.serve_budget, "lanes": args.serve_lanes,
-                                   "max_batch": args.serve_batch}}
-    return res
+    # admission limited by memory: a budget of SERVE_TIGHT_BUDGET bytes (a few dozen requests in flight)
+    # under the offered load of the 85% point
+    tight = cddt.Server(maps, offs, tabs, [MAX_RANGE] * len(maps), budget_bytes=SERVE_TIGHT_BUDGET,
+                        n_lanes=lanes, max_batch=args.serve_batch)
+    serve_at(tight, warm, None, 0)
+    reqs = make_requests(args.serve_requests, 30, pools, obs)
+    rate = 0.85 * ref_rays_per_s / (sum(r[5] for r in reqs) * RAYS / len(reqs))
+    budget_point = {"budget_bytes": SERVE_TIGHT_BUDGET, **serve_at(tight, reqs, float(rate), 30),
+                    "stats": tight.stats()}
+    tight.close()
+    log(f"bench: serving with a {SERVE_TIGHT_BUDGET >> 20} MiB budget: {budget_point}")
+    return {"batched_capacity_rays_per_s": ref_rays_per_s, "batched_capacity_from": ref_kind,
+            "burst_capacity_rps": cap["completed_rps"], "burst_capacity_rays_per_s": cap["rays_per_s"],
+            "points": points, "stats": st, "budget_limited": budget_point,
+            "config": {"maps": list(SERVE_SIDES), "theta_bins": [m.theta_bins for m in maps], "robots": 256,
+                       "request_particles": "log-uniform 17..1639", "bucket_log2": buckets,
+                       "budget_bytes": args.serve_budget, "lanes": lanes, "max_batch": args.serve_batch,
+                       "requests_per_rate": args.serve_requests}}
 
 
 def copy_calibration(mib: int) -> None:
@@ -624,17 +664,15 @@ def main():
     ap.add_argument("--tuning", type=str, default=None,
                     help="fixed persistent-kernel tuning 'ppt,waves,blocks,K' (skips the autotuner)")
     ap.add_argument("--no-graph", action="store_true", help="launch the plan directly instead of a graph")
-    ap.add_argument("--serve-requests", type=int, default=0,
-                    help="requests per offered rate (default 20000 for the serving workload, 3000 in the summary)")
+    ap.add_argument("--serve-requests", type=int, default=20000, help="requests per offered rate")
     ap.add_argument("--serve-budget", type=int, default=256 << 20)
-    ap.add_argument("--serve-lanes", type=int, default=1)
+    ap.add_argument("--serve-lanes", type=str, default="4",
+                    help="batches in flight (streams, 1..4); the serving workload takes a comma-separated list")
     ap.add_argument("--serve-batch", type=int, default=512)
     ap.add_argument("--probe-gib", type=str, default="4", help="probe buffer sizes in GiB, comma separated")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
-    if not args.serve_requests:
-        args.serve_requests = 20000 if args.workload == "serving" else 3000
     global BUCKETS
     if args.buckets.lower() == "auto":
         BUCKETS = {"batched": 6, "floor": 7, "updates": 7}.get(args.workload)
@@ -665,7 +703,8 @@ def main():
     elif args.workload == "updates":
         out = run_updates(args)
     elif args.workload == "serving":
-        out = {"metric": "serving: completed rays/s and p50/p99 latency vs offered load", **run_serving(args)}
+        out = {"metric": "serving: completed rays/s and p50/p99 latency vs offered load",
+               "runs": [run_serving(args, lanes=int(v)) for v in args.serve_lanes.split(",")]}
     else:
         out = {"gather_probe": [cddt.probe_gather(gib=float(g), depth=d) for g in args.probe_gib.split(",")
                                 for d in (1, 4)]}

@@ -422,8 +422,9 @@ typedef struct cddt_server_s* cddt_server;
 
 typedef struct {
   int64_t budget_bytes;     /* device staging budget for request inputs/outputs */
-  int32_t n_lanes;          /* batches in flight (streams), 1..8; 1 gave the lowest latency
-                               measured, since one persistent launch already fills the device */
+  int32_t n_lanes;          /* batches in flight (streams), 1..4 (HIP's hardware queues per
+                               process); a lane's batch writes its results straight into
+                               pinned host memory, so it uses no copy engine */
   int32_t max_batch;        /* requests per batch, 1..4096 */
   int32_t max_rays;         /* rays per request, 1..1024 */
   int32_t reserved;
@@ -436,7 +437,7 @@ typedef struct {
   int64_t rays;
   int64_t peak_bytes;       /* highest staging bytes in use */
   double busy_seconds;      /* wall time with at least one batch in flight */
-  double device_seconds;    /* sum over batches of device time, input copy start to output copy end */
+  double device_seconds;    /* sum over batches of device time, input copy start to batch kernel end */
   double max_batch_seconds; /* the slowest batch's device time */
 } cddt_server_stats;
 

@@ -6,13 +6,15 @@
 // staging.  Whenever a lane is idle, the scheduler admits queued requests in
 // arrival order while the lane's arena and batch size allow, packs their
 // inputs and filter descriptors into the staging buffer, and issues a staging
-// kernel that pulls them into the arena, one persistent batched launch (the
-// same kernel as cddt_plan_run) and one download on the lane's stream,
-// followed by an event.  Up to n_lanes
+// kernel that pulls them into the arena and one persistent batched launch
+// (the same kernel as cddt_plan_run), which writes the log-weights straight
+// into the lane's pinned output buffer, followed by an event: a batch uses no
+// copy engine, only its lane's kernel queue.  Up to n_lanes
 // batches are in flight at once, so requests that arrive while others run are
 // admitted as lanes and memory free up and their work overlaps on the device.
 // A batch's requests complete when its event has fired: their log-weights are
-// copied out and their completion time is stamped on the host clock.
+// taken from the pinned buffer and their completion time is stamped on the
+// host clock.
 //
 // Results are bit-identical to running each request alone: every particle's
 // weight is computed by the same per-particle routine, in a fixed order.
@@ -63,6 +65,9 @@ constexpr size_t kTimesRing = 1 << 16;
 constexpr double kSpinSeconds = 200e-6;  // idle polling before the scheduler blocks
 
 constexpr size_t kAlign = 256;
+// Lanes are streams, and HIP maps a process's streams onto four hardware
+// queues by default: more lanes would share queues (and wait on each other).
+constexpr int32_t kMaxLanes = 4;
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 // Copy a lane's packed inputs from pinned host memory into its device arena.
@@ -74,11 +79,12 @@ __global__ void k_stage_in(const uint4* __restrict__ src, uint4* __restrict__ ds
 struct Lane {
   hipStream_t stream = nullptr;
   hipEvent_t start = nullptr;  // before the input copy
-  hipEvent_t done = nullptr;   // after the output copy
-  char* d_arena = nullptr;   // device: [descriptors][prefix][counter][inputs...][outputs...]
+  hipEvent_t done = nullptr;   // after the batch kernel
+  char* d_arena = nullptr;   // device: [descriptors][prefix][counter][inputs...]
   char* h_in = nullptr;      // pinned staging of the same layout (inputs part)
   const char* h_in_dev = nullptr;  // h_in as the device addresses it
-  float* h_out = nullptr;    // pinned log-weights
+  float* h_out = nullptr;    // pinned log-weights, written by the batch kernel
+  float* h_out_dev = nullptr;  // h_out as the device addresses it
   size_t arena = 0;
   std::vector<Request*> batch;
   std::vector<size_t> out_off;  // per request: float offset of its log-weights in h_out
@@ -170,7 +176,7 @@ cddt_status launch_lane(const cddt_server_s* s, Lane& L) {
     prefix[k + 1] = prefix[k] + ((int64_t)n + ppt - 1) / ppt;
   }
   const size_t in_bytes = off;
-  for (size_t k = 0; k < nb; ++k) fd[k].logw = (float*)(L.d_arena + in_bytes) + L.out_off[k];
+  for (size_t k = 0; k < nb; ++k) fd[k].logw = L.h_out_dev + L.out_off[k];
   L.out_floats = out_floats;
   CDDT_HIP(hipEventRecord(L.start, L.stream));
   // the inputs are pulled from pinned memory by a kernel, so that all of a
@@ -182,7 +188,6 @@ cddt_status launch_lane(const cddt_server_s* s, Lane& L) {
   CDDT_TRY(launch_batch((const FilterDev*)L.d_arena, (const int64_t*)(L.d_arena + desc_bytes), (int32_t)nb,
                         prefix[nb], s->cfg.tuning, (unsigned long long*)(L.d_arena + counter_off), s->cus,
                         L.stream, s->zp16, /*counter_zeroed=*/true));
-  CDDT_HIP(hipMemcpyAsync(L.h_out, L.d_arena + in_bytes, out_floats * 4, hipMemcpyDeviceToHost, L.stream));
   CDDT_HIP(hipEventRecord(L.done, L.stream));
   return CDDT_OK;
 }
@@ -367,7 +372,8 @@ cddt_status cddt_server_create(const cddt_map* maps_h, int32_t n_maps, const flo
   if (!maps_h || !offsets_h || !n_rays_h || !log_tables || !max_range_h || !config_h || n_maps < 1)
     return fail(CDDT_EINVAL, "cddt_server_create: NULL argument or no maps");
   const cddt_server_config& c = *config_h;
-  if (c.n_lanes < 1 || c.n_lanes > 8) return fail(CDDT_EINVAL, "cddt_server_create: n_lanes must be in 1..8");
+  if (c.n_lanes < 1 || c.n_lanes > kMaxLanes)
+    return fail(CDDT_EINVAL, "cddt_server_create: n_lanes must be in 1..4");
   if (c.max_batch < 1 || c.max_batch > 4096) return fail(CDDT_EINVAL, "cddt_server_create: max_batch in 1..4096");
   if (c.max_rays < 1 || c.max_rays > kMaxRays) return fail(CDDT_EINVAL, "cddt_server_create: max_rays in 1..1024");
   if (c.budget_bytes < (int64_t)c.n_lanes * 4096) return fail(CDDT_EINVAL, "cddt_server_create: budget too small");
@@ -411,7 +417,8 @@ cddt_status cddt_server_create(const cddt_map* maps_h, int32_t n_maps, const flo
         hipMalloc(&L.d_arena, fixed + arena) != hipSuccess ||
         hipHostMalloc((void**)&L.h_in, fixed + arena, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&L.h_out, arena, hipHostMallocDefault) != hipSuccess ||
-        hipHostGetDevicePointer((void**)&L.h_in_dev, L.h_in, 0) != hipSuccess)
+        hipHostGetDevicePointer((void**)&L.h_in_dev, L.h_in, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&L.h_out_dev, L.h_out, 0) != hipSuccess)
       return bail("cddt_server_create: lane allocation failed");
   }
   s->sched = std::thread(scheduler, s);

@@ -68,6 +68,14 @@ def test_validation_needs_no_gpu():
     assert L.cddt_update(None, None, None, None, 1, None) == cddt.EINVAL
     assert L.cddt_destroy(None) == cddt.OK
     assert L.cddt_plan_create(None, 0, None, None, C.byref(out)) == cddt.EINVAL
+    # servers: at most 4 lanes (refused before any map is touched)
+    cfg = cddt.ServerConfig(1 << 20, 5, 8, 61, 0, cddt.Tuning(8, 2, 8, 7))
+    fake = (C.c_void_p * 1)(1)
+    offs = (C.c_void_p * 1)(1)
+    nr = (C.c_int32 * 1)(61)
+    mr = (C.c_int32 * 1)(500)
+    assert L.cddt_server_create(fake, 1, offs, nr, offs, mr, C.byref(cfg), C.byref(out)) == cddt.EINVAL
+    assert b"1..4" in L.cddt_last_error()
     assert L.cddt_batch_weight(None, 1, None, None) == cddt.EINVAL
     f = cddt.Filter()   # map NULL: refused before any device call
     assert L.cddt_batch_weight(C.byref(f), 0, None, None) == cddt.EINVAL
