@@ -410,13 +410,27 @@ cddt_status cddt_probe_gather(const void* buf, int64_t bytes, int32_t blocks, in
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching over resident maps.
  * A server keeps maps resident and accepts requests (one robot's particles
- * and one scan) from host threads.  A scheduler thread admits queued requests
- * whenever a batch slot and enough of the staging budget are free, packs
- * every admitted request into one persistent batched launch on one of
- * `n_lanes` streams, and keeps up to n_lanes batches in flight, so requests
- * that arrive while others run are admitted as slots and memory free up and
- * their work overlaps on the device.  Results are bit-identical to running
- * the request alone.
+ * and one scan) from host threads, in one of two modes.  Results are
+ * bit-identical to running each request alone in either.
+ *
+ * Lanes (resident = 0): a scheduler thread admits queued requests whenever a
+ * batch slot and enough of the staging budget are free, packs every admitted
+ * request into one persistent batched launch on one of `n_lanes` streams, and
+ * keeps up to n_lanes batches in flight, so requests that arrive while others
+ * run are admitted as slots and memory free up and their work overlaps on the
+ * device.
+ *
+ * Resident (resident = 1): one persistent kernel stays on the device while
+ * there is work and admits requests as they are published.  A request takes
+ * one of `max_batch` ring slots (each budget_bytes / max_batch bytes of
+ * pinned, device-mapped host memory for its inputs and log-weights; a request
+ * that does not fit is refused with EBUSY, one that finds no free slot waits),
+ * is written there by the submitting thread and published at once; the
+ * kernel's waves take its tiles as they come, among every other request's,
+ * and the last tile writes the request's completion word back to host memory.
+ * No launch or copy happens per request.  The kernel leaves about a
+ * millisecond after the last request finished and is launched again by the
+ * next one.  Takes search modes 0, 6, 7 and 8; n_lanes must be 1.
  * ------------------------------------------------------------------------- */
 typedef struct cddt_server_s* cddt_server;
 
@@ -425,15 +439,15 @@ typedef struct {
   int32_t n_lanes;          /* batches in flight (streams), 1..4 (HIP's hardware queues per
                                process); a lane's batch writes its results straight into
                                pinned host memory, so it uses no copy engine */
-  int32_t max_batch;        /* requests per batch, 1..4096 */
+  int32_t max_batch;        /* requests per batch, 1..4096 (resident: ring slots, 1..65536) */
   int32_t max_rays;         /* rays per request, 1..1024 */
-  int32_t reserved;
+  int32_t resident;         /* 0: lanes of batches; 1: one resident kernel fed through a ring */
   cddt_tuning tuning;       /* persistent-kernel tuning for server batches */
 } cddt_server_config;
 
 typedef struct {
   int64_t submitted, completed, rejected;
-  int64_t batches;
+  int64_t batches;          /* batches launched (resident: kernel launches) */
   int64_t rays;
   int64_t peak_bytes;       /* highest staging bytes in use */
   double busy_seconds;      /* wall time with at least one batch in flight */

@@ -65,7 +65,7 @@ class Tuning(C.Structure):
 
 class ServerConfig(C.Structure):
     _fields_ = [("budget_bytes", C.c_int64), ("n_lanes", C.c_int32), ("max_batch", C.c_int32),
-                ("max_rays", C.c_int32), ("reserved", C.c_int32), ("tuning", Tuning)]
+                ("max_rays", C.c_int32), ("resident", C.c_int32), ("tuning", Tuning)]
 
 
 class ServerStats(C.Structure):
@@ -489,14 +489,15 @@ class Server:
     """Continuous-batching server over resident maps (cddt_server_*)."""
 
     def __init__(self, maps, offsets, tables, max_ranges, budget_bytes: int = 1 << 30, n_lanes: int = 1,
-                 max_batch: int = 256, tuning=(8, 4, 2, 7)):
+                 max_batch: int = 256, tuning=(8, 4, 2, 7), resident: bool = False):
+        """resident: one persistent kernel fed through a ring of max_batch slots (n_lanes must be 1)."""
         n = len(maps)
         self._offsets = [np.ascontiguousarray(np.asarray(o, np.float32)) for o in offsets]
         self._tables = list(tables)              # keep device tables alive
         self._maps = list(maps)
         self._n_rays = [o.size for o in self._offsets]
-        cfg = ServerConfig(int(budget_bytes), int(n_lanes), int(max_batch), int(max(self._n_rays)), 0,
-                           Tuning(*tuning))
+        cfg = ServerConfig(int(budget_bytes), int(n_lanes), int(max_batch), int(max(self._n_rays)),
+                           1 if resident else 0, Tuning(*tuning))
         handles = (C.c_void_p * n)(*[m.handle.value for m in maps])
         offp = (C.c_void_p * n)(*[o.ctypes.data for o in self._offsets])
         nr = (C.c_int32 * n)(*self._n_rays)

@@ -46,6 +46,26 @@ __device__ __forceinline__ int4 ldg4(const int4* p) {
   return make_int4(v.x, v.y, v.z, v.w);
 }
 
+// Loads and stores of a request's own inputs and outputs.  With Sys they are
+// system-coherent (relaxed atomics at system scope): they bypass the L2, so
+// data that the host rewrites while a kernel runs (a resident server's slots
+// in pinned host memory) is read fresh, and results reach host memory when
+// the store is acknowledged.
+template <bool Sys, typename T>
+__device__ __forceinline__ T ldx(const T* p) {
+  if constexpr (Sys)
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  else
+    return ldg(p);
+}
+template <bool Sys, typename T>
+__device__ __forceinline__ void stx(T* p, T v) {
+  if constexpr (Sys)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  else
+    stg(p, v);
+}
+
 // Quantised query position: floor(v * 2^16); v * 2^16 is exact in float32.
 __device__ __forceinline__ int32_t quantize16(float v) {
   return (int32_t)floorf(__fmul_rn(v, 65536.0f));
@@ -794,7 +814,8 @@ __device__ __forceinline__ int32_t wave_cast(const MapDev& m, bool active, float
 // Radial pairing (Sec. IV-C): if pair_off > 0, lane l + pair_off reuses the
 // search of lane l when both rays land in the same slice (their bins differ by
 // n/2): every search returns both the successor and the predecessor.
-template <int K, bool Z>
+// Sys: observations are read system-coherently (ldx).
+template <int K, bool Z, bool Sys = false>
 __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, float py, float pth,
                                                     const float* __restrict__ offsets,
                                                     const int32_t* __restrict__ obs, int32_t n_rays,
@@ -842,7 +863,7 @@ __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, f
     int32_t range = 0;
     if (valid) range = paired ? (fwd ? (opk & 0xffff) : (int32_t)((uint32_t)opk >> 16)) : (fwd ? rs : rp);
     if (active) {
-      int32_t zo = ldg(obs + r);
+      int32_t zo = ldx<Sys>(obs + r);
       zo = zo < 0 ? 0 : (zo > max_range ? max_range : zo);
       acc += ldg(table + (int64_t)zo * m1 + range);
       if (ranges_row) stg(ranges_row + r, range);
@@ -971,7 +992,9 @@ __device__ __forceinline__ void wave_cast_tile(const MapDev& m, const float* __r
 // runs two searches of a round side by side (128 searches per round).
 // Otherwise the queue is drained by drain_jobs (half-line first pass on maps
 // with a bucket index, deferred full searches).
-template <int Q, int Lanes2, bool Z>
+// Sys: poses and observations are read, and log-weights written,
+// system-coherently (ldx / stx).
+template <int Q, int Lanes2, bool Z, bool Sys = false>
 __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, int32_t cnt, int2* jobs,
                                                int32_t* codes, int32_t* later) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -981,8 +1004,8 @@ __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, i
   float qt = 0.0f;
   int32_t qxf = 0, qyf = 0, qok = 0;
   if (lane < cnt) {
-    const float x = ldg(f.px + p0 + lane), y = ldg(f.py + p0 + lane);
-    qt = ldg(f.pth + p0 + lane);
+    const float x = ldx<Sys>(f.px + p0 + lane), y = ldx<Sys>(f.py + p0 + lane);
+    qt = ldx<Sys>(f.pth + p0 + lane);
     if (pose_inside(m, x, y)) {
       qxf = quantize16(x);
       qyf = quantize16(y);
@@ -991,7 +1014,7 @@ __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, i
   }
   const bool active = lane < f.n_rays;
   const float off = active ? ldg(f.offsets + lane) : 0.0f;
-  int32_t zo = active ? ldg(f.obs + lane) : 0;
+  int32_t zo = active ? ldx<Sys>(f.obs + lane) : 0;
   zo = zo < 0 ? 0 : (zo > M ? M : zo);
   const int P = f.pair_offset;
   // B: bins, pairing and the search queue
@@ -1074,7 +1097,7 @@ __device__ __forceinline__ void wave_tile_logw(const FilterDev& f, int64_t p0, i
     if (q < cnt) {
       if (f.ranges && active) stg(f.ranges + (p0 + q) * f.n_rays + lane, rg[q]);
       const float lw = wave_sum(tv[q]);
-      if (lane == 0) stg(f.logw + p0 + q, lw);
+      if (lane == 0) stx<Sys>(f.logw + p0 + q, lw);
     }
   }
 }

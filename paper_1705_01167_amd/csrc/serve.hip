@@ -24,12 +24,14 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
 #include <vector>
 
 #include "cddt_common.h"
+#include "ring_kernel.h"
 
 namespace cddt {
 namespace {
@@ -93,6 +95,42 @@ struct Lane {
   bool busy = false;
 };
 
+// Resident mode: the ring in pinned, fine-grained host memory (host and
+// device addresses), the device counters, and the host's bookkeeping.
+struct Pending {
+  Request* r;
+  int32_t slot;  // >= 0: the inputs are already in this slot
+};
+struct Resident {
+  RingCtl* ctl = nullptr;
+  RingSlot* slots = nullptr;
+  int32_t* tilemap = nullptr;
+  int64_t* done = nullptr;
+  char* arena = nullptr;
+  RingCtl* ctl_d = nullptr;
+  RingSlot* slots_d = nullptr;
+  int32_t* tilemap_d = nullptr;
+  int64_t* done_d = nullptr;
+  char* arena_d = nullptr;
+  RingDev* rd = nullptr;          // device
+  uint32_t* tiles_done = nullptr;  // device, one count per slot
+  int32_t n_slots = 0;
+  size_t slot_bytes = 0;
+  int64_t tiles = 0;  // tile map entries (a power of two)
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_start = nullptr, ev_end = nullptr;
+  bool running = false, drain_asked = false;
+  int64_t pub = 0;  // tiles published (host copy of ctl->pub)
+  std::vector<int32_t> free_slots;
+  std::vector<Request*> owner;          // request in each slot
+  std::vector<int64_t> t_begin;         // host copy of each slot's first tile
+  std::vector<int32_t> inflight;        // published slots, not finished
+  std::vector<int32_t> where;           // index of each slot in inflight (-1: not there)
+  std::deque<Pending> pending;
+  std::deque<std::pair<int64_t, int32_t>> order;  // (first tile, slot) in publication order, pruned lazily
+  uint64_t idle_ticks = 0, watch_ticks = 0;  // of the device's constant wall clock
+};
+
 }  // namespace
 }  // namespace cddt
 
@@ -117,6 +155,7 @@ struct cddt_server_s {
   cddt::Clock::time_point t0;
   double busy_since = -1.0;
   std::string error;
+  std::unique_ptr<cddt::Resident> res;  // resident mode
   double now() const { return std::chrono::duration<double>(cddt::Clock::now() - t0).count(); }
 };
 
@@ -349,6 +388,397 @@ void destroy_lanes(cddt_server_s* s) {
   s->maps.clear();
 }
 
+// ---------------------------------------------------------------------------
+// Resident mode
+// ---------------------------------------------------------------------------
+// The server leaves the kernel on the device this long after its last request
+// finished (then asks it to drain); the kernel's own limits are far longer and
+// only matter if the host stops answering.
+constexpr double kResidentIdleSeconds = 1e-3;
+constexpr double kWatchSeconds = 1.0, kWorkerIdleSeconds = 2.0;
+
+// Bytes a request takes in a slot: poses, observations, log-weights.
+size_t slot_need(const cddt_server_s* s, int32_t map, int32_t n) {
+  return align_up((size_t)n * 12) + align_up((size_t)s->maps[map].n_rays * 4) + align_up((size_t)n * 4);
+}
+
+// Copy a request's inputs into slot `sl` (host side of the pinned arena).
+void ring_fill(cddt_server_s* s, int32_t sl, int32_t map, int32_t n, const float* px, const float* py,
+               const float* pth, const int32_t* obs) {
+  Resident& R = *s->res;
+  char* b = R.arena + (size_t)sl * R.slot_bytes;
+  std::memcpy(b, px, 4 * (size_t)n);
+  std::memcpy(b + 4 * (size_t)n, py, 4 * (size_t)n);
+  std::memcpy(b + 8 * (size_t)n, pth, 4 * (size_t)n);
+  std::memcpy(b + align_up((size_t)n * 12), obs, 4 * (size_t)s->maps[map].n_rays);
+}
+
+// Lock held.  Give the request in slot `sl` the next tile numbers, write its
+// descriptor and tile map entries, and publish.  False when the tile map has
+// no room yet (the oldest request in flight still holds numbers that would
+// be reused).
+bool ring_publish(cddt_server_s* s, int32_t sl) {
+  Resident& R = *s->res;
+  Request* r = R.owner[sl];
+  const int64_t ppt = s->cfg.tuning.particles_per_tile;
+  const int64_t nt = ((int64_t)r->n + ppt - 1) / ppt;
+  while (!R.order.empty()) {  // drop finished or renumbered entries from the front
+    const auto& e = R.order.front();
+    if (R.where[e.second] >= 0 && R.t_begin[e.second] == e.first) break;
+    R.order.pop_front();
+  }
+  const int64_t oldest = R.order.empty() ? R.pub : R.order.front().first;
+  if (R.pub + nt - oldest > R.tiles) return false;
+  const ServedMap& m = s->maps[r->map];
+  const size_t n = (size_t)r->n;
+  char* b = R.arena_d + (size_t)sl * R.slot_bytes;
+  RingSlot slot{};
+  FilterDev& d = slot.f;
+  d.map = m.map->dev();
+  d.px = (const float*)b;
+  d.py = (const float*)b + n;
+  d.pth = (const float*)b + 2 * n;
+  d.obs = (const int32_t*)(b + align_up(n * 12));
+  d.logw = (float*)(b + align_up(n * 12) + align_up((size_t)m.n_rays * 4));
+  d.offsets = m.d_offsets;
+  d.table = m.table;
+  d.ranges = nullptr;
+  d.n_particles = (int64_t)n;
+  d.n_rays = m.n_rays;
+  d.pair_offset = m.pair;
+  d.max_range = m.max_range;
+  slot.t_begin = R.pub;
+  slot.n_tiles = (int32_t)nt;
+  slot.id = r->id;
+  std::memcpy(&R.slots[sl], &slot, sizeof(RingSlot));
+  for (int64_t k = 0; k < nt; ++k) R.tilemap[(R.pub + k) & (R.tiles - 1)] = sl;
+  __atomic_store_n(&R.done[sl], (int64_t)0, __ATOMIC_RELAXED);
+  R.t_begin[sl] = R.pub;
+  R.order.emplace_back(R.pub, sl);
+  if (R.where[sl] < 0) {
+    R.where[sl] = (int32_t)R.inflight.size();
+    R.inflight.push_back(sl);
+  }
+  R.pub += nt;
+  __atomic_store_n(&R.ctl->pub, R.pub, __ATOMIC_RELEASE);
+  return true;
+}
+
+// Lock held.  Publish waiting requests while slots and tile numbers allow.
+void ring_admit(cddt_server_s* s) {
+  Resident& R = *s->res;
+  while (!R.pending.empty()) {
+    Pending& pd = R.pending.front();
+    if (pd.slot < 0) {
+      if (R.free_slots.empty()) return;
+      pd.slot = R.free_slots.back();
+      R.free_slots.pop_back();
+      Request* r = pd.r;
+      R.owner[pd.slot] = r;
+      const size_t n = (size_t)r->n;
+      ring_fill(s, pd.slot, r->map, r->n, r->poses.data(), r->poses.data() + n, r->poses.data() + 2 * n,
+                r->obs.data());
+      r->poses.clear();
+      r->poses.shrink_to_fit();
+      s->bytes_in_flight += (int64_t)R.slot_bytes;
+      s->stats.peak_bytes = std::max<int64_t>(s->stats.peak_bytes, s->bytes_in_flight);
+    }
+    if (!ring_publish(s, pd.slot)) return;
+    R.pending.pop_front();
+  }
+}
+
+// Lock held.  Finish the request in slot `sl` (results already copied out,
+// or NaN when `ok` is false).
+void ring_finish(cddt_server_s* s, int32_t sl, double t, bool ok = true) {
+  Resident& R = *s->res;
+  Request* r = R.owner[sl];
+  r->done_t = t;
+  r->done = true;
+  s->times[(size_t)r->id % kTimesRing] = {r->id, r->submit_t, t};
+  if (ok) {
+    s->stats.completed++;
+    s->stats.rays += (int64_t)r->n * s->maps[r->map].n_rays;
+  }
+  R.owner[sl] = nullptr;
+  const int32_t i = R.where[sl];
+  R.inflight[i] = R.inflight.back();
+  R.where[R.inflight[i]] = i;
+  R.inflight.pop_back();
+  R.where[sl] = -1;
+  R.free_slots.push_back(sl);
+  s->bytes_in_flight -= (int64_t)R.slot_bytes;
+}
+
+template <int Mode>
+void ring_launch_mode(cddt_server_s* s, unsigned blocks, unsigned threads, size_t lds) {
+  Resident& R = *s->res;
+  if (s->zp16)
+    hipLaunchKernelGGL((k_resident<Mode, true>), dim3(blocks), dim3(threads), lds, R.stream, R.ctl_d, R.slots_d,
+                       R.tilemap_d, R.tiles - 1, R.done_d, R.rd, R.tiles_done, R.n_slots,
+                       s->cfg.tuning.particles_per_tile, R.idle_ticks, R.watch_ticks);
+  else
+    hipLaunchKernelGGL((k_resident<Mode, false>), dim3(blocks), dim3(threads), lds, R.stream, R.ctl_d, R.slots_d,
+                       R.tilemap_d, R.tiles - 1, R.done_d, R.rd, R.tiles_done, R.n_slots,
+                       s->cfg.tuning.particles_per_tile, R.idle_ticks, R.watch_ticks);
+}
+
+// Launch the resident kernel with tickets from `base` (nothing below it is
+// left to do), after clearing its counters, between two events.
+cddt_status ring_launch(cddt_server_s* s, int64_t base) {
+  Resident& R = *s->res;
+  const cddt_tuning& t = s->cfg.tuning;
+  hipLaunchKernelGGL(k_ring_reset, dim3(std::max(1, std::min(64, (R.n_slots + 255) / 256))), dim3(256), 0,
+                     R.stream, R.rd, (unsigned long long)base, R.tiles_done, R.n_slots);
+  CDDT_HIP(hipGetLastError());
+  CDDT_HIP(hipEventRecord(R.ev_start, R.stream));
+  const unsigned blocks = (unsigned)(s->cus * t.blocks_per_cu + 1);  // block 0 watches
+  const unsigned threads = (unsigned)(kWave * t.waves_per_block);
+  const size_t lds = tile_lds_bytes(t.search_mode, t.waves_per_block);
+  switch (t.search_mode) {
+    case 0: ring_launch_mode<0>(s, blocks, threads, lds); break;
+    case 6: ring_launch_mode<6>(s, blocks, threads, lds); break;
+    case 7: ring_launch_mode<7>(s, blocks, threads, lds); break;
+    case 8: ring_launch_mode<8>(s, blocks, threads, lds); break;
+    default: return fail(CDDT_EINVAL, "resident server: search mode must be 0, 6, 7 or 8");
+  }
+  CDDT_HIP(hipGetLastError());
+  CDDT_HIP(hipEventRecord(R.ev_end, R.stream));
+  return CDDT_OK;
+}
+
+// Lock held.  The kernel has ended: renumber every request still in flight
+// (the ended kernel may have dropped some of its tiles), fail them all if it
+// ended in error.
+void ring_after_end(cddt_server_s* s, hipError_t st) {
+  Resident& R = *s->res;
+  R.running = false;
+  R.drain_asked = false;
+  __atomic_store_n(&R.ctl->drain, 0, __ATOMIC_RELEASE);
+  float ms = 0.f;
+  if (st == hipSuccess && hipEventElapsedTime(&ms, R.ev_start, R.ev_end) == hipSuccess) {
+    s->stats.device_seconds += 1e-3 * ms;
+    s->stats.max_batch_seconds = std::max(s->stats.max_batch_seconds, 1e-3 * ms);
+  }
+  if (st != hipSuccess) {
+    s->error = hipGetErrorString(st);
+    const double t = s->now();
+    while (!R.inflight.empty()) {
+      const int32_t sl = R.inflight.back();
+      Request* r = R.owner[sl];
+      r->logw.assign((size_t)r->n, __builtin_nanf(""));
+      ring_finish(s, sl, t, false);
+    }
+    s->cv_done.notify_all();
+    return;
+  }
+  R.order.clear();
+  const std::vector<int32_t> again = R.inflight;
+  for (int32_t sl : again) (void)ring_publish(s, sl);  // the map is sized for every slot at once
+}
+
+void ring_driver(cddt_server_s* s) {
+  (void)hipSetDevice(s->device);
+  Resident& R = *s->res;
+  std::vector<std::pair<int32_t, int64_t>> look;  // (slot, id) in flight
+  std::vector<int32_t> finished;
+  double idle_since = -1.0;
+  for (;;) {
+    // 1. locked: what is in flight
+    look.clear();
+    {
+      std::lock_guard<std::mutex> g(s->mu);
+      for (int32_t sl : R.inflight) look.emplace_back(sl, R.owner[sl]->id);
+    }
+    // 2. unlocked: completion words, results out of the pinned arena
+    finished.clear();
+    for (const auto& e : look) {
+      if (__atomic_load_n(&R.done[e.first], __ATOMIC_ACQUIRE) != e.second + 1) continue;
+      Request* r = R.owner[e.first];
+      const ServedMap& m = s->maps[r->map];
+      const float* lw = (const float*)(R.arena + (size_t)e.first * R.slot_bytes + align_up((size_t)r->n * 12) +
+                                       align_up((size_t)m.n_rays * 4));
+      r->logw.assign(lw, lw + r->n);
+      finished.push_back(e.first);
+    }
+    hipError_t ended = hipErrorNotReady;
+    if (R.running) ended = hipEventQuery(R.ev_end);
+    // 3. locked: publish completions, relaunch or drain
+    bool launch = false, busy = false, stop = false;
+    int64_t base = 0;
+    {
+      std::lock_guard<std::mutex> g(s->mu);
+      const double t = s->now();
+      for (int32_t sl : finished) ring_finish(s, sl, t);
+      if (!finished.empty()) s->cv_done.notify_all();
+      if (ended != hipErrorNotReady && R.running) ring_after_end(s, ended);
+      ring_admit(s);
+      stop = s->stop;
+      busy = !R.inflight.empty() || !R.pending.empty();
+      if (busy && s->busy_since < 0) s->busy_since = t;
+      if (!busy && s->busy_since >= 0) {
+        s->stats.busy_seconds += t - s->busy_since;
+        s->busy_since = -1.0;
+      }
+      if (!R.running && !R.inflight.empty() && !stop) {
+        // every tile below the oldest first tile in flight is finished or dropped
+        base = R.pub;
+        for (int32_t sl : R.inflight) base = std::min(base, R.t_begin[sl]);
+        R.running = true;
+        launch = true;
+        s->stats.batches++;
+      }
+      if (R.running && !R.drain_asked) {
+        if (busy && !stop) {
+          idle_since = -1.0;
+        } else {
+          if (idle_since < 0) idle_since = t;
+          if (stop || t - idle_since > kResidentIdleSeconds) {
+            __atomic_store_n(&R.ctl->drain, 1, __ATOMIC_RELEASE);
+            R.drain_asked = true;
+          }
+        }
+      }
+      if (stop && !R.running) break;
+    }
+    if (launch && ring_launch(s, base) != CDDT_OK) {
+      std::lock_guard<std::mutex> g(s->mu);
+      ring_after_end(s, hipErrorLaunchFailure);
+      continue;
+    }
+    // 4. spin while a kernel is on the device or work waits; block when idle
+    if (R.running || busy) {
+      std::this_thread::yield();
+      continue;
+    }
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_work.wait(lk, [&] { return s->stop || !R.pending.empty() || !R.inflight.empty(); });
+  }
+  (void)hipStreamSynchronize(R.stream);
+}
+
+// Submission in resident mode: a free slot is filled without the lock and
+// published at once; otherwise the request waits with its own copy.
+cddt_status ring_submit(cddt_server_s* s, int32_t map_index, const float* px_h, const float* py_h,
+                        const float* ptheta_h, int32_t n_particles, const int32_t* obs_h, double arrival,
+                        int64_t* id_h) {
+  Resident& R = *s->res;
+  if (slot_need(s, map_index, n_particles) > R.slot_bytes) {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stats.rejected++;
+    return fail(CDDT_EBUSY, "server: request larger than a ring slot (budget_bytes / max_batch)");
+  }
+  Request* r = new Request();
+  r->map = map_index;
+  r->n = n_particles;
+  r->bytes = R.slot_bytes;
+  int32_t sl = -1;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->stop) {
+      s->stats.rejected++;
+      delete r;
+      return fail(CDDT_EBUSY, "server: closing");
+    }
+    r->id = s->next_id++;
+    r->submit_t = arrival >= 0.0 ? arrival : s->now();
+    s->live[r->id] = r;
+    s->stats.submitted++;
+    *id_h = r->id;
+    if (n_particles == 0) {  // nothing to compute
+      r->done = true;
+      r->done_t = s->now();
+      s->times[(size_t)r->id % kTimesRing] = {r->id, r->submit_t, r->done_t};
+      s->stats.completed++;
+      s->cv_done.notify_all();
+      return CDDT_OK;
+    }
+    if (R.pending.empty() && !R.free_slots.empty()) {
+      sl = R.free_slots.back();
+      R.free_slots.pop_back();
+      R.owner[sl] = r;
+      s->bytes_in_flight += (int64_t)R.slot_bytes;
+      s->stats.peak_bytes = std::max<int64_t>(s->stats.peak_bytes, s->bytes_in_flight);
+    }
+  }
+  if (sl >= 0) {
+    ring_fill(s, sl, map_index, n_particles, px_h, py_h, ptheta_h, obs_h);
+    std::lock_guard<std::mutex> g(s->mu);
+    if (!R.pending.empty() || !ring_publish(s, sl)) R.pending.push_back({r, sl});
+  } else {
+    r->poses.resize((size_t)n_particles * 3);
+    std::memcpy(r->poses.data(), px_h, 4 * (size_t)n_particles);
+    std::memcpy(r->poses.data() + n_particles, py_h, 4 * (size_t)n_particles);
+    std::memcpy(r->poses.data() + 2 * (size_t)n_particles, ptheta_h, 4 * (size_t)n_particles);
+    r->obs.assign(obs_h, obs_h + s->maps[map_index].n_rays);
+    std::lock_guard<std::mutex> g(s->mu);
+    R.pending.push_back({r, -1});
+    ring_admit(s);
+  }
+  s->cv_work.notify_one();
+  return CDDT_OK;
+}
+
+void destroy_resident(cddt_server_s* s) {
+  if (!s->res) return;
+  Resident& R = *s->res;
+  if (R.ev_start) (void)hipEventDestroy(R.ev_start);
+  if (R.ev_end) (void)hipEventDestroy(R.ev_end);
+  if (R.stream) (void)hipStreamDestroy(R.stream);
+  if (R.rd) (void)hipFree(R.rd);
+  if (R.tiles_done) (void)hipFree(R.tiles_done);
+  for (void* p : {(void*)R.ctl, (void*)R.slots, (void*)R.tilemap, (void*)R.done, (void*)R.arena})
+    if (p) (void)hipHostFree(p);
+  for (Pending& pd : R.pending) {
+    if (s->live.erase(pd.r->id) == 0) continue;
+    delete pd.r;
+  }
+  R.pending.clear();
+  s->res.reset();
+}
+
+// Allocate the ring for `c` (resident mode).  Errors as cddt_server_create.
+cddt_status create_resident(cddt_server_s* s, const cddt_server_config& c) {
+  s->res.reset(new Resident());
+  Resident& R = *s->res;
+  R.n_slots = c.max_batch;
+  R.slot_bytes = (size_t)(c.budget_bytes / c.max_batch) & ~(kAlign - 1);
+  if (R.slot_bytes < 3 * kAlign + (size_t)4 * c.max_rays)
+    return fail(CDDT_EINVAL, "cddt_server_create: budget_bytes / max_batch too small for one request");
+  const int64_t max_n = (int64_t)(R.slot_bytes / 16);
+  const int64_t per_slot = (max_n + c.tuning.particles_per_tile - 1) / c.tuning.particles_per_tile;
+  R.tiles = 1;
+  while (R.tiles < (int64_t)R.n_slots * per_slot) R.tiles *= 2;
+  if (R.tiles > ((int64_t)1 << 28)) return fail(CDDT_EINVAL, "cddt_server_create: ring tile map too large");
+  // the kernel's own exit limits in ticks of the device's constant wall clock
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device) != hipSuccess || khz <= 0)
+    return fail(CDDT_EDEVICE, "cddt_server_create: cannot query the device's wall clock rate");
+  R.watch_ticks = (uint64_t)(kWatchSeconds * 1e3 * khz);
+  R.idle_ticks = (uint64_t)(kWorkerIdleSeconds * 1e3 * khz);
+  const unsigned fl = hipHostMallocCoherent | hipHostMallocMapped;
+  auto pin = [&](void** h, void** d, size_t bytes) {
+    return hipHostMalloc(h, bytes, fl) == hipSuccess && hipHostGetDevicePointer(d, *h, 0) == hipSuccess;
+  };
+  if (!pin((void**)&R.ctl, (void**)&R.ctl_d, sizeof(RingCtl)) ||
+      !pin((void**)&R.slots, (void**)&R.slots_d, sizeof(RingSlot) * (size_t)R.n_slots) ||
+      !pin((void**)&R.tilemap, (void**)&R.tilemap_d, 4 * (size_t)R.tiles) ||
+      !pin((void**)&R.done, (void**)&R.done_d, 8 * (size_t)R.n_slots) ||
+      !pin((void**)&R.arena, (void**)&R.arena_d, R.slot_bytes * (size_t)R.n_slots) ||
+      hipMalloc(&R.rd, sizeof(RingDev)) != hipSuccess || hipMalloc(&R.tiles_done, 4 * (size_t)R.n_slots) != hipSuccess ||
+      hipStreamCreateWithFlags(&R.stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&R.ev_start) != hipSuccess || hipEventCreate(&R.ev_end) != hipSuccess)
+    return fail(CDDT_ENOMEM, "cddt_server_create: ring allocation failed");
+  std::memset(R.ctl, 0, sizeof(RingCtl));
+  std::memset(R.tilemap, 0xff, 4 * (size_t)R.tiles);  // -1: no slot
+  std::memset(R.done, 0, 8 * (size_t)R.n_slots);
+  R.owner.assign(R.n_slots, nullptr);
+  R.t_begin.assign(R.n_slots, 0);
+  R.where.assign(R.n_slots, -1);
+  for (int32_t k = R.n_slots - 1; k >= 0; --k) R.free_slots.push_back(k);
+  return CDDT_OK;
+}
+
 }  // namespace
 }  // namespace cddt
 
@@ -374,7 +804,12 @@ cddt_status cddt_server_create(const cddt_map* maps_h, int32_t n_maps, const flo
   const cddt_server_config& c = *config_h;
   if (c.n_lanes < 1 || c.n_lanes > kMaxLanes)
     return fail(CDDT_EINVAL, "cddt_server_create: n_lanes must be in 1..4");
-  if (c.max_batch < 1 || c.max_batch > 4096) return fail(CDDT_EINVAL, "cddt_server_create: max_batch in 1..4096");
+  if (c.resident != 0 && c.resident != 1) return fail(CDDT_EINVAL, "cddt_server_create: resident must be 0 or 1");
+  if (c.resident && c.n_lanes != 1) return fail(CDDT_EINVAL, "cddt_server_create: resident mode takes n_lanes = 1");
+  if (c.resident && c.tuning.search_mode != 0 && (c.tuning.search_mode < 6 || c.tuning.search_mode > 8))
+    return fail(CDDT_EINVAL, "cddt_server_create: resident mode takes search modes 0, 6, 7 and 8");
+  if (c.max_batch < 1 || c.max_batch > (c.resident ? 65536 : 4096))
+    return fail(CDDT_EINVAL, "cddt_server_create: max_batch in 1..4096 (resident: 1..65536)");
   if (c.max_rays < 1 || c.max_rays > kMaxRays) return fail(CDDT_EINVAL, "cddt_server_create: max_rays in 1..1024");
   if (c.budget_bytes < (int64_t)c.n_lanes * 4096) return fail(CDDT_EINVAL, "cddt_server_create: budget too small");
   CDDT_TRY(check_tuning(c.tuning));
@@ -405,6 +840,19 @@ cddt_status cddt_server_create(const cddt_map* maps_h, int32_t n_maps, const flo
     s->maps.push_back(m);
     if (hipMemcpy(m.d_offsets, offsets_h[i], 4 * (size_t)m.n_rays, hipMemcpyHostToDevice) != hipSuccess)
       return bail("cddt_server_create: offsets upload");
+  }
+  if (c.resident) {
+    const cddt_status st = create_resident(s, c);
+    if (st != CDDT_OK) {
+      const std::string msg = cddt_last_error();
+      destroy_resident(s);
+      destroy_lanes(s);
+      delete s;
+      return fail(st, msg);
+    }
+    s->sched = std::thread(ring_driver, s);
+    *out_h = s;
+    return CDDT_OK;
   }
   const size_t arena = (size_t)(c.budget_bytes / c.n_lanes);
   s->lanes.resize(c.n_lanes);
@@ -465,6 +913,7 @@ namespace {
 cddt_status submit_one(cddt_server_s* s, int32_t map_index, const float* px_h, const float* py_h,
                        const float* ptheta_h, int32_t n_particles, const int32_t* obs_h, double arrival,
                        int64_t* id_h) {
+  if (s->res) return ring_submit(s, map_index, px_h, py_h, ptheta_h, n_particles, obs_h, arrival, id_h);
   const size_t bytes = request_bytes(s, map_index, n_particles);
   Request* r = new Request();
   r->map = map_index;
@@ -559,6 +1008,7 @@ cddt_status cddt_server_destroy(cddt_server s) {
   }
   s->cv_work.notify_all();
   if (s->sched.joinable()) s->sched.join();
+  destroy_resident(s);
   for (auto& kv : s->live) delete kv.second;
   s->live.clear();
   destroy_lanes(s);

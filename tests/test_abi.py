@@ -76,6 +76,12 @@ def test_validation_needs_no_gpu():
     mr = (C.c_int32 * 1)(500)
     assert L.cddt_server_create(fake, 1, offs, nr, offs, mr, C.byref(cfg), C.byref(out)) == cddt.EINVAL
     assert b"1..4" in L.cddt_last_error()
+    # resident mode: one lane, search modes 0 and 6..8
+    cfg = cddt.ServerConfig(1 << 20, 2, 8, 61, 1, cddt.Tuning(8, 2, 8, 7))
+    assert L.cddt_server_create(fake, 1, offs, nr, offs, mr, C.byref(cfg), C.byref(out)) == cddt.EINVAL
+    cfg = cddt.ServerConfig(1 << 20, 1, 8, 61, 1, cddt.Tuning(8, 2, 8, 9))
+    assert L.cddt_server_create(fake, 1, offs, nr, offs, mr, C.byref(cfg), C.byref(out)) == cddt.EINVAL
+    assert b"search modes" in L.cddt_last_error()
     assert L.cddt_batch_weight(None, 1, None, None) == cddt.EINVAL
     f = cddt.Filter()   # map NULL: refused before any device call
     assert L.cddt_batch_weight(C.byref(f), 0, None, None) == cddt.EINVAL
