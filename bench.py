@@ -14,7 +14,9 @@ Other workloads (each prints its own JSON line): `small` (256^2 rectangle map,
 1000 particles x 61 rays, plain casts), `floor` (2000^2 floor, 2500 particles,
 fused weights), `updates` (4000^2 floor, 1000 toggles + 1M particles x 61
 casts per step), `serving` (8 resident maps, Poisson arrivals swept over load),
-`probe` (random-gather bandwidth only).
+`suites` (the paper's grid and random query suites: per-query time distribution
+and rays/s on CDDT, PCDDT and the dense lookup-table comparator), `probe`
+(random-gather bandwidth only).
 """
 from __future__ import annotations
 
@@ -432,6 +434,130 @@ def run_floor(args) -> dict:
                          "algorithmic_GBps": 2500 * RAYS * BYTES_PER_RAY_FUSED / (ms * 1e-3) / 1e9}}
 
 
+# The paper's query-time suites (Sec. VI): a uniformly spaced grid over the states and uniformly random states,
+# on the building floor and on a 1000^2 stand-in for the paper's maps (which are not available)
+SUITE_MAPS = (("floor 2000^2, 200 bins (the building-floor map)", 2000, 200),
+              ("room map 1000^2, 108 bins (stand-in for the paper's ~1000^2 maps)", 1000, 108))
+SUITE_LAYOUTS = (("cddt", {}), ("cddt, bucket index 2^7", {"buckets": 7}), ("pcddt", {"prune": True}))
+SUITE_POSITIONS = 500  # grid positions per axis (stride = side / 500), at every bin: 250,000 x bins queries
+SUITE_SAMPLE = 1 << 21  # per-query times summarised on this many queries (a seeded sample)
+SUITE_CPU_QUERIES = 1 << 20  # queries the CPU oracle times per suite, one thread
+# the paper's per-query times in seconds (one CPU thread; its Synthetic map, ~1000^2; its tables), as context
+PAPER_SUITE_TIMES = {"random": {"cddt": (1.24e-07, 1.05e-07, 5.3e-08), "pcddt": (1.19e-07, 1.01e-07, 5e-08),
+                                "lut": (1.82e-07, 1.68e-07, 1.4e-08)},
+                     "grid": {"cddt": (7.02e-08, 6.8e-08, 1e-08), "pcddt": (6.94e-08, 6.8e-08, 9e-09),
+                              "lut": (6.33e-08, 4.2e-08, 4.6e-08)}}
+
+
+def per_query_stats(ticks, khz: int, seed: int) -> dict:
+    """Mean, median and inter-quartile range of per-query times (ns) on a seeded sample."""
+    import torch
+    n = ticks.numel()
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    idx = torch.randint(0, n, (min(n, SUITE_SAMPLE),), generator=g).to(ticks.device)
+    ns = ticks[idx].double().cpu().numpy() * (1e6 / khz)
+    q1, med, q3 = np.percentile(ns, [25, 50, 75])
+    return {"mean_ns": float(ns.mean()), "median_ns": float(med), "iqr_ns": float(q3 - q1), "sampled": int(ns.size)}
+
+
+def time_queries(fn, reps: int = 3) -> float:
+    """Kernel milliseconds of fn(stream): best of reps, HIP events on the stream the launch uses."""
+    import torch
+    st = torch.cuda.Stream()
+    fn(st)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        fn(st)
+        e1.record(st)
+        st.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def run_suites(args) -> dict:
+    import torch
+    from oracle import ref as oref
+    from paper_1705_01167_amd import cddt
+    from paper_1705_01167_amd import workloads as wl
+    khz = cddt.device_clock_khz()
+    out = []
+    for mi, (name, side, n) in enumerate(SUITE_MAPS):
+        seed_map = (wl.FLOOR, wl.S_MAP) if side == 2000 else (wl.SUITES, wl.S_MAP)
+        occ = wl.building_map(wl.rng_for(*seed_map), side, side)
+        stride = side // SUITE_POSITIONS
+        suites = {"grid": wl.grid_states(side, side, n, stride),
+                  "random": wl.random_states(wl.rng_for(wl.SUITES, wl.S_POSES, mi), side, side,
+                                             SUITE_POSITIONS * SUITE_POSITIONS * n)}
+        dev = {k: tuple(t_dev(a) for a in v) for k, v in suites.items()}
+        log(f"bench: suites on {name}: {suites['grid'][0].size} queries per suite")
+        entry = {"map": name, "occupancy": float(occ.mean()), "queries_per_suite": int(suites["grid"][0].size),
+                 "grid_stride_cells": stride, "layouts": {}}
+        plain_ranges = {}
+        for lname, kw in SUITE_LAYOUTS:
+            m = cddt.Map(t_dev(occ), n, **kw)
+            info = m.info()
+            res = {"structure_bytes": int(info["device_bytes"]), "zero_points": int(info["zero_points"])}
+            for sname, (x, y, th) in dev.items():
+                q = x.numel()
+                ms = time_queries(lambda st: m.cast(x, y, th, MAX_RANGE, stream=st))
+                rg = m.cast(x, y, th, MAX_RANGE)
+                rg_t, ticks = m.cast_timed(x, y, th, MAX_RANGE)
+                torch.cuda.synchronize()
+                if lname == "cddt":
+                    plain_ranges[sname] = rg
+                res[sname] = {"rays_per_s": q / (ms * 1e-3), "ns_per_query_amortized": ms * 1e6 / q,
+                              "kernel_ms": ms, "per_query": per_query_stats(ticks, khz, 7 + mi),
+                              "timed_equals_untimed": bool(torch.equal(rg, rg_t)),
+                              "equals_cddt": bool(torch.equal(rg, plain_ranges[sname]))
+                              if sname in plain_ranges else None}
+                log(f"bench: suites {name} / {lname} / {sname}: {res[sname]}")
+            entry["layouts"][lname] = res
+            m.close()
+        # the dense lookup-table comparator, built from the plain map's casts at every discrete state
+        m = cddt.Map(t_dev(occ), n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lut = m.lut(MAX_RANGE)
+        torch.cuda.synchronize()
+        res = {"bytes": lut.numel() * 2, "build_s": time.perf_counter() - t0}
+        for sname, (x, y, th) in dev.items():
+            q = x.numel()
+            ms = time_queries(lambda st: cddt.lut_cast(lut, x, y, th, stream=st))
+            rg, ticks = cddt.lut_cast(lut, x, y, th, timed=True)
+            torch.cuda.synchronize()
+            res[sname] = {"rays_per_s": q / (ms * 1e-3), "ns_per_query_amortized": ms * 1e6 / q, "kernel_ms": ms,
+                          "per_query": per_query_stats(ticks, khz, 9 + mi),
+                          "agreement_with_cddt": float((rg == plain_ranges[sname]).double().mean())}
+            log(f"bench: suites {name} / table / {sname}: {res[sname]}")
+        entry["lut"] = res
+        del lut
+        m.close()
+        # the CPU oracle (plain C++ CDDT) per query on one thread, a sample of each suite
+        if not args.no_cpu:
+            rm = oref.RefCDDT(occ, n)
+            cpu = {}
+            for sname, (x, y, th) in suites.items():
+                sel = np.random.default_rng(11 + mi).integers(0, x.size, SUITE_CPU_QUERIES)
+                xs, ys, ts = x[sel], y[sel], th[sel]
+                rm.cast(xs[:1024], ys[:1024], ts[:1024], MAX_RANGE)
+                t0 = time.perf_counter()
+                rm.cast(xs, ys, ts, MAX_RANGE)
+                cpu[sname] = {"ns_per_query_amortized": (time.perf_counter() - t0) * 1e9 / xs.size,
+                              "queries": int(xs.size), "threads": 1}
+            rm.close()
+            entry["cpu_oracle"] = cpu
+        del dev
+        torch.cuda.empty_cache()
+        out.append(entry)
+    return {"metric": "query-time suites: per-query time (mean, median, IQR) and rays/s, grid and random states",
+            "device_clock_khz": khz, "maps": out, "paper_context_seconds_mean_median_iqr": PAPER_SUITE_TIMES,
+            "per_query_note": "per-query time = device wall-clock ticks from a query's load to its result, for "
+                              "its wave (64 queries, or 256 in the queued kernel) among all the waves in flight; "
+                              "ns_per_query_amortized = kernel time / queries"}
+
+
 def run_updates(args) -> dict:
     import torch
     from paper_1705_01167_amd import cddt
@@ -497,6 +623,13 @@ SERVE_SIDES = (1000, 1500, 2000, 2500, 3000, 3500, 4000, 4000)
 # request per robot on the serving maps), converted to requests/s with the requests' mean ray count
 SERVE_FRACTIONS = (0.10, 0.25, 0.40, 0.55, 0.70, 0.85, 1.00, 1.20)
 SERVE_TIGHT_BUDGET = 2 << 20  # bytes: lanes share it, so each batch holds a few dozen requests at most
+SERVE_SLOTS = 1024  # ring slots of the resident server (the budget is split among them)
+SERVE_SLOT_MIN = 32 << 10  # bytes: a slot holds the largest request (1,639 particles)
+SERVE_RESIDENT_TUNING = (8, 2, 8, 7)
+
+
+def resident_slots(budget: int) -> int:
+    return max(1, min(SERVE_SLOTS, budget // SERVE_SLOT_MIN))
 
 
 def build_serving(buckets):
@@ -576,19 +709,27 @@ def serving_plan_capacity(maps, offs, tabs, pools, obs) -> float:
     return sum(r[5] for r in reqs) * RAYS / (ms * 1e-3)
 
 
-def run_serving(args, ref_rays_per_s: float | None = None, lanes: int | None = None) -> dict:
-    """Open-loop Poisson arrivals at SERVE_FRACTIONS of the batched capacity, args.serve_requests each."""
+def make_server(maps, offs, tabs, args, mode: str, budget: int):
+    """mode: a lane count ('1'..'4': batches on that many streams) or 'r' (one resident kernel, ring slots)."""
     from paper_1705_01167_amd import cddt
+    if mode == "r":
+        return cddt.Server(maps, offs, tabs, [MAX_RANGE] * len(maps), budget_bytes=budget, n_lanes=1,
+                           max_batch=resident_slots(budget), tuning=SERVE_RESIDENT_TUNING, resident=True)
+    return cddt.Server(maps, offs, tabs, [MAX_RANGE] * len(maps), budget_bytes=budget, n_lanes=int(mode),
+                       max_batch=args.serve_batch)
+
+
+def run_serving(args, ref_rays_per_s: float | None = None, mode: str | None = None) -> dict:
+    """Open-loop Poisson arrivals at SERVE_FRACTIONS of the batched capacity, args.serve_requests each."""
     # the serving maps have no bucket index unless one is asked for explicitly
     buckets = None if args.buckets.lower() == "auto" else BUCKETS
-    lanes = lanes or int(str(args.serve_lanes).split(",")[0])
+    mode = mode or str(args.serve_lanes).split(",")[0]
     maps, offs, tabs, pools, obs = build_serving(buckets)
     ref_kind = "the many-filter step's kernel rays/s in this run"
     if ref_rays_per_s is None:
         ref_rays_per_s = serving_plan_capacity(maps, offs, tabs, pools, obs)
         ref_kind = "one persistent launch over one request per robot on the serving maps"
-    srv = cddt.Server(maps, offs, tabs, [MAX_RANGE] * len(maps), budget_bytes=args.serve_budget,
-                      n_lanes=lanes, max_batch=args.serve_batch)
+    srv = make_server(maps, offs, tabs, args, mode, args.serve_budget)
     warm = make_requests(500, 0, pools, obs)
     serve_at(srv, warm, None, 0)
     # burst capacity: median of three bursts (every request arrives at once, so batches are as large as the
@@ -602,13 +743,12 @@ def run_serving(args, ref_rays_per_s: float | None = None, lanes: int | None = N
         mean_rays = sum(r[5] for r in reqs) * RAYS / len(reqs)
         rate = frac * ref_rays_per_s / mean_rays
         points.append({"fraction_of_batched_capacity": frac, **serve_at(srv, reqs, float(rate), 10 + j)})
-        log(f"bench: serving ({lanes} lanes) at {frac:.0%} of batched capacity: {points[-1]}")
+        log(f"bench: serving ({mode}) at {frac:.0%} of batched capacity: {points[-1]}")
     st = srv.stats()
     srv.close()
     # admission limited by memory: a budget of SERVE_TIGHT_BUDGET bytes (a few dozen requests in flight)
     # under the offered load of the 85% point
-    tight = cddt.Server(maps, offs, tabs, [MAX_RANGE] * len(maps), budget_bytes=SERVE_TIGHT_BUDGET,
-                        n_lanes=lanes, max_batch=args.serve_batch)
+    tight = make_server(maps, offs, tabs, args, mode, SERVE_TIGHT_BUDGET)
     serve_at(tight, warm, None, 0)
     reqs = make_requests(args.serve_requests, 30, pools, obs)
     rate = 0.85 * ref_rays_per_s / (sum(r[5] for r in reqs) * RAYS / len(reqs))
@@ -621,7 +761,10 @@ def run_serving(args, ref_rays_per_s: float | None = None, lanes: int | None = N
             "points": points, "stats": st, "budget_limited": budget_point,
             "config": {"maps": list(SERVE_SIDES), "theta_bins": [m.theta_bins for m in maps], "robots": 256,
                        "request_particles": "log-uniform 17..1639", "bucket_log2": buckets,
-                       "budget_bytes": args.serve_budget, "lanes": lanes, "max_batch": args.serve_batch,
+                       "budget_bytes": args.serve_budget,
+                       "mode": "resident kernel, ring of slots" if mode == "r" else f"{mode} lanes",
+                       "slots" if mode == "r" else "max_batch":
+                           resident_slots(args.serve_budget) if mode == "r" else args.serve_batch,
                        "requests_per_rate": args.serve_requests}}
 
 
@@ -643,7 +786,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batched",
-                    choices=["batched", "small", "floor", "updates", "serving", "probe"])
+                    choices=["batched", "small", "floor", "updates", "serving", "suites", "probe"])
     ap.add_argument("--filters", type=int, default=64)
     ap.add_argument("--buckets", type=str, default="auto",
                     help="log2 bucket width in cells of the maps' bucket index, 'none' for no index, or 'auto': "
@@ -667,7 +810,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=20000, help="requests per offered rate")
     ap.add_argument("--serve-budget", type=int, default=256 << 20)
     ap.add_argument("--serve-lanes", type=str, default="4",
-                    help="batches in flight (streams, 1..4); the serving workload takes a comma-separated list")
+                    help="batches in flight (streams, 1..4), or r for one resident kernel fed through a ring of "
+                         "slots; the serving workload takes a comma-separated list")
     ap.add_argument("--serve-batch", type=int, default=512)
     ap.add_argument("--probe-gib", type=str, default="4", help="probe buffer sizes in GiB, comma separated")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -702,9 +846,11 @@ def main():
         out = run_floor(args)
     elif args.workload == "updates":
         out = run_updates(args)
+    elif args.workload == "suites":
+        out = run_suites(args)
     elif args.workload == "serving":
         out = {"metric": "serving: completed rays/s and p50/p99 latency vs offered load",
-               "runs": [run_serving(args, lanes=int(v)) for v in args.serve_lanes.split(",")]}
+               "runs": [run_serving(args, mode=v) for v in args.serve_lanes.split(",")]}
     else:
         out = {"gather_probe": [cddt.probe_gather(gib=float(g), depth=d) for g in args.probe_gib.split(",")
                                 for d in (1, 4)]}

@@ -395,6 +395,32 @@ cddt_status cddt_plan_capture_mcl(cddt_plan p, void* stream);
 /* Number of compute units of the current device (for tuning spaces). */
 int32_t cddt_device_cus(void);
 
+/* ---------------------------------------------------------------------------
+ * Measurement helpers for the paper's query-time benchmarks (Sec. VI: casts
+ * from a uniformly spaced grid over the (x, y, theta) states and from uniformly
+ * random states, reported per query) and its dense lookup-table comparator
+ * (Sec. II-III: the range of every discrete state stored in a 3-D table).
+ * ------------------------------------------------------------------------- */
+/* Rate of the device's constant wall clock in kHz (0 if it cannot be read). */
+int32_t cddt_device_clock_khz(void);
+/* cddt_cast (same kernels, same ranges) that also writes, per ray, the
+ * wall-clock ticks its wave spent from loading the ray to its result:
+ * ticks_out device int32[n].  Errors as cddt_cast. */
+cddt_status cddt_cast_timed(cddt_map m, const float* x, const float* y, const float* theta, int64_t n,
+                            int32_t max_range, int32_t* ranges_out, int32_t* ticks_out, void* stream);
+/* Dense table of m's casts: lut[(k * H + j) * W + i] = the cast from the centre
+ * (i + 1/2, j + 1/2) of cell (i, j) at the bin centre angle (float)(2 pi k / n),
+ * for every bin k < n (0 in occupied cells).  lut: caller-owned device
+ * uint16[n * W * H] (n * W * H * 2 bytes).  Asynchronous.  Errors: EINVAL. */
+cddt_status cddt_lut_build(cddt_map m, int32_t max_range, uint16_t* lut, void* stream);
+/* Table lookups: each query gets the same guards as a cast (0 when theta is
+ * not finite or |theta| >= 1e6, or (x, y) is off the W x H map), then the
+ * entry of its cell (floor(x), floor(y)) and bin (the cast's theta binning).
+ * ticks_out: nullable, as in cddt_cast_timed.  Asynchronous.  Errors: EINVAL. */
+cddt_status cddt_lut_cast(const uint16_t* lut, int32_t width, int32_t height, int32_t theta_bins, const float* x,
+                          const float* y, const float* theta, int64_t n, int32_t* ranges_out, int32_t* ticks_out,
+                          void* stream);
+
 /* Measurement helper, not part of the method: the band search's memory access
  * pattern without the search.  Groups of 8 lanes read whole 128-byte lines
  * (16 bytes per lane) at hashed random line indices of `buf`, keeping `depth`

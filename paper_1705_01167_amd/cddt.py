@@ -114,6 +114,10 @@ SIGNATURES = {
     "cddt_tuning_cache_get": (_i32, [_vp, _i32, C.POINTER(Tuning), C.POINTER(_i32)]),
     "cddt_batch_weight": (_i32, [_vp, _i32, _vp, _vp]),
     "cddt_batch_weight_noalloc": (_i32, [_vp, _i32, _vp, _vp]),
+    "cddt_device_clock_khz": (_i32, []),
+    "cddt_cast_timed": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp]),
+    "cddt_lut_build": (_i32, [_vp, _i32, _vp, _vp]),
+    "cddt_lut_cast": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "cddt_device_cus": (_i32, []),
     "cddt_probe_gather": (_i32, [_vp, _i64, _i32, _i32, _i32, _u32, _vp, _vp]),
     "cddt_server_create": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, C.POINTER(ServerConfig), C.POINTER(_vp)]),
@@ -272,6 +276,25 @@ class Map:
                                  _ptr(obs), _ptr(log_table), int(max_range), _ptr(logw), _ptr(rng),
                                  _stream(stream)))
         return (logw, rng) if ranges else logw
+
+    def cast_timed(self, x, y, theta, max_range: int, stream=None):
+        """(ranges, ticks): cddt_cast_timed; ticks in device wall-clock ticks (device_clock_khz per ms)."""
+        import torch
+        n = x.numel()
+        for t, nm in ((x, "x"), (y, "y"), (theta, "theta")):
+            _need(t, torch.float32, nm, n)
+        out = torch.empty(n, dtype=torch.int32, device=x.device)
+        ticks = torch.empty(n, dtype=torch.int32, device=x.device)
+        _check(lib().cddt_cast_timed(self.handle, _ptr(x), _ptr(y), _ptr(theta), n, int(max_range), _ptr(out),
+                                     _ptr(ticks), _stream(stream)))
+        return out, ticks
+
+    def lut(self, max_range: int, stream=None):
+        """Dense table [theta_bins, height, width] (uint16 stored in an int16 tensor) of casts from cell centres."""
+        import torch
+        t = torch.empty((self.theta_bins, self.height, self.width), dtype=torch.int16, device="cuda")
+        _check(lib().cddt_lut_build(self.handle, int(max_range), _ptr(t), _stream(stream)))
+        return t
 
     def update(self, xs, ys, values, stream=None):
         xs = np.ascontiguousarray(np.asarray(xs), np.int32)
@@ -454,6 +477,22 @@ def batch_weight_noalloc(filters, tuning: tuple | None = None, stream=None) -> N
     t = Tuning(*tuning) if tuning is not None else None
     _check(lib().cddt_batch_weight_noalloc(C.cast(arr, C.c_void_p), len(filters),
                                            C.byref(t) if t is not None else None, _stream(stream)))
+
+
+def lut_cast(lut, x, y, theta, timed: bool = False, stream=None):
+    """Lookups in a table from Map.lut: ranges (and ticks when timed)."""
+    import torch
+    n = x.numel()
+    th, h, w = (int(v) for v in lut.shape)
+    out = torch.empty(n, dtype=torch.int32, device=x.device)
+    ticks = torch.empty(n, dtype=torch.int32, device=x.device) if timed else None
+    _check(lib().cddt_lut_cast(_ptr(lut), w, h, th, _ptr(x), _ptr(y), _ptr(theta), n, _ptr(out), _ptr(ticks),
+                               _stream(stream)))
+    return (out, ticks) if timed else out
+
+
+def device_clock_khz() -> int:
+    return int(lib().cddt_device_clock_khz())
 
 
 def device_cus() -> int:

@@ -125,8 +125,9 @@ cddt_status finalize_bands(int32_t* hdr, int32_t* zeros, int64_t rows, hipStream
 // prune.hip: PCDDT pruning of a freshly built static structure.  Blocks.
 cddt_status prune_structure(cddt_map_s* m, hipStream_t st);
 // query.hip
+// ticks (nullable): per ray, device wall-clock ticks of its wave from load to result.
 cddt_status launch_cast(const MapDev& m, const float* x, const float* y, const float* th, int64_t n,
-                        int32_t max_range, int32_t* out, hipStream_t st);
+                        int32_t max_range, int32_t* out, hipStream_t st, int32_t* ticks = nullptr);
 cddt_status launch_weight(const FilterDev& f, hipStream_t st);
 // batch.hip.  d_counter: kBatchCounterBytes of device memory (the per-part
 // tile counters); counter_zeroed: the caller has already cleared all of it in

@@ -15,19 +15,26 @@ constexpr int kWeightK = 0;
 // the same for every lane of a wave so the cooperative search stays converged.
 // Maps without a bucket index only (those with one go to k_cast_tiles), so
 // never 16-bit lines.
+// ticks (nullable): per ray, the device wall-clock ticks its wave spent from
+// loading the ray to its result.
 __global__ __launch_bounds__(kCastThreads) void k_cast(MapDev m, const float* __restrict__ x,
                                                        const float* __restrict__ y,
                                                        const float* __restrict__ th, int64_t n,
-                                                       int32_t max_range, int32_t* __restrict__ out) {
+                                                       int32_t max_range, int32_t* __restrict__ out,
+                                                       int32_t* __restrict__ ticks) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t waves = (int64_t)gridDim.x * (kCastThreads / kWave);
   const int64_t chunks = (n + kWave - 1) / kWave;
   for (int64_t c = (int64_t)blockIdx.x * (kCastThreads / kWave) + (threadIdx.x >> 6); c < chunks; c += waves) {
+    const uint64_t t0 = ticks ? wall_clock64() : 0;
     const int64_t i = c * kWave + lane;
     const bool active = i < n;
     const float xi = active ? ldg(x + i) : 0.0f, yi = active ? ldg(y + i) : 0.0f, ti = active ? ldg(th + i) : 0.0f;
     const int32_t r = wave_cast<kCastK, false>(m, active, xi, yi, ti, max_range);
-    if (active) stg(out + i, r);
+    if (active) {
+      stg(out + i, r);
+      if (ticks) stg(ticks + i, (int32_t)(wall_clock64() - t0));
+    }
   }
 }
 
@@ -38,7 +45,8 @@ template <bool Z>
 __global__ __launch_bounds__(kCastThreads) void k_cast_tiles(MapDev m, const float* __restrict__ x,
                                                              const float* __restrict__ y,
                                                              const float* __restrict__ th, int64_t n,
-                                                             int32_t max_range, int32_t* __restrict__ out) {
+                                                             int32_t max_range, int32_t* __restrict__ out,
+                                                             int32_t* __restrict__ ticks) {
   __shared__ int2 jobs[kCastThreads / kWave][kCastQ * kWave];
   __shared__ int32_t codes[kCastThreads / kWave][kCastQ * kWave];
   __shared__ int32_t later[kCastThreads / kWave][kCastQ * kWave];
@@ -47,7 +55,7 @@ __global__ __launch_bounds__(kCastThreads) void k_cast_tiles(MapDev m, const flo
   const int64_t tiles = (n + per - 1) / per;
   const int64_t waves = (int64_t)gridDim.x * (kCastThreads / kWave);
   for (int64_t t = (int64_t)blockIdx.x * (kCastThreads / kWave) + wave; t < tiles; t += waves)
-    wave_cast_tile<kCastQ, Z>(m, x, y, th, n, t * per, max_range, out, jobs[wave], codes[wave], later[wave]);
+    wave_cast_tile<kCastQ, Z>(m, x, y, th, n, t * per, max_range, out, jobs[wave], codes[wave], later[wave], ticks);
 }
 
 // Q particles per wave through the phased tile routine (ray layouts of <= 64 rays).
@@ -78,7 +86,7 @@ __global__ __launch_bounds__(kWeightThreads) void k_weight(FilterDev f) {
 }  // namespace
 
 cddt_status launch_cast(const MapDev& m, const float* x, const float* y, const float* th, int64_t n,
-                        int32_t max_range, int32_t* out, hipStream_t st) {
+                        int32_t max_range, int32_t* out, hipStream_t st, int32_t* ticks) {
   if (n == 0) return CDDT_OK;
   if (m.bk) {
     const int64_t tiles = (n + (int64_t)kCastQ * kWave - 1) / ((int64_t)kCastQ * kWave);
@@ -86,16 +94,17 @@ cddt_status launch_cast(const MapDev& m, const float* x, const float* y, const f
     if (tb > (1 << 16)) tb = 1 << 16;
     if (m.zp16)
       hipLaunchKernelGGL(k_cast_tiles<true>, dim3((unsigned)tb), dim3(kCastThreads), 0, st, m, x, y, th, n,
-                         max_range, out);
+                         max_range, out, ticks);
     else
       hipLaunchKernelGGL(k_cast_tiles<false>, dim3((unsigned)tb), dim3(kCastThreads), 0, st, m, x, y, th, n,
-                         max_range, out);
+                         max_range, out, ticks);
     CDDT_HIP(hipGetLastError());
     return CDDT_OK;
   }
   int64_t blocks = (n + kCastThreads - 1) / kCastThreads;
   if (blocks > (1 << 16)) blocks = 1 << 16;
-  hipLaunchKernelGGL(k_cast, dim3((unsigned)blocks), dim3(kCastThreads), 0, st, m, x, y, th, n, max_range, out);
+  hipLaunchKernelGGL(k_cast, dim3((unsigned)blocks), dim3(kCastThreads), 0, st, m, x, y, th, n, max_range, out,
+                     ticks);
   CDDT_HIP(hipGetLastError());
   return CDDT_OK;
 }

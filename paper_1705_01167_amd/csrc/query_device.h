@@ -930,8 +930,10 @@ template <int Q, bool Z>
 __device__ __forceinline__ void wave_cast_tile(const MapDev& m, const float* __restrict__ x,
                                                const float* __restrict__ y, const float* __restrict__ th,
                                                int64_t n, int64_t base, int32_t max_range, int32_t* __restrict__ out,
-                                               int2* jobs, int32_t* codes, int32_t* later) {
+                                               int2* jobs, int32_t* codes, int32_t* later,
+                                               int32_t* __restrict__ ticks = nullptr) {
   const int lane = threadIdx.x & (kWave - 1);
+  const uint64_t t0 = ticks ? wall_clock64() : 0;
   int32_t njobs = 0;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -972,6 +974,7 @@ __device__ __forceinline__ void wave_cast_tile(const MapDev& m, const float* __r
         r = (code & 1) ? (pk & 0xffff) : (int32_t)((uint32_t)pk >> 16);
       }
       stg(out + i, r);
+      if (ticks) stg(ticks + i, (int32_t)(wall_clock64() - t0));
     }
   }
 }

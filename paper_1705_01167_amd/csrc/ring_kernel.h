@@ -14,8 +14,8 @@
 //
 // Exit: the watcher leaves when the host asks the kernel to drain, or when no
 // tile has been published for `watch_ticks` of the constant wall clock, and
-// then tells every wave to leave; a worker also leaves by itself after
-// `idle_ticks` without work.  A wave may leave holding an unpublished ticket;
+// then tells every wave to leave (the top bit of the device copy of the
+// count); a worker also leaves by itself after `idle_ticks` without work.  A wave may leave holding an unpublished ticket;
 // the host gives requests that an ended kernel left unfinished new tile
 // numbers before the next launch.
 //
@@ -60,11 +60,10 @@ static_assert(sizeof(RingSlot) % 64 == 0, "slots stay line-aligned");
 struct RingDev {
   unsigned long long claim;  // next tile ticket
   unsigned long long pad0[31];
-  unsigned long long dpub;   // the watcher's copy of RingCtl::pub
+  unsigned long long dpub;   // the watcher's copy of RingCtl::pub; kRingLeave set as the watcher leaves
   unsigned long long pad1[31];
-  int32_t ddrain;            // set by the watcher as it leaves
-  int32_t pad2[63];
 };
+constexpr unsigned long long kRingLeave = 1ull << 63;
 
 namespace {
 
@@ -75,7 +74,6 @@ __global__ void k_ring_reset(RingDev* rd, unsigned long long base, uint32_t* til
   if (i == 0) {
     rd->claim = base;
     rd->dpub = base;
-    rd->ddrain = 0;
   }
   for (int k = i; k < n_slots; k += gridDim.x * blockDim.x) tiles_done[k] = 0u;
 }
@@ -134,7 +132,7 @@ __device__ __forceinline__ void ring_watch(RingCtl* ctl, RingDev* rd, uint64_t w
       drain = 1;
     }
     if (drain) {
-      if (lane == 0) __hip_atomic_store(&rd->ddrain, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0) __hip_atomic_store(&rd->dpub, last | kRingLeave, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
     __builtin_amdgcn_s_sleep(4);
@@ -166,19 +164,18 @@ __global__ __launch_bounds__(kMaxBatchThreads) void k_resident(RingCtl* ctl, con
   };
   unsigned long long t = claim();
   for (;;) {
-    // wait, sleeping, until tile t is published (or leave)
+    // wait, sleeping, until tile t is published (or leave); a wave whose
+    // ticket lies far beyond the published count sleeps longer between polls
     const uint64_t since = wall_clock64();
     for (;;) {
       unsigned long long p = 0;
-      int32_t stop = 0;
-      if (lane == 0) {
-        p = __hip_atomic_load(&rd->dpub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        stop = __hip_atomic_load(&rd->ddrain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+      if (lane == 0) p = __hip_atomic_load(&rd->dpub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       p = lane0_u64(p);
+      if (p & kRingLeave) return;
       if (t < p) break;
-      if (__builtin_amdgcn_readfirstlane(stop) || wall_clock64() - since > idle_ticks) return;
-      __builtin_amdgcn_s_sleep(16);
+      if (wall_clock64() - since > idle_ticks) return;
+      const uint64_t gap = t - p;
+      for (uint64_t k = 0; k <= (gap >> 7) && k < 8; ++k) __builtin_amdgcn_s_sleep(16);
     }
     const int32_t slot =
         __builtin_amdgcn_readfirstlane(lane == 0 ? ldx<true>(tilemap + (int64_t)(t & (uint64_t)mask)) : 0);

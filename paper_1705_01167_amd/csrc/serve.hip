@@ -582,7 +582,7 @@ void ring_driver(cddt_server_s* s) {
   Resident& R = *s->res;
   std::vector<std::pair<int32_t, int64_t>> look;  // (slot, id) in flight
   std::vector<int32_t> finished;
-  double idle_since = -1.0;
+  double idle_since = -1.0, last_query = -1.0;
   for (;;) {
     // 1. locked: what is in flight
     look.clear();
@@ -601,8 +601,15 @@ void ring_driver(cddt_server_s* s) {
       r->logw.assign(lw, lw + r->n);
       finished.push_back(e.first);
     }
+    // the kernel's end: looked for while it drains, otherwise every 50 us (a
+    // runtime call costs microseconds; the kernel only ends on its own if the
+    // host stopped answering for a second)
     hipError_t ended = hipErrorNotReady;
-    if (R.running) ended = hipEventQuery(R.ev_end);
+    const double tq = s->now();
+    if (R.running && (R.drain_asked || tq - last_query > 50e-6)) {
+      ended = hipEventQuery(R.ev_end);
+      last_query = tq;
+    }
     // 3. locked: publish completions, relaunch or drain
     bool launch = false, busy = false, stop = false;
     int64_t base = 0;

@@ -18,7 +18,7 @@ import math
 import numpy as np
 
 # Workload ids used as the first SeedSequence word.
-SMALL, FLOOR, BATCHED, UPDATES, SERVING = 1, 2, 3, 4, 5
+SMALL, FLOOR, BATCHED, UPDATES, SERVING, SUITES = 1, 2, 3, 4, 5, 6
 
 # Stream ids (second SeedSequence word).
 S_MAP, S_POSES, S_TABLE, S_OBS, S_OPS, S_SPEC, S_ARRIVALS, S_MOTION = range(8)
@@ -143,6 +143,27 @@ def free_poses(rng: np.random.Generator, occ: np.ndarray, n: int):
     y = np.minimum(cj + v, np.nextafter(cj + np.float32(1), np.float32(0)))
     th = (rng.random(n) * (2.0 * math.pi)).astype(np.float32)
     return x.astype(np.float32), y.astype(np.float32), th
+
+
+def grid_states(width: int, height: int, theta_bins: int, stride: int = 1):
+    """The "grid" suite's queries (Sec. VI): every stride-th cell centre in x and y, at every bin centre angle
+    (float32 of 2 pi k / n computed in double); k slowest, then y, then x.  float32 (x, y, theta)."""
+    xs = np.arange(0, width, stride, dtype=np.float64) + 0.5
+    ys = np.arange(0, height, stride, dtype=np.float64) + 0.5
+    th = (2.0 * math.pi * np.arange(theta_bins, dtype=np.float64) / theta_bins).astype(np.float32)
+    k, j, i = np.meshgrid(np.arange(theta_bins), np.arange(ys.size), np.arange(xs.size), indexing="ij")
+    return (xs[i.ravel()].astype(np.float32), ys[j.ravel()].astype(np.float32), th[k.ravel()])
+
+
+def random_states(rng: np.random.Generator, width: int, height: int, count: int):
+    """The "random" suite's queries (Sec. VI): states uniform over [0, W) x [0, H) x [0, 2 pi), float32 (occupied
+    cells included: their casts return 0)."""
+    x = (rng.random(count) * width).astype(np.float32)
+    y = (rng.random(count) * height).astype(np.float32)
+    x = np.minimum(x, np.nextafter(np.float32(width), np.float32(0)))
+    y = np.minimum(y, np.nextafter(np.float32(height), np.float32(0)))
+    th = (rng.random(count) * (2.0 * math.pi)).astype(np.float32)
+    return x, y, th
 
 
 def ray_offsets(n_rays: int = 61, fov: float = 1.5 * math.pi) -> np.ndarray:
