@@ -674,6 +674,7 @@ def serve_at(srv, reqs, rate: float | None, seed: int):
     gaps = rng.exponential(1.0 / rate, k) if rate else np.zeros(k)
     # submitted from a native thread at the scheduled offsets (cddt_server_replay)
     ids = srv.replay([r[:5] for r in reqs], np.cumsum(gaps))
+    t_sub = srv.last_replay_seconds
     if (ids < 0).any():
         raise RuntimeError("serving: a request was refused")
     arrive, done = np.empty(k), np.empty(k)
@@ -683,7 +684,7 @@ def serve_at(srv, reqs, rate: float | None, seed: int):
     lat = done - arrive
     rays = sum(r[5] for r in reqs) * RAYS
     span = done.max() - arrive[0]
-    return {"offered_rps": rate, "completed_rps": k / span, "rays_per_s": rays / span,
+    return {"offered_rps": rate, "completed_rps": k / span, "rays_per_s": rays / span, "submit_seconds": t_sub,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "requests": k}
 
@@ -809,7 +810,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch the plan directly instead of a graph")
     ap.add_argument("--serve-requests", type=int, default=20000, help="requests per offered rate")
     ap.add_argument("--serve-budget", type=int, default=256 << 20)
-    ap.add_argument("--serve-lanes", type=str, default="4",
+    ap.add_argument("--serve-lanes", type=str, default="r",
                     help="batches in flight (streams, 1..4), or r for one resident kernel fed through a ring of "
                          "slots; the serving workload takes a comma-separated list")
     ap.add_argument("--serve-batch", type=int, default=512)

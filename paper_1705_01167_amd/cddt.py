@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import time
 
 import numpy as np
 
@@ -583,11 +584,13 @@ class Server:
                 arr[k][i] = v.ctypes.data
         at = np.ascontiguousarray(at, np.float64)
         ids = np.full(n, -1, np.int64)
+        t0 = time.perf_counter()
         _check(lib().cddt_server_replay(self.handle, n, maps.ctypes.data_as(C.c_void_p),
                                         counts.ctypes.data_as(C.c_void_p), C.cast(arr["px"], C.c_void_p),
                                         C.cast(arr["py"], C.c_void_p), C.cast(arr["pth"], C.c_void_p),
                                         C.cast(arr["obs"], C.c_void_p), at.ctypes.data_as(C.c_void_p),
                                         ids.ctypes.data_as(C.c_void_p)))
+        self.last_replay_seconds = time.perf_counter() - t0  # the native submission loop alone
         for i, rid in enumerate(ids.tolist()):
             if rid >= 0:
                 self._sizes[rid] = int(counts[i])

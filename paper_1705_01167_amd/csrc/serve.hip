@@ -123,6 +123,10 @@ struct Resident {
   int64_t pub = 0;  // tiles published (host copy of ctl->pub)
   std::vector<int32_t> free_slots;
   std::vector<Request*> owner;          // request in each slot
+  // id of the request published in each slot, -1 when none: set under the
+  // lock by publication, cleared only by the driver, read by the driver's
+  // unlocked scan of completion words
+  std::unique_ptr<std::atomic<int64_t>[]> pub_id;
   std::vector<int64_t> t_begin;         // host copy of each slot's first tile
   std::vector<int32_t> inflight;        // published slots, not finished
   std::vector<int32_t> where;           // index of each slot in inflight (-1: not there)
@@ -461,6 +465,7 @@ bool ring_publish(cddt_server_s* s, int32_t sl) {
   }
   R.pub += nt;
   __atomic_store_n(&R.ctl->pub, R.pub, __ATOMIC_RELEASE);
+  R.pub_id[sl].store(r->id, std::memory_order_release);
   return true;
 }
 
@@ -501,6 +506,7 @@ void ring_finish(cddt_server_s* s, int32_t sl, double t, bool ok = true) {
     s->stats.rays += (int64_t)r->n * s->maps[r->map].n_rays;
   }
   R.owner[sl] = nullptr;
+  R.pub_id[sl].store(-1, std::memory_order_relaxed);
   const int32_t i = R.where[sl];
   R.inflight[i] = R.inflight.back();
   R.where[R.inflight[i]] = i;
@@ -580,26 +586,22 @@ void ring_after_end(cddt_server_s* s, hipError_t st) {
 void ring_driver(cddt_server_s* s) {
   (void)hipSetDevice(s->device);
   Resident& R = *s->res;
-  std::vector<std::pair<int32_t, int64_t>> look;  // (slot, id) in flight
   std::vector<int32_t> finished;
   double idle_since = -1.0, last_query = -1.0;
   for (;;) {
-    // 1. locked: what is in flight
-    look.clear();
-    {
-      std::lock_guard<std::mutex> g(s->mu);
-      for (int32_t sl : R.inflight) look.emplace_back(sl, R.owner[sl]->id);
-    }
-    // 2. unlocked: completion words, results out of the pinned arena
+    // 1. unlocked: completion words of every published slot, results out of
+    // the pinned arena (a published slot keeps its request until this thread
+    // finishes it, so its owner is stable here)
     finished.clear();
-    for (const auto& e : look) {
-      if (__atomic_load_n(&R.done[e.first], __ATOMIC_ACQUIRE) != e.second + 1) continue;
-      Request* r = R.owner[e.first];
+    for (int32_t sl = 0; sl < R.n_slots; ++sl) {
+      const int64_t id = R.pub_id[sl].load(std::memory_order_acquire);
+      if (id < 0 || __atomic_load_n(&R.done[sl], __ATOMIC_ACQUIRE) != id + 1) continue;
+      Request* r = R.owner[sl];
       const ServedMap& m = s->maps[r->map];
-      const float* lw = (const float*)(R.arena + (size_t)e.first * R.slot_bytes + align_up((size_t)r->n * 12) +
+      const float* lw = (const float*)(R.arena + (size_t)sl * R.slot_bytes + align_up((size_t)r->n * 12) +
                                        align_up((size_t)m.n_rays * 4));
       r->logw.assign(lw, lw + r->n);
-      finished.push_back(e.first);
+      finished.push_back(sl);
     }
     // the kernel's end: looked for while it drains, otherwise every 50 us (a
     // runtime call costs microseconds; the kernel only ends on its own if the
@@ -610,7 +612,7 @@ void ring_driver(cddt_server_s* s) {
       ended = hipEventQuery(R.ev_end);
       last_query = tq;
     }
-    // 3. locked: publish completions, relaunch or drain
+    // 2. locked: publish completions, relaunch or drain
     bool launch = false, busy = false, stop = false;
     int64_t base = 0;
     {
@@ -653,7 +655,7 @@ void ring_driver(cddt_server_s* s) {
       ring_after_end(s, hipErrorLaunchFailure);
       continue;
     }
-    // 4. spin while a kernel is on the device or work waits; block when idle
+    // 3. spin while a kernel is on the device or work waits; block when idle
     if (R.running || busy) {
       std::this_thread::yield();
       continue;
@@ -780,6 +782,8 @@ cddt_status create_resident(cddt_server_s* s, const cddt_server_config& c) {
   std::memset(R.tilemap, 0xff, 4 * (size_t)R.tiles);  // -1: no slot
   std::memset(R.done, 0, 8 * (size_t)R.n_slots);
   R.owner.assign(R.n_slots, nullptr);
+  R.pub_id.reset(new std::atomic<int64_t>[R.n_slots]);
+  for (int32_t k = 0; k < R.n_slots; ++k) R.pub_id[k].store(-1, std::memory_order_relaxed);
   R.t_begin.assign(R.n_slots, 0);
   R.where.assign(R.n_slots, -1);
   for (int32_t k = R.n_slots - 1; k >= 0; --k) R.free_slots.push_back(k);
