@@ -15,7 +15,8 @@ Other workloads (each prints its own JSON line): `small` (256^2 rectangle map,
 fused weights), `updates` (4000^2 floor, 1000 toggles + 1M particles x 61
 casts per step), `serving` (8 resident maps, Poisson arrivals swept over load),
 `suites` (the paper's grid and random query suites: per-query time distribution
-and rays/s on CDDT, PCDDT and the dense lookup-table comparator), `probe`
+and rays/s on CDDT, PCDDT, the dense lookup-table comparator and the cell-walk
+comparator), `probe`
 (random-gather bandwidth only).
 """
 from __future__ import annotations
@@ -533,6 +534,18 @@ def run_suites(args) -> dict:
             log(f"bench: suites {name} / table / {sname}: {res[sname]}")
         entry["lut"] = res
         del lut
+        # the cell-walk comparator (exact ray, theta not binned) on the same grid
+        res = {}
+        for sname, (x, y, th) in dev.items():
+            q = x.numel()
+            ms = time_queries(lambda st: m.march(x, y, th, MAX_RANGE, stream=st))
+            rg, ticks = m.march(x, y, th, MAX_RANGE, timed=True)
+            torch.cuda.synchronize()
+            res[sname] = {"rays_per_s": q / (ms * 1e-3), "ns_per_query_amortized": ms * 1e6 / q, "kernel_ms": ms,
+                          "per_query": per_query_stats(ticks, khz, 13 + mi),
+                          "within_one_cell_of_cddt": float(((rg - plain_ranges[sname]).abs() <= 1).double().mean())}
+            log(f"bench: suites {name} / cell walk / {sname}: {res[sname]}")
+        entry["cell_walk"] = res
         m.close()
         # the CPU oracle (plain C++ CDDT) per query on one thread, a sample of each suite
         if not args.no_cpu:

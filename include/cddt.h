@@ -420,6 +420,17 @@ cddt_status cddt_lut_build(cddt_map m, int32_t max_range, uint16_t* lut, void* s
 cddt_status cddt_lut_cast(const uint16_t* lut, int32_t width, int32_t height, int32_t theta_bins, const float* x,
                           const float* y, const float* theta, int64_t n, int32_t* ranges_out, int32_t* ticks_out,
                           void* stream);
+/* The cell-walk comparator (Bresenham's line family, Sec. II; here the exact
+ * traversal of Amanatides and Woo): from (x, y) along (cos theta, sin theta),
+ * theta not binned, the cells in the order the exact ray enters them (ties
+ * step in y) are read from m's occupancy grid until the first occupied one;
+ * the range is its entry distance rounded half up and capped at max_range
+ * (max_range when the ray leaves the map first), 0 under the cast's guards.
+ * Double precision; sin and cos by range reduction and a Taylor series in a
+ * fixed order of operations.  ticks_out nullable, as in cddt_cast_timed.
+ * Asynchronous.  Errors: EINVAL. */
+cddt_status cddt_march_cast(cddt_map m, const float* x, const float* y, const float* theta, int64_t n,
+                            int32_t max_range, int32_t* ranges_out, int32_t* ticks_out, void* stream);
 
 /* Measurement helper, not part of the method: the band search's memory access
  * pattern without the search.  Groups of 8 lanes read whole 128-byte lines

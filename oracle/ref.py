@@ -213,3 +213,29 @@ def resample(logw, u: int, px, py, pth):
     if r != 0:
         raise ValueError("resample: n must be in 0..2^20")
     return idx, out[0], out[1], out[2]
+
+
+# ---------------------------------------------------------------------------
+# The cell-walk comparator (Sec. II: Bresenham's line family; here the exact
+# traversal of Amanatides and Woo), a comparison system, not CDDT
+# ---------------------------------------------------------------------------
+def march_cast(occ, x, y, theta, max_range: int) -> int:
+    """Range of a ray walked cell by cell along (cos theta, sin theta), theta not binned: the entry distance into
+    the first occupied cell the exact ray enters (exact.grid_traversal, ties step in y), rounded half up and capped
+    at max_range; max_range if the ray leaves the map first; 0 for a non-finite or |theta| >= 1e6 angle, a position
+    off the map, or a position in an occupied cell.  sin and cos from det_sincos (fixed operation order)."""
+    import math
+    from oracle import exact
+    occ = np.asarray(occ)
+    h, w = occ.shape
+    xf, yf, th = np.float32(x), np.float32(y), np.float32(theta)
+    if not (abs(float(th)) < 1e6) or not (0.0 <= xf < w and 0.0 <= yf < h):
+        return 0
+    px, py = float(xf), float(yf)
+    if occ[int(math.floor(py)), int(math.floor(px))]:
+        return 0
+    s, c = det_sincos(float(th))
+    hit = exact.grid_traversal(occ, px, py, c, s)
+    if hit is None:
+        return int(max_range)
+    return min(int(max_range), int(math.floor(hit[0] + 0.5)))

@@ -119,6 +119,7 @@ SIGNATURES = {
     "cddt_cast_timed": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp]),
     "cddt_lut_build": (_i32, [_vp, _i32, _vp, _vp]),
     "cddt_lut_cast": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "cddt_march_cast": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp]),
     "cddt_device_cus": (_i32, []),
     "cddt_probe_gather": (_i32, [_vp, _i64, _i32, _i32, _i32, _u32, _vp, _vp]),
     "cddt_server_create": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, C.POINTER(ServerConfig), C.POINTER(_vp)]),
@@ -289,6 +290,16 @@ class Map:
         _check(lib().cddt_cast_timed(self.handle, _ptr(x), _ptr(y), _ptr(theta), n, int(max_range), _ptr(out),
                                      _ptr(ticks), _stream(stream)))
         return out, ticks
+
+    def march(self, x, y, theta, max_range: int, timed: bool = False, stream=None):
+        """The cell-walk comparator (cddt_march_cast) on this map's grid: ranges (and ticks when timed)."""
+        import torch
+        n = x.numel()
+        out = torch.empty(n, dtype=torch.int32, device=x.device)
+        ticks = torch.empty(n, dtype=torch.int32, device=x.device) if timed else None
+        _check(lib().cddt_march_cast(self.handle, _ptr(x), _ptr(y), _ptr(theta), n, int(max_range), _ptr(out),
+                                     _ptr(ticks), _stream(stream)))
+        return (out, ticks) if timed else out
 
     def lut(self, max_range: int, stream=None):
         """Dense table [theta_bins, height, width] (uint16 stored in an int16 tensor) of casts from cell centres."""

@@ -1,7 +1,9 @@
 // Measurement helpers for the paper's query-time suites (Sec. VI: casts from
 // a uniformly spaced grid of states and from uniformly random states, timed
-// per query) and its dense lookup-table comparator (Sec. II-III: the range of
-// every discrete state stored in a 3-D table).
+// per query) and two of its comparators (Sec. II-III): the dense lookup table
+// (the range of every discrete state stored in a 3-D table) and a cell-by-cell
+// walk along the exact ray (the family of Bresenham's line; here the exact
+// traversal of Amanatides and Woo).
 //
 // cddt_cast_timed runs the same kernels as cddt_cast and also records, per
 // ray, the device wall-clock ticks its wave spent on it.  The table holds, for
@@ -12,6 +14,7 @@
 #include <algorithm>
 
 #include "cddt_common.h"
+#include "det_math.h"
 #include "query_device.h"
 
 namespace cddt {
@@ -57,6 +60,63 @@ __global__ __launch_bounds__(kLutThreads) void k_lut_cast(const uint16_t* __rest
       const int32_t k = theta_bin(ti, k_scale, n);
       r = ldg(lut + ((int64_t)k * h + j) * w + i);
     }
+    stg(out + q, r);
+    if (ticks) stg(ticks + q, (int32_t)(wall_clock64() - t0));
+  }
+}
+
+// Cell walk: from the query position along (cos theta, sin theta) (theta not
+// binned; sin and cos from det_math.h), stepping from cell to cell in the
+// order the exact ray enters them (ties step in y), the range is the entry
+// distance into the first occupied cell, rounded half up and capped at
+// max_range, or max_range when the ray leaves the map first; the cast's
+// guards give 0 (including a query in an occupied cell).  In double, every
+// operation as written.
+__device__ int32_t march_one(const uint8_t* __restrict__ occ, int32_t w, int32_t h, float x, float y, float th,
+                             int32_t max_range) {
+  if (!(fabsf(th) < 1e6f) || !(x >= 0.0f && x < (float)w && y >= 0.0f && y < (float)h)) return 0;
+  const double px = (double)x, py = (double)y;
+  int32_t i = (int32_t)floor(px), j = (int32_t)floor(py);
+  if (ldg(occ + (size_t)j * w + i) != 0) return 0;
+  double dy, dx;
+  sin_cos((double)th, dy, dx);
+  const int32_t si = dx > 0.0 ? 1 : -1, sj = dy > 0.0 ? 1 : -1;
+  const double inf = __builtin_huge_val();
+  double tmx = inf, tdx = inf, tmy = inf, tdy = inf;
+  if (dx != 0.0) {
+    tmx = ((double)(dx > 0.0 ? i + 1 : i) - px) / dx;
+    tdx = fabs(1.0 / dx);
+  }
+  if (dy != 0.0) {
+    tmy = ((double)(dy > 0.0 ? j + 1 : j) - py) / dy;
+    tdy = fabs(1.0 / dy);
+  }
+  const double limit = (double)max_range + 0.5;  // entries at or beyond round to max_range or more
+  for (;;) {
+    double t;
+    if (tmx < tmy) {
+      t = tmx;
+      i += si;
+      tmx += tdx;
+    } else {
+      t = tmy;
+      j += sj;
+      tmy += tdy;
+    }
+    if (t >= limit || i < 0 || i >= w || j < 0 || j >= h) return max_range;
+    if (ldg(occ + (size_t)j * w + i) != 0) return (int32_t)floor(t + 0.5);
+  }
+}
+
+__global__ __launch_bounds__(kLutThreads) void k_march_cast(const uint8_t* __restrict__ occ, int32_t w, int32_t h,
+                                                            const float* __restrict__ x, const float* __restrict__ y,
+                                                            const float* __restrict__ th, int64_t count,
+                                                            int32_t max_range, int32_t* __restrict__ out,
+                                                            int32_t* __restrict__ ticks) {
+  const int64_t stride = (int64_t)gridDim.x * kLutThreads;
+  for (int64_t q = (int64_t)blockIdx.x * kLutThreads + threadIdx.x; q < count; q += stride) {
+    const uint64_t t0 = ticks ? wall_clock64() : 0;
+    const int32_t r = march_one(occ, w, h, ldg(x + q), ldg(y + q), ldg(th + q), max_range);
     stg(out + q, r);
     if (ticks) stg(ticks + q, (int32_t)(wall_clock64() - t0));
   }
@@ -116,6 +176,20 @@ cddt_status cddt_lut_cast(const uint16_t* lut, int32_t width, int32_t height, in
   const int64_t blocks = std::min<int64_t>((n + kLutThreads - 1) / kLutThreads, 1 << 16);
   hipLaunchKernelGGL(k_lut_cast, dim3((unsigned)blocks), dim3(kLutThreads), 0, (hipStream_t)stream, lut, width,
                      height, theta_bins, k_scale, x, y, theta, n, ranges_out, ticks_out);
+  CDDT_HIP(hipGetLastError());
+  return CDDT_OK;
+}
+
+cddt_status cddt_march_cast(cddt_map m, const float* x, const float* y, const float* theta, int64_t n,
+                            int32_t max_range, int32_t* ranges_out, int32_t* ticks_out, void* stream) {
+  if (!m) return fail(CDDT_EINVAL, "cddt_march_cast: map is NULL");
+  if (n < 0) return fail(CDDT_EINVAL, "cddt_march_cast: n < 0");
+  if (max_range < 0 || max_range > 65535) return fail(CDDT_EINVAL, "cddt_march_cast: max_range must be in 0..65535");
+  if (n == 0) return CDDT_OK;
+  if (!x || !y || !theta || !ranges_out) return fail(CDDT_EINVAL, "cddt_march_cast: NULL array");
+  const int64_t blocks = std::min<int64_t>((n + kLutThreads - 1) / kLutThreads, 1 << 16);
+  hipLaunchKernelGGL(k_march_cast, dim3((unsigned)blocks), dim3(kLutThreads), 0, (hipStream_t)stream, m->d_occ, m->w,
+                     m->h, x, y, theta, n, max_range, ranges_out, ticks_out);
   CDDT_HIP(hipGetLastError());
   return CDDT_OK;
 }

@@ -7,7 +7,9 @@ and from uniformly random states) and the dense lookup-table comparator:
 - the table built on the GPU equals the oracle's casts from every cell centre
   at every bin centre angle (for the pruned map too: pruning is exact from grid
   states, Sec. IV-C), and table lookups equal a gather from it by the query's
-  cell and the oracle's binning.
+  cell and the oracle's binning;
+- the cell-walk comparator equals the oracle's walk (exact.grid_traversal with
+  the oracle's own sin and cos) query by query.
 """
 import sys
 
@@ -88,3 +90,24 @@ def test_suites_and_table_against_oracle(mi):
     assert (ticks.cpu().numpy() >= 0).all()
     rm.close()
     _say(f"suites {kind} {w}x{h} n={n}: {gx.size} grid and {rx.size} random casts exact on {len(LAYOUTS)} layouts")
+
+
+@pytest.mark.parametrize("mi", range(len(MAPS)))
+def test_march_comparator_against_oracle(mi):
+    from paper_1705_01167_amd import cddt
+    kind, w, h, n = MAPS[mi]
+    occ = _occ(kind, w, h, mi)
+    gm = cddt.Map(_dev(occ), n)
+    x, y, t = wl.random_states(wl.rng_for(wl.SUITES, wl.S_OBS, mi), w, h, 3000)
+    gx, gy, gt = wl.grid_states(w, h, n, stride=max(1, w // 12))
+    x = np.concatenate([x, gx, np.array([-1.0, 1.5, 1.5], np.float32)])
+    y = np.concatenate([y, gy, np.array([1.5, 1.5, 1.5], np.float32)])
+    t = np.concatenate([t, gt, np.array([0.0, np.inf, -3e6], np.float32)])
+    got, ticks = gm.march(_dev(x), _dev(y), _dev(t), M, timed=True)
+    got = got.cpu().numpy()
+    want = np.array([oref.march_cast(occ, x[q], y[q], t[q], M) for q in range(x.size)], np.int32)
+    bad = np.flatnonzero(got != want)
+    assert bad.size == 0, f"{kind}: {bad.size} walks differ, first {[(x[q], y[q], t[q], got[q], want[q]) for q in bad[:3]]}"
+    assert (ticks.cpu().numpy() >= 0).all()
+    gm.close()
+    _say(f"march {kind}: {x.size} walks exact")
