@@ -80,28 +80,36 @@ __host__ __device__ __forceinline__ uint32_t key_capacity(uint32_t len, bool no_
   return round_line((uint64_t)len + (no_slack ? 0u : 8u + (len >> 3)));
 }
 
-// Sample levels and header top level of one band from its sorted keys; all 64
-// lanes of the calling wave take part.  Used after construction and after an
-// update changes the band.
+// Sample levels and header top level of a band whose region starts at
+// `start` with capacity `cap`, from its len sorted keys at src (the region
+// itself, or a copy in LDS); all 64 lanes of the calling wave take part.
+__device__ __forceinline__ void band_levels(int32_t* __restrict__ hdr_node, int32_t* __restrict__ zeros,
+                                            uint32_t start, int32_t len, uint32_t cap, const int32_t* src) {
+  const int lane = threadIdx.x & 63;
+  const int T = top_level(len);
+  for (int t = 1; t < T; ++t) {
+    const int32_t nt = level_count(len, t);
+    int32_t* lv = zeros + level_base(start, cap, t);
+    for (int32_t k = lane; k < (int32_t)round_line((uint64_t)nt); k += 64)
+      lv[k] = k < nt ? src[(int64_t)k << (kLineShift * t)] : INT_MAX;
+  }
+  const int32_t nT = level_count(len, T);
+  if (lane >= kHeaderWords && lane < kNodeInts) {
+    const int32_t u = lane - kHeaderWords;
+    hdr_node[lane] = u < nT ? src[(int64_t)u << (kLineShift * T)] : INT_MAX;
+  }
+}
+
+// Padding, sample levels and header top level of one band from its sorted
+// keys in place; all 64 lanes of the calling wave take part.  Used after
+// construction and after an update changes the band in place.
 __device__ inline void finalize_band(int32_t* __restrict__ hdr_node, int32_t* __restrict__ zeros) {
   const int lane = threadIdx.x & 63;
   const uint32_t start = (uint32_t)hdr_node[0];
   const int32_t len = hdr_node[1];
   const uint32_t cap = (uint32_t)hdr_node[2];
-  const int T = top_level(len);
-  const int32_t* keys = zeros + start;
   for (int32_t k = len + lane; k < (int32_t)round_line((uint64_t)len); k += 64) zeros[start + k] = INT_MAX;
-  for (int t = 1; t < T; ++t) {
-    const int32_t nt = level_count(len, t);
-    int32_t* lv = zeros + level_base(start, cap, t);
-    for (int32_t k = lane; k < (int32_t)round_line((uint64_t)nt); k += 64)
-      lv[k] = k < nt ? keys[(int64_t)k << (kLineShift * t)] : INT_MAX;
-  }
-  const int32_t nT = level_count(len, T);
-  if (lane >= kHeaderWords && lane < kNodeInts) {
-    const int32_t u = lane - kHeaderWords;
-    hdr_node[lane] = u < nT ? keys[(int64_t)u << (kLineShift * T)] : INT_MAX;
-  }
+  band_levels(hdr_node, zeros, start, len, cap, zeros + start);
 }
 
 }  // namespace cddt

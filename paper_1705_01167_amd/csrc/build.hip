@@ -24,6 +24,7 @@
 #include <climits>
 
 #include "band_layout.h"
+#include "bucket_lines.h"
 #include "cddt_common.h"
 
 namespace cddt {
@@ -115,124 +116,35 @@ __global__ void k_project(const SliceDev* __restrict__ slices, const uint32_t* _
   }
 }
 
-// Bucket index fill: one wave per band.  first[b] (LDS) = index of the band's
-// first key at or after the start of bucket b, b = 0..nbk: a pass over the
-// keys in order (coalesced) lets key k claim the buckets after its
-// predecessor's bucket up to its own; then one lane per bucket (64 buckets per
-// pass) writes the bucket's whole line from first[b], first[b + 1].  Band t of
-// the list is rows_list[t] (band t when rows_list is null).  With `partial`
-// the old line is read first so that the overflow counter stays exact.
-// Buckets per band are at most (16384 sqrt(2) cells) / 2^4 + 1 = 1449: the
-// longest slice extent of the largest map at the narrowest bucket width.
-constexpr int kFillMaxBuckets = 1456;
+// Bucket index fill after a build: one wave per band, every line of the band
+// (bucket_lines.h).
 constexpr int kFillThreads = 256;
-// LDS words of one wave's tables: first[0..nbk] and one mark byte per bucket.
-// Sized per map, so that maps with few buckets per band keep more waves per CU.
-__host__ __device__ constexpr int32_t fill_wave_words(int32_t nbk) { return (nbk + 1) + (nbk + 3) / 4; }
+// LDS words of one wave's tables: first[0..nbk].
+__host__ __device__ constexpr int32_t fill_wave_words(int32_t nbk) { return nbk + 1; }
 static_assert((kFillThreads / 64) * fill_wave_words(kFillMaxBuckets) * 4 <= 65536, "fill tables fit in LDS");
 
-// The slice of a band: the last s with row_start[s] <= band (row_start rises
-// from row_start[0] = 0).  A 64-ary search by the whole wave, one candidate
-// per lane and the ballot's count as the answer: two dependent loads instead
-// of log2(half).  `band` is the same on every lane.
-static_assert(kMaxBins / 2 <= 64 * 64, "two levels of 64 candidates cover every slice count");
-__device__ __forceinline__ int32_t band_slice(const int32_t* __restrict__ row_start, int32_t half, uint32_t band) {
-  const int lane = threadIdx.x & 63;
-  const int32_t stride = (half + 63) >> 6;
-  int32_t s = lane * stride;
-  uint64_t m = __ballot(s < half && (uint32_t)row_start[s] <= band);
-  int32_t lo = (__popcll(m) - 1) * stride;
-  if (stride > 1) {
-    s = lo + lane;
-    m = __ballot(lane < stride && s < half && (uint32_t)row_start[s] <= band);
-    lo += __popcll(m) - 1;
-  }
-  return lo;
-}
-__global__ __launch_bounds__(kFillThreads) void k_bucket_fill(
-    const int32_t* __restrict__ hdr, const int32_t* __restrict__ zeros, const SliceDev* __restrict__ slices,
-    const int32_t* __restrict__ row_start, int32_t half, int32_t shift, int32_t nbk, int32_t* __restrict__ bk,
-    const uint32_t* __restrict__ rows_list, uint64_t n_bands, unsigned long long* __restrict__ over, int partial,
-    int zp16, const uint32_t* __restrict__ rec_off, const int2* __restrict__ recs, uint32_t n_recs) {
+__global__ __launch_bounds__(kFillThreads) void k_bucket_fill(const int32_t* __restrict__ hdr,
+                                                              const int32_t* __restrict__ zeros,
+                                                              const SliceDev* __restrict__ slices,
+                                                              const int32_t* __restrict__ row_start, int32_t half,
+                                                              int32_t shift, int32_t nbk, int32_t* __restrict__ bk,
+                                                              uint64_t n_bands, unsigned long long* __restrict__ over,
+                                                              int zp16) {
   extern __shared__ int32_t fill_lds[];
   int32_t* first = fill_lds + (threadIdx.x >> 6) * fill_wave_words(nbk);
-  uint8_t* mark = reinterpret_cast<uint8_t*>(first + nbk + 1);
-  const int lane = threadIdx.x & 63;
   const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t t = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < n_bands; t += n_waves) {
-    const uint32_t band = rows_list ? rows_list[t] : (uint32_t)t;
-    const int32_t zlo = slices[band_slice(row_start, half, band)].zlo;
+  int over_n = 0;
+  for (uint64_t band = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; band < n_bands; band += n_waves) {
+    const int32_t zlo = slices[band_slice(row_start, half, (uint32_t)band)].zlo;
     const int32_t* node = hdr + (int64_t)band * kNodeInts;
     const int32_t* keys = zeros + (uint32_t)node[0];
     const int32_t len = node[1];
-    for (int32_t b = lane; b <= nbk; b += 64) first[b] = len;
-    __threadfence_block();
-    for (int32_t k0 = 0; k0 < len; k0 += 64) {
-      const int32_t k = k0 + lane;
-      if (k < len) {
-        const int64_t bk_k = min(((int64_t)keys[k] - zlo) >> shift, (int64_t)nbk);
-        const int64_t bk_p = k > 0 ? min(((int64_t)keys[k - 1] - zlo) >> shift, (int64_t)nbk) : -1;
-        for (int64_t b = bk_p + 1; b <= bk_k; ++b) first[b] = k;  // key k is the first at or after bucket b
-      }
-    }
-    __threadfence_block();
-    if (recs) {  // mark the buckets the band's edits can change
-      for (int32_t b = lane; b < nbk; b += 64) mark[b] = 0;
-      __threadfence_block();
-      const uint32_t r0 = rec_off[t], r1 = t + 1 < n_bands ? rec_off[t + 1] : n_recs;
-      for (uint32_t r = r0 + lane; r < r1; r += 64) {
-        const int32_t bz = (int32_t)min(max(((int64_t)recs[r].y - zlo) >> shift, (int64_t)0), (int64_t)nbk - 1);
-        mark[bz] = 1;
-        for (int32_t b = bz - 1; b >= 0; --b) {  // buckets that carry this point as their next key
-          mark[b] = 1;
-          if (first[b] < first[b + 1]) break;
-        }
-        for (int32_t b = bz + 1; b < nbk; ++b) {  // buckets that carry it as their previous key
-          mark[b] = 1;
-          if (first[b] < first[b + 1]) break;
-        }
-      }
-      __threadfence_block();
-    }
-    int over_delta = 0;
-    for (int32_t b0 = 0; b0 < nbk; b0 += 64) {
-      const int32_t b = b0 + lane;
-      if (b >= nbk || (recs && !mark[b])) continue;
-      const int32_t i0 = first[b], i1 = first[b + 1];
-      const int32_t n_in = i1 - i0;
-      int4* line = reinterpret_cast<int4*>(bk + ((int64_t)band * nbk + b) * kLineInts);
-      const int old_over = partial ? (reinterpret_cast<const int32_t*>(line)[0] == kBucketOverflow) : 0;
-      const int cap_keys = zp16 ? kBucketKeys16 : kBucketKeys;
-      if (n_in > cap_keys) {
-        line[0] = make_int4(kBucketOverflow, zlo, 0, 0);
-#pragma unroll
-        for (int q = 1; q < 8; ++q) line[q] = make_int4(0, 0, 0, 0);
-      } else if (zp16) {  // bin centres of the neighbours; bins relative to the bucket's first bin
-        const int32_t base = b << (shift - kBinShift);
-        int32_t e[32];
-        e[0] = i0 > 0 ? ((keys[i0 - 1] - zlo) >> kBinShift) * 8192 + 4096 : INT_MIN;
-        e[1] = i1 < len ? ((keys[i1] - zlo) >> kBinShift) * 8192 + 4096 : INT_MAX;
-#pragma unroll
-        for (int k = 0; k < kBucketKeys16 / 2; ++k) {
-          const int32_t lo = 2 * k < n_in ? ((keys[i0 + 2 * k] - zlo) >> kBinShift) - base : 0xffff;
-          const int32_t hi = 2 * k + 1 < n_in ? ((keys[i0 + 2 * k + 1] - zlo) >> kBinShift) - base : 0xffff;
-          e[2 + k] = (int32_t)(((uint32_t)hi << 16) | (uint32_t)lo);
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) line[q] = make_int4(e[4 * q], e[4 * q + 1], e[4 * q + 2], e[4 * q + 3]);
-      } else {
-        int32_t e[32];
-        e[0] = i0 > 0 ? keys[i0 - 1] - zlo : INT_MIN;
-        e[1] = i1 < len ? keys[i1] - zlo : INT_MAX;
-#pragma unroll
-        for (int k = 0; k < kBucketKeys; ++k) e[2 + k] = k < n_in ? keys[i0 + k] - zlo : INT_MAX;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) line[q] = make_int4(e[4 * q], e[4 * q + 1], e[4 * q + 2], e[4 * q + 3]);
-      }
-      over_delta += (n_in > cap_keys ? 1 : 0) - old_over;
-    }
-    if (over_delta != 0) atomicAdd(over, (unsigned long long)(long long)over_delta);
+    bucket_firsts(keys, len, zlo, shift, nbk, first);
+    int32_t* lines = bk + (int64_t)band * nbk * kLineInts;
+    over_n += write_bucket_lines<true>(keys, len, zlo, shift, nbk, first, nullptr, nullptr, lines, zp16);
+    wave_fence();  // first[] is rewritten for the wave's next band
   }
+  if (over_n != 0) atomicAdd(over, (unsigned long long)over_n);
 }
 
 __device__ __forceinline__ uint64_t region_of(uint32_t len, int no_slack) {
@@ -575,7 +487,7 @@ cddt_status build_structure(cddt_map_s* m, hipStream_t st) {
                      (const uint32_t*)big_t.p, (const BuildCounters*)ctr);
   CDDT_TRY(finalize_bands(m->d_hdr, m->d_zeros, R, st));
   if (m->flags & CDDT_FLAG_PRUNE) CDDT_TRY(prune_structure(m, st));
-  if (m->d_bk) return fill_buckets(m, nullptr, R, st);
+  if (m->d_bk) return fill_buckets(m, st);
   return CDDT_OK;
 }
 
@@ -611,19 +523,17 @@ cddt_status finalize_bands(int32_t* hdr, int32_t* zeros, int64_t rows, hipStream
   return CDDT_OK;
 }
 
-cddt_status fill_buckets(cddt_map_s* m, const uint32_t* rows_list, int64_t n_rows, hipStream_t st,
-                         const uint32_t* rec_off, const int2* recs, uint32_t n_recs) {
+cddt_status fill_buckets(cddt_map_s* m, hipStream_t st) {
+  const int64_t n_rows = m->rows;
   if (!m->d_bk || n_rows <= 0) return CDDT_OK;
   if (m->nbk > kFillMaxBuckets) return fail(CDDT_EINTERNAL, "bucket fill: more buckets per band than planned");
-  const int partial = rows_list ? 1 : 0;
-  if (!partial) CDDT_HIP(hipMemsetAsync(m->d_bk_over, 0, 8, st));
+  CDDT_HIP(hipMemsetAsync(m->d_bk_over, 0, 8, st));
   const uint64_t blocks = std::min<uint64_t>(((uint64_t)n_rows + 3) / 4, 1u << 16);  // 4 bands per block
   const size_t lds = (size_t)(kFillThreads / 64) * fill_wave_words(m->nbk) * sizeof(int32_t);
   hipLaunchKernelGGL(k_bucket_fill, dim3((unsigned)std::max<uint64_t>(blocks, 1)), dim3(kFillThreads), lds, st,
                      (const int32_t*)m->d_hdr, (const int32_t*)m->d_zeros, (const SliceDev*)m->d_slices,
-                     (const int32_t*)m->d_row_start, m->half, 16 + m->blog2, m->nbk, m->d_bk, rows_list,
-                     (uint64_t)n_rows, m->d_bk_over, partial, (m->flags & CDDT_FLAG_ZP16) ? 1 : 0,
-                     rows_list ? rec_off : nullptr, rows_list ? recs : nullptr, n_recs);
+                     (const int32_t*)m->d_row_start, m->half, 16 + m->blog2, m->nbk, m->d_bk, (uint64_t)n_rows,
+                     m->d_bk_over, (m->flags & CDDT_FLAG_ZP16) ? 1 : 0);
   CDDT_HIP(hipGetLastError());
   unsigned long long over = 0;
   CDDT_HIP(hipMemcpyAsync(&over, m->d_bk_over, 8, hipMemcpyDeviceToHost, st));

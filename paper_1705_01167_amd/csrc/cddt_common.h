@@ -104,15 +104,10 @@ struct cddt_map_s {
 
 namespace cddt {
 // build.hip.  build_structure also fills the bucket index when the map has
-// one; fill_buckets refreshes the buckets of the listed bands (all bands when
-// rows_list is null) and blocks.
+// one; fill_buckets writes every band's bucket lines and the overflow count,
+// and blocks.  (An incremental update rewrites its edited bands' lines itself.)
 cddt_status build_structure(cddt_map_s* m, hipStream_t st);
-// With update records (rec_off[t] = first record of listed band t, recs[i] =
-// {band | removal bit, zero point}, n_recs records in all), only the buckets
-// an edit can change are rewritten: the edited point's bucket and, on each
-// side, the empty buckets up to the first one that holds a key.
-cddt_status fill_buckets(cddt_map_s* m, const uint32_t* rows_list, int64_t n_rows, hipStream_t st,
-                         const uint32_t* rec_off = nullptr, const int2* recs = nullptr, uint32_t n_recs = 0);
+cddt_status fill_buckets(cddt_map_s* m, hipStream_t st);
 void free_structure(cddt_map_s* m);
 cddt_status refresh_stats(cddt_map_s* m, hipStream_t st);
 // Band layout from per-band lengths cnt[rows] (reset to 0 on return): header
