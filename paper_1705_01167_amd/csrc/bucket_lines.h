@@ -68,6 +68,29 @@ __device__ __forceinline__ void bucket_firsts(const int32_t* keys, int32_t len, 
   wave_fence();
 }
 
+// first[0..nbk] of keys[0, len) in LDS, 16-byte aligned: each lane takes four
+// consecutive keys.
+__device__ __forceinline__ void bucket_firsts4(const int32_t* keys, int32_t len, int32_t zlo, int32_t shift,
+                                               int32_t nbk, int32_t* first) {
+  const int lane = threadIdx.x & 63;
+  for (int32_t b = lane; b <= nbk; b += 64) first[b] = len;
+  wave_fence();
+  for (int32_t k0 = 4 * lane; k0 < len; k0 += 256) {
+    const int4 v = *reinterpret_cast<const int4*>(keys + k0);
+    int32_t bp = k0 > 0 ? bucket_of(keys[k0 - 1], zlo, shift, nbk) : -1;
+    const int32_t kv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (k0 + c < len) {
+        const int32_t bk = bucket_of(kv[c], zlo, shift, nbk);
+        for (int32_t b = bp + 1; b <= bk; ++b) first[b] = k0 + c;
+        bp = bk;
+      }
+    }
+  }
+  wave_fence();
+}
+
 // Marks the buckets whose line inserting or removing zero point z can change
 // (first[] of the edited keys): z's bucket and, on each side, the empty
 // buckets up to and including the first one that holds a key (they carry z as

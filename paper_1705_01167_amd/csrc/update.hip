@@ -404,9 +404,10 @@ struct EditBuckets {
 // records are edited in an LDS copy.  Per wave: the copy, first[] after and
 // (for bands edited in place) before the edit, one mark byte per bucket.
 constexpr int kStageKeys = 1024;
-__host__ __device__ constexpr int32_t edit_wave_words(int32_t nbk) {
-  return kStageKeys + (nbk > 0 ? 2 * (nbk + 1) + (nbk + 3) / 4 : 0);
+__host__ __device__ constexpr int32_t edit_wave_words(int32_t nbk) {  // a multiple of 4 (16-byte groups)
+  return (kStageKeys + (nbk > 0 ? 2 * (nbk + 1) + (nbk + 3) / 4 : 0) + 3) & ~3;
 }
+static_assert(kStageKeys == 4 * 4 * 64, "a staged band is four 16-byte groups per lane");
 
 // One wave per touched band: its records are applied, removals first (each
 // must find its key), then inserts after any equal keys.  A band whose new
@@ -417,37 +418,60 @@ __host__ __device__ constexpr int32_t edit_wave_words(int32_t nbk) {
 // that the edits can change are rewritten (bucket_lines.h); the old lines'
 // overflow count follows from the records (LDS copy) or from first[] before
 // the edit (in place).
-__global__ __launch_bounds__(256) void k_edit_bands(int32_t* __restrict__ hdr, int32_t* __restrict__ zeros,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_edit_bands(int32_t* __restrict__ hdr, int32_t* __restrict__ zeros,
                                                     const uint32_t* __restrict__ touched,
                                                     const int32_t* __restrict__ tzlo,
                                                     const uint32_t* __restrict__ toff, uint32_t* __restrict__ rowcnt,
                                                     const Rec* __restrict__ grp, UpdCounters* ctr,
                                                     unsigned long long* __restrict__ spare_cursor, uint64_t spare_end,
                                                     EditBuckets eb) {
-  extern __shared__ int32_t edit_lds[];
+  extern __shared__ int4 edit_lds[];
   const int lane = threadIdx.x & 63;
   const uint32_t wpb = blockDim.x >> 6;
-  int32_t* stage = edit_lds + (threadIdx.x >> 6) * edit_wave_words(eb.nbk);
+  int32_t* stage = reinterpret_cast<int32_t*>(edit_lds) + (threadIdx.x >> 6) * edit_wave_words(eb.nbk);
   int32_t* first = stage + kStageKeys;
   int32_t* first_old = first + eb.nbk + 1;
   uint8_t* mark = reinterpret_cast<uint8_t*>(first_old + eb.nbk + 1);
   const uint32_t n_touched = ctr->touched, n_records = ctr->records;
   int over_n = 0;
-  for (uint32_t t = blockIdx.x * wpb + (threadIdx.x >> 6); t < n_touched; t += gridDim.x * wpb) {
-    // one load each of the band, its records' range and its slice origin; then
-    // its header and records; then its keys
-    const uint32_t row = touched[t];
-    const uint32_t o0 = toff[t];
-    const uint32_t cnt = (t + 1 < n_touched ? toff[t + 1] : n_records) - o0;
-    const int32_t zlo = eb.lines ? tzlo[t] : 0;
+  const uint32_t stride = gridDim.x * wpb;
+  // Loads run ahead of the band being edited: a band's keys are loaded
+  // together with the next band's header and records and the band after
+  // that's number, record range and slice origin, so that one wait covers
+  // all three.
+  uint32_t t = blockIdx.x * wpb + (threadIdx.x >> 6);
+  uint32_t row_a = 0, o0_a = 0, cnt_a = 0, row_b = 0, o0_b = 0, cnt_b = 0;
+  int32_t zlo_a = 0, zlo_b = 0, hv_a = 0;
+  Rec r_a{0u, 0};
+  auto indices = [&](uint32_t u, uint32_t& row_, uint32_t& o0_, uint32_t& cnt_, int32_t& zlo_) {
+    if (u < n_touched) {
+      row_ = touched[u];
+      o0_ = toff[u];
+      cnt_ = (u + 1 < n_touched ? toff[u + 1] : n_records) - o0_;
+      zlo_ = eb.lines ? tzlo[u] : 0;
+    }
+  };
+  auto header = [&](uint32_t u) {  // band u's header words and records (lane k: record k < 64)
+    if (u < n_touched) {
+      hv_a = lane < kHeaderWords ? hdr[(int64_t)row_a * kNodeInts + lane] : 0;
+      r_a = lane < (int)cnt_a ? grp[o0_a + lane] : Rec{0u, 0};
+    }
+  };
+  indices(t, row_a, o0_a, cnt_a, zlo_a);
+  header(t);
+  indices(t + stride, row_b, o0_b, cnt_b, zlo_b);
+  for (; t < n_touched; t += stride) {
+    const uint32_t row = row_a, o0 = o0_a, cnt = cnt_a;
+    const int32_t zlo = zlo_a, hv = hv_a;
+    const Rec r = r_a;
+    row_a = row_b, o0_a = o0_b, cnt_a = cnt_b, zlo_a = zlo_b;
+    header(t + stride);
+    indices(t + 2 * stride, row_b, o0_b, cnt_b, zlo_b);
     const Rec* g = grp + o0;
     int32_t* node = hdr + (int64_t)row * kNodeInts;
-    const int32_t hv = lane < kHeaderWords ? node[lane] : 0;
     const uint32_t old_start = (uint32_t)__builtin_amdgcn_readlane(hv, 0);
     const int32_t len = __builtin_amdgcn_readlane(hv, 1);
     uint32_t cap = (uint32_t)__builtin_amdgcn_readlane(hv, 2);
-    // lane k holds record k (k < 64)
-    const Rec r = lane < (int)cnt ? g[lane] : Rec{0u, 0};
     const bool removal = (r.row & 0x80000000u) != 0;
     const uint64_t rm_mask = __ballot(lane < (int)cnt && removal);
     const uint64_t in_mask = __ballot(lane < (int)cnt && !removal);
@@ -479,7 +503,20 @@ __global__ __launch_bounds__(256) void k_edit_bands(int32_t* __restrict__ hdr, i
     }
     int32_t* lines = eb.lines ? eb.lines + (int64_t)row * eb.nbk * kLineInts : nullptr;
     if (len <= kStageKeys && new_len <= kStageKeys && cnt <= 64) {
-      for (int32_t k = lane; k < len; k += 64) stage[k] = zeros[old_start + k];
+      {  // whole 16-byte groups up to the end of the band's last line (inside its region), loads first
+        const int4* src = reinterpret_cast<const int4*>(zeros + old_start);
+        int4* dst = reinterpret_cast<int4*>(stage);
+        const int32_t groups = (int32_t)round_line((uint64_t)len) >> 2;
+        int4 v0 = make_int4(0, 0, 0, 0), v1 = v0, v2 = v0, v3 = v0;
+        if (lane < groups) v0 = src[lane];
+        if (64 + lane < groups) v1 = src[64 + lane];
+        if (128 + lane < groups) v2 = src[128 + lane];
+        if (192 + lane < groups) v3 = src[192 + lane];
+        if (lane < groups) dst[lane] = v0;
+        if (64 + lane < groups) dst[64 + lane] = v1;
+        if (128 + lane < groups) dst[128 + lane] = v2;
+        if (192 + lane < groups) dst[192 + lane] = v3;
+      }
       wave_fence();
       int32_t n = len;
       bool missing = false;
@@ -509,8 +546,24 @@ __global__ __launch_bounds__(256) void k_edit_bands(int32_t* __restrict__ hdr, i
         wave_fence();
         ++n;
       }
-      for (int32_t k = lane; k < (int32_t)round_line((uint64_t)n); k += 64)
-        zeros[start + k] = k < n ? stage[k] : INT_MAX;
+      {  // the keys and the INT_MAX padding of the last line, 16 bytes a lane
+        const int4* src = reinterpret_cast<const int4*>(stage);
+        int4* dst = reinterpret_cast<int4*>(zeros + start);
+        const int32_t groups = (int32_t)round_line((uint64_t)n) >> 2;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t gi = u * 64 + lane;
+          if (gi < groups) {
+            int4 v = src[gi];
+            const int32_t k = 4 * gi;
+            if (k >= n) v.x = INT_MAX;
+            if (k + 1 >= n) v.y = INT_MAX;
+            if (k + 2 >= n) v.z = INT_MAX;
+            if (k + 3 >= n) v.w = INT_MAX;
+            dst[gi] = v;
+          }
+        }
+      }
       band_levels(node, zeros, start, n, cap, stage);
       if (lane == 0) {
         node[0] = (int32_t)start;
@@ -519,7 +572,7 @@ __global__ __launch_bounds__(256) void k_edit_bands(int32_t* __restrict__ hdr, i
         rowcnt[row] = 0;
       }
       if (lines) {
-        bucket_firsts(stage, n, zlo, eb.shift, eb.nbk, first);
+        bucket_firsts4(stage, n, zlo, eb.shift, eb.nbk, first);
         for (int32_t b = lane; b < eb.nbk; b += 64) mark[b] = 0;
         wave_fence();
         if (lane < (int)cnt) mark_around(r.z, zlo, eb.shift, eb.nbk, first, mark);
