@@ -5,7 +5,7 @@
 // The persistent grid has blocks_per_cu blocks per compute unit; every wave
 // repeatedly takes the next tile index from one of eight 64-bit device
 // counters (one per contiguous part of the tiles), finds
-// its filter by binary search over the prefix sums and computes the tile's
+// its filter in the plan's tile map (one load) and computes the tile's
 // particle weights with the same per-particle routine as the plain kernel, so
 // the results are identical bit for bit.  A wave leaves when every part's
 // counter has passed the part's last tile, so the grid always drains.
@@ -23,6 +23,7 @@ struct cddt_plan_s {
   std::vector<int64_t> prefix;  // n_filters + 1 tile offsets for the current tuning
   cddt::FilterDev* d_filters = nullptr;
   int64_t* d_prefix = nullptr;
+  int4* d_tilemap = nullptr;  // per tile {filter, first particle, end particle, 0}; one entry per particle
   unsigned long long* d_counter = nullptr;
   cddt_tuning tuning{};
   int64_t total_tiles = 0;
@@ -48,7 +49,7 @@ namespace cddt {
 // Counter reset plus one persistent launch over the tiles of n_filters filters.
 cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, int32_t n_filters,
                          int64_t total_tiles, const cddt_tuning& t, unsigned long long* d_counter, int32_t cus,
-                         hipStream_t st, bool zp16, bool counter_zeroed) {
+                         hipStream_t st, bool zp16, bool counter_zeroed, const int4* d_tilemap) {
   if (!counter_zeroed) hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, d_counter);
   if (total_tiles > 0) {
     // no more blocks than tiles need (small batches): every wave claims at least once per part
@@ -62,10 +63,10 @@ cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, in
   case KK:                                                                                                      \
     if (zp16)                                                                                                   \
       hipLaunchKernelGGL((k_batch<KK, true>), dim3(blocks), dim3(threads), lds, st, d_filters, d_prefix,        \
-                         n_filters, total_tiles, ppt, d_counter);                                               \
+                         d_tilemap, n_filters, total_tiles, ppt, d_counter);                                               \
     else                                                                                                        \
       hipLaunchKernelGGL((k_batch<KK, false>), dim3(blocks), dim3(threads), lds, st, d_filters, d_prefix,       \
-                         n_filters, total_tiles, ppt, d_counter);                                               \
+                         d_tilemap, n_filters, total_tiles, ppt, d_counter);                                               \
     break;
       CDDT_BATCH_K(1)
       CDDT_BATCH_K(2)
@@ -110,16 +111,33 @@ cddt_tuning default_tuning() {
 
 namespace {
 
-// Recompute tile prefix sums for the plan's tuning and upload them (blocking).
+// The tile map of a tuning: tiles of ppt particles (the last of a filter
+// clipped), in filter order.  (Cutting the launch's last tiles into smaller
+// pieces, so that waves end closer together, measured slower: a tile's fixed
+// costs outweigh the shorter tail.)
+std::vector<int4> build_tilemap(const std::vector<cddt_filter>& filters, const cddt_tuning& t) {
+  const int64_t ppt = t.particles_per_tile;
+  std::vector<int4> tm;
+  for (size_t f = 0; f < filters.size(); ++f)
+    for (int64_t p = 0; p < filters[f].n_particles; p += ppt)
+      tm.push_back(make_int4((int32_t)f, (int32_t)p, (int32_t)std::min(p + ppt, filters[f].n_particles), 0));
+  return tm;
+}
+
+// Recompute the tile prefix sums and the tile map for the plan's tuning and
+// upload them (blocking).  The kernel takes its tiles from the map.
 cddt_status apply_tuning(cddt_plan_s* p, const cddt_tuning& t, hipStream_t st) {
   CDDT_TRY(check_tuning(t));
   const int64_t ppt = t.particles_per_tile;
   p->prefix.assign(p->filters.size() + 1, 0);
   for (size_t f = 0; f < p->filters.size(); ++f)
     p->prefix[f + 1] = p->prefix[f] + (p->filters[f].n_particles + ppt - 1) / ppt;
-  p->total_tiles = p->prefix.back();
+  const std::vector<int4> tm = build_tilemap(p->filters, t);
+  p->total_tiles = (int64_t)tm.size();  // = prefix.back()
   CDDT_HIP(hipMemcpyAsync(p->d_prefix, p->prefix.data(), sizeof(int64_t) * p->prefix.size(), hipMemcpyHostToDevice,
                           st));
+  if (!tm.empty())
+    CDDT_HIP(hipMemcpyAsync(p->d_tilemap, tm.data(), sizeof(int4) * tm.size(), hipMemcpyHostToDevice, st));
   CDDT_HIP(hipStreamSynchronize(st));
   p->tuning = t;
   return CDDT_OK;
@@ -145,7 +163,7 @@ cddt_status refresh_descriptors(cddt_plan_s* p, hipStream_t st) {
 
 cddt_status launch_plan(cddt_plan_s* p, hipStream_t st) {
   return launch_batch(p->d_filters, p->d_prefix, (int32_t)p->filters.size(), p->total_tiles, p->tuning,
-                      p->d_counter, p->cus, st, p->zp16);
+                      p->d_counter, p->cus, st, p->zp16, /*counter_zeroed=*/false, p->d_tilemap);
 }
 
 void drop_graph(cddt_plan_s* p);
@@ -217,6 +235,7 @@ cddt_status cddt_plan_create(const cddt_filter* filters_h, int32_t n_filters, co
   auto bail = [&](const std::string& msg) {
     if (p->d_filters) (void)hipFree(p->d_filters);
     if (p->d_prefix) (void)hipFree(p->d_prefix);
+    if (p->d_tilemap) (void)hipFree(p->d_tilemap);
     if (p->d_counter) (void)hipFree(p->d_counter);
     if (p->d_ppre) (void)hipFree(p->d_ppre);
     delete p;
@@ -224,6 +243,7 @@ cddt_status cddt_plan_create(const cddt_filter* filters_h, int32_t n_filters, co
   };
   if (hipMalloc(&p->d_filters, sizeof(FilterDev) * n_filters) != hipSuccess ||
       hipMalloc(&p->d_prefix, sizeof(int64_t) * (n_filters + 1)) != hipSuccess ||
+      hipMalloc(&p->d_tilemap, sizeof(int4) * (size_t)std::max<int64_t>(1, p->total_particles)) != hipSuccess ||
       hipMalloc(&p->d_counter, kBatchCounterBytes) != hipSuccess ||
       hipMalloc(&p->d_ppre, sizeof(int64_t) * (n_filters + 1)) != hipSuccess)
     return bail("cddt_plan_create: hipMalloc failed");
@@ -375,6 +395,7 @@ cddt_status cddt_plan_destroy(cddt_plan p) {
   drop_graph(p);
   if (p->d_filters) (void)hipFree(p->d_filters);
   if (p->d_prefix) (void)hipFree(p->d_prefix);
+  if (p->d_tilemap) (void)hipFree(p->d_tilemap);
   if (p->d_counter) (void)hipFree(p->d_counter);
   if (p->d_ppre) (void)hipFree(p->d_ppre);
   if (p->d_stage) (void)hipFree(p->d_stage);

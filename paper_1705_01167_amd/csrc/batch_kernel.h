@@ -1,8 +1,8 @@
 // The persistent batched kernel: every wave repeatedly takes the next tile
 // index from the 64-bit device counter of its part of the tiles, finds its
-// filter by binary search over the prefix sums of tile counts and computes
-// the tile's particle weights with the same per-particle routine as the plain
-// kernel.
+// filter (from the tile map when the caller provides one, else by binary
+// search over the prefix sums of tile counts) and computes the tile's particle
+// weights with the same per-particle routine as the plain kernel.
 #pragma once
 
 #include "query_device.h"
@@ -58,9 +58,12 @@ __host__ __device__ constexpr size_t tile_lds_bytes(int mode, int waves) {
 
 // Z: instantiated for batches that hold a map with 16-bit zero points in its
 // bucket lines (the plain instantiation has no code for them).
+// tilemap (nullable): per tile {filter, first particle, end particle, 0}; a
+// tile may be empty (first == end).  Without it tile t of filter f covers
+// particles [t ppt, (t + 1) ppt) of f (the last tile clipped).
 template <int Mode, bool Z>
 __global__ __launch_bounds__(kMaxBatchThreads) void k_batch(const FilterDev* __restrict__ filters, const int64_t* __restrict__ prefix,
-                        int32_t n_filters, int64_t total_tiles, int32_t ppt,
+                        const int4* __restrict__ tilemap, int32_t n_filters, int64_t total_tiles, int32_t ppt,
                         unsigned long long* __restrict__ counter) {
   extern __shared__ int2 smem_jobs[];
   constexpr int Q = tile_q(Mode);
@@ -106,22 +109,35 @@ __global__ __launch_bounds__(kMaxBatchThreads) void k_batch(const FilterDev* __r
       continue;
     }
     ticket = claim(part);
-    // prefix[lo] <= t < prefix[hi], by scalar loads: they wait on their own
+    // the tile's filter and particles: one load from the tile map, or
+    // prefix[lo] <= t < prefix[hi]; by scalar loads, which wait on their own
     // counter, not behind the ticket claim and other vector loads in flight
-    // (the prefix is written before the launch, so the scalar cache is current)
-    const __attribute__((address_space(4))) int64_t* sprefix =
-        (const __attribute__((address_space(4))) int64_t*)prefix;
-    int32_t lo = 0, hi = n_filters;
-    while (hi - lo > 1) {
-      int32_t mid = (lo + hi) >> 1;
-      if ((uint64_t)sprefix[mid] <= t)
-        lo = mid;
-      else
-        hi = mid;
+    // (both arrays are written before the launch, so the scalar cache is current)
+    int32_t lo = 0;
+    int64_t p0, p1;
+    if (tilemap) {
+      const __attribute__((address_space(4))) int32_t* stm =
+          (const __attribute__((address_space(4))) int32_t*)tilemap;
+      lo = stm[4 * t];
+      p0 = stm[4 * t + 1];
+      p1 = stm[4 * t + 2];
+      if (p0 >= p1) continue;  // an empty tile
+    } else {
+      const __attribute__((address_space(4))) int64_t* sprefix =
+          (const __attribute__((address_space(4))) int64_t*)prefix;
+      int32_t hi = n_filters;
+      while (hi - lo > 1) {
+        int32_t mid = (lo + hi) >> 1;
+        if ((uint64_t)sprefix[mid] <= t)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      p0 = (int64_t)(t - (uint64_t)sprefix[lo]) * ppt;
+      p1 = -1;
     }
     const FilterDev f = filters[lo];
-    const int64_t p0 = (int64_t)(t - (uint64_t)sprefix[lo]) * ppt;
-    const int64_t p1 = p0 + ppt < f.n_particles ? p0 + ppt : f.n_particles;
+    if (p1 < 0) p1 = p0 + ppt < f.n_particles ? p0 + ppt : f.n_particles;
     if constexpr (Q > 0) {
       if (f.n_rays <= kWave) {
         for (int64_t p = p0; p < p1; p += Q)

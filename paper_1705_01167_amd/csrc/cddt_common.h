@@ -126,10 +126,12 @@ cddt_status launch_cast(const MapDev& m, const float* x, const float* y, const f
 cddt_status launch_weight(const FilterDev& f, hipStream_t st);
 // batch.hip.  d_counter: kBatchCounterBytes of device memory (the per-part
 // tile counters); counter_zeroed: the caller has already cleared all of it in
-// stream order.
+// stream order; d_tilemap (nullable): per tile {filter, first particle, end
+// particle, 0}, total_tiles entries; else tile t of a filter is its t-th run
+// of ppt particles, the filter found by searching d_prefix.
 cddt_status launch_batch(const FilterDev* d_filters, const int64_t* d_prefix, int32_t n_filters,
                          int64_t total_tiles, const cddt_tuning& t, unsigned long long* d_counter, int32_t cus,
-                         hipStream_t st, bool zp16, bool counter_zeroed = false);
+                         hipStream_t st, bool zp16, bool counter_zeroed = false, const int4* d_tilemap = nullptr);
 cddt_status check_tuning(const cddt_tuning& t);
 // mcl.hip: motion of every particle of every filter (particle offsets d_pre,
 // n_filters + 1 entries), and one resampling workgroup per filter.
