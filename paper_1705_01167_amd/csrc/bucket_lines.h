@@ -47,8 +47,10 @@ __device__ __forceinline__ int32_t band_slice(const int32_t* __restrict__ row_st
   return lo;
 }
 
+// Bucket of key z, nbk for keys past the last bucket (z >= zlo, so the
+// difference fits 32 unsigned bits).
 __device__ __forceinline__ int32_t bucket_of(int32_t z, int32_t zlo, int32_t shift, int32_t nbk) {
-  return (int32_t)min(((int64_t)z - zlo) >> shift, (int64_t)nbk);
+  return (int32_t)min(((uint32_t)z - (uint32_t)zlo) >> shift, (uint32_t)nbk);
 }
 
 // first[0..nbk] of keys[0, len) (keys ascending, all >= zlo).

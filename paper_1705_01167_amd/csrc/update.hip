@@ -378,6 +378,22 @@ __device__ __forceinline__ void shift_left(int32_t* keys, int32_t a, int32_t b) 
   }
 }
 
+// Position in keys[0, len) of the first key >= z (lower) or > z (upper), for
+// keys in LDS and len <= 1024 = 64 x 16: lane l compares key 16 l, which
+// finds the group of 16 that holds the position; lanes 0..15 then compare the
+// group's keys.  Two LDS reads and two ballots; the same on every lane.
+__device__ __forceinline__ int32_t bound_lds(const int32_t* keys, int32_t len, int32_t z, bool upper) {
+  const int lane = threadIdx.x & 63;
+  auto before = [&](int32_t k) {  // key k lies before the position
+    const int32_t v = keys[k];
+    return upper ? v <= z : v < z;
+  };
+  const int32_t g = __popcll(__ballot(16 * lane < len && before(16 * lane)));  // groups that start before it
+  if (g == 0) return 0;
+  const int32_t base = 16 * (g - 1);
+  return base + __popcll(__ballot(lane < 16 && base + lane < len && before(base + lane)));
+}
+
 // Position in keys[0, len) of the first key >= z (lower) or > z (upper); every lane computes it.
 __device__ __forceinline__ int32_t bound(const int32_t* keys, int32_t len, int32_t z, bool upper) {
   int32_t lo = 0, cnt = len;
@@ -522,7 +538,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
       bool missing = false;
       for (uint64_t mm = rm_mask; mm; mm &= mm - 1) {
         const int32_t z = __builtin_amdgcn_readlane(r.z, (int)__builtin_ctzll(mm));
-        const int32_t pos = bound(stage, n, z, false);
+        const int32_t pos = bound_lds(stage, n, z, false);
         if (pos >= n || stage[pos] != z) {
           missing = true;
           break;
@@ -540,7 +556,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
       }
       for (uint64_t mm = in_mask; mm; mm &= mm - 1) {
         const int32_t z = __builtin_amdgcn_readlane(r.z, (int)__builtin_ctzll(mm));
-        const int32_t pos = bound(stage, n, z, true);
+        const int32_t pos = bound_lds(stage, n, z, true);
         shift_right<true>(stage, pos, n);
         if (lane == 0) stage[pos] = z;
         wave_fence();
