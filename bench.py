@@ -264,6 +264,19 @@ def run_batched(args) -> dict:
     wall, batched_ms = timed(step, args.steps, args.warmup, stream)
     exact = all(torch.equal(a, k[2]) for a, k in zip(plain_out, keep))
     _, plain_ms = timed(plan.run_plain, args.steps, max(1, args.warmup // 2), stream)
+    # The same persistent kernel and tuning, one launch per filter: splits the
+    # gain over plain launches into the search strategy's and the batching's.
+    singles = [cddt.Plan([f], tuning=tuple(best), stream=stream, keepalive=keep) for f in filters]
+
+    def run_singles(st):
+        for sp in singles:
+            sp.run(st)
+
+    _, single_ms = timed(run_singles, args.steps, max(1, args.warmup // 2), stream)
+    for sp in singles:
+        sp.close()
+    log(f"bench: batched {batched_ms:.3f} ms, plain launches {plain_ms:.3f} ms, the batched kernel per filter "
+        f"{single_ms:.3f} ms")
 
     mcl = None if args.no_mcl else run_mcl_step(args, plan, pose_buf, specs, stream, batched_ms)
 
@@ -311,6 +324,8 @@ def run_batched(args) -> dict:
         "batched_rays_per_s_kernel": rays_per_step / (batched_ms * 1e-3),
         "plain_rays_per_s": rays_per_step / (plain_ms * 1e-3),
         "batched_over_plain": plain_ms / batched_ms,
+        "per_filter_same_kernel_rays_per_s": rays_per_step / (single_ms * 1e-3),
+        "batched_over_per_filter_same_kernel": single_ms / batched_ms,
         "batched_equals_plain": bool(exact),
         "build_seconds": times["gpu_build_s"],
         "roofline": {
