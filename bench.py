@@ -173,6 +173,7 @@ def build_batched(n_filters: int, with_ranges: bool = False):
 def cpu_baseline(specs, host, off_h, budget_s: float, max_build_s: float = 40.0):
     """The C++ oracle (plain CDDT, std::thread over particles) on filters spread over map sizes."""
     from oracle import ref as oref
+    flags = oref.select_native()
     threads = max(1, len(os.sched_getaffinity(0)))
     order = sorted(range(len(specs)), key=lambda f: specs[f]["side"])
     picks = sorted({order[int(round(q * (len(order) - 1)))] for q in (0.0, 0.25, 0.5, 0.75, 1.0)})
@@ -207,7 +208,7 @@ def cpu_baseline(specs, host, off_h, budget_s: float, max_build_s: float = 40.0)
         rm.close()
     return {"value": rays / secs, "unit": "rays/s", "cores": threads, "kind": "oracle",
             "single_thread_rays_per_s": rays1 / secs1, "cpu_model": cpu_model(),
-            "sample": (f"plain C++ CDDT oracle (sorted vectors, std::upper_bound, double log-sum) with "
+            "sample": (f"plain C++ CDDT oracle (sorted vectors, std::upper_bound, double log-sum; {flags}) with "
                        f"{threads} threads on {len(built)} of {len(specs)} filters spread over map size "
                        f"[{', '.join(names)}], all their particles, {passes} passes, {rays} rays in "
                        f"{secs:.1f} s; oracle structure build ({build_s:.1f} s) excluded; one thread: "
@@ -564,6 +565,7 @@ def run_suites(args) -> dict:
         m.close()
         # the CPU oracle (plain C++ CDDT) per query on one thread, a sample of each suite
         if not args.no_cpu:
+            oref.select_native()
             rm = oref.RefCDDT(occ, n)
             cpu = {}
             for sname, (x, y, th) in suites.items():

@@ -7,6 +7,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 import subprocess
+import tempfile
 
 import numpy as np
 
@@ -18,19 +19,41 @@ LIB = os.path.join(HERE, "libcddt_ref.so")
 SRC_MCL = os.path.join(HERE, "mcl_ref.c")
 
 
+def _compile(out: str, extra: list[str]) -> str:
+    tmp = out + ".tmp"
+    obj = out + ".mcl.o"
+    subprocess.run(["gcc", "-std=c11", "-O2", *extra, "-ffp-contract=off", "-fPIC", "-c", SRC_MCL, "-o", obj],
+                   check=True)
+    cmd = ["g++", "-std=c++17", "-O2", *extra, "-ffp-contract=off", "-fPIC", "-shared", "-pthread",
+           SRC, obj, "-o", tmp]
+    subprocess.run(cmd, check=True)
+    os.remove(obj)
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with the host compilers (no GPU code involved)."""
     if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp"
-        obj = LIB + ".mcl.o"
-        subprocess.run(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fPIC", "-c", SRC_MCL, "-o", obj],
-                       check=True)
-        cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-pthread",
-               SRC, obj, "-o", tmp]
-        subprocess.run(cmd, check=True)
-        os.remove(obj)
-        os.replace(tmp, LIB)
+        _compile(LIB, [])
     return LIB
+
+
+def select_native() -> str:
+    """Load an oracle library compiled for this host's CPU (-O2 -march=native),
+    built in a temporary directory, for timing the CPU baseline on the machine
+    that runs it; the portable build in this directory stays the one the tests
+    load.  Must come before the first call into the oracle.  Returns the flags
+    in use."""
+    global LIB
+    if _lib is not None:
+        return "-O2 -march=native" if LIB.endswith("_native.so") else "-O2"
+    try:
+        d = tempfile.mkdtemp(prefix="cddt_ref_")
+        LIB = _compile(os.path.join(d, "libcddt_ref_native.so"), ["-march=native"])
+        return "-O2 -march=native"
+    except (OSError, subprocess.CalledProcessError):
+        return "-O2"
 
 
 _lib = None
