@@ -103,9 +103,12 @@ __device__ __forceinline__ int32_t lower_bound_i32(const int32_t* __restrict__ a
 }
 
 // Round the Q16 distance half up and clamp to the max range.
-__device__ __forceinline__ int32_t range_of(int64_t d, int32_t max_range) {
-  int64_t v = (d + 32768) >> 16;
-  return v < (int64_t)max_range ? (int32_t)v : max_range;
+// Range from the distance d >= 0 (Q16) between a query and a zero point,
+// rounded half up, capped at max_range.  Zero points and in-map queries lie
+// within 2^31 - 2^28 of 0, so d < 2^32 - 2^29 and d + 2^15 fits 32 unsigned bits.
+__device__ __forceinline__ int32_t range_of(uint32_t d, int32_t max_range) {
+  const uint32_t v = (d + 32768u) >> 16;
+  return v < (uint32_t)max_range ? (int32_t)v : max_range;
 }
 
 // Where a valid query lands: along-ray coordinate and global band index.
@@ -288,7 +291,7 @@ __device__ __forceinline__ void wave_search(const MapDev& m, bool want, int32_t 
     int32_t gs[K], gp[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      gs[j] = c[j] < len[j] ? range_of((int64_t)nxt[j] - x[j], max_range) : max_range;
+      gs[j] = c[j] < len[j] ? range_of((uint32_t)nxt[j] - (uint32_t)x[j], max_range) : max_range;
       gp[j] = max_range;
       if (c[j] > 0) {
         int32_t pv = prv[j];
@@ -296,7 +299,7 @@ __device__ __forceinline__ void wave_search(const MapDev& m, bool want, int32_t 
           const int32_t lb = lower_bound_i32(m.zeros + start[j], c[j], x[j]);
           pv = lb > 0 ? ldg(m.zeros + start[j] + lb - 1) : INT_MIN;
         }
-        if (pv != INT_MIN) gp[j] = range_of((int64_t)x[j] - pv, max_range);
+        if (pv != INT_MIN) gp[j] = range_of((uint32_t)x[j] - (uint32_t)pv, max_range);
       }
     }
     // hand results back: search k = base + 8j + g sits in slot j of group g;
@@ -401,8 +404,8 @@ __device__ __forceinline__ void tree_search(const MapDev& m, bool want, int32_t 
   if (!want) return;
   int32_t succ, pred;
   tree_keys(m, row, x, true, succ, pred);
-  if (succ != INT_MAX) r_succ = range_of((int64_t)succ - x, max_range);
-  if (pred != INT_MIN) r_pred = range_of((int64_t)x - pred, max_range);
+  if (succ != INT_MAX) r_succ = range_of((uint32_t)succ - (uint32_t)x, max_range);
+  if (pred != INT_MIN) r_pred = range_of((uint32_t)x - (uint32_t)pred, max_range);
 }
 
 // Bucket-index search by one lane: the bucket line of (band, x) gives the
@@ -429,8 +432,8 @@ __device__ __forceinline__ void scan_bucket(const Line32& L, int32_t x, int32_t 
   int32_t nxt = has_above(dn, x) ? (int32_t)((uint32_t)x + 1u + dn) : INT_MAX;
   const int32_t prv = has_below(dp, xm) ? (int32_t)((uint32_t)xm - dp) : L.e[0];
   nxt = nxt < L.e[1] ? nxt : L.e[1];
-  r_succ = nxt != INT_MAX ? range_of((int64_t)nxt - x, max_range) : max_range;
-  r_pred = prv != INT_MIN ? range_of((int64_t)x - prv, max_range) : max_range;
+  r_succ = nxt != INT_MAX ? range_of((uint32_t)nxt - (uint32_t)x, max_range) : max_range;
+  r_pred = prv != INT_MIN ? range_of((uint32_t)x - (uint32_t)prv, max_range) : max_range;
 }
 
 // 16-bit zero points: a key of bin B stands for the bin centre B 8192 + 4096
@@ -462,8 +465,8 @@ __device__ __forceinline__ void scan_bucket16(const MapDev& m, const Line32& L, 
   const int32_t p16 = dp < 0x80000000u ? tp - (int32_t)dp : -1;
   const int32_t nxt = s16 != 0xffff ? bin_centre(base + s16) : L.e[1];
   const int32_t prv = p16 >= 0 ? bin_centre(base + p16) : L.e[0];
-  r_succ = nxt != INT_MAX ? range_of((int64_t)nxt - x, max_range) : max_range;
-  r_pred = prv != INT_MIN ? range_of((int64_t)x - prv, max_range) : max_range;
+  r_succ = nxt != INT_MAX ? range_of((uint32_t)nxt - (uint32_t)x, max_range) : max_range;
+  r_pred = prv != INT_MIN ? range_of((uint32_t)x - (uint32_t)prv, max_range) : max_range;
 }
 
 // Overflowing bucket: the band's exact keys by one tree descent, in a kernel
@@ -491,8 +494,8 @@ __device__ __forceinline__ void tree_search_any(const MapDev& m, bool z, int32_t
     vp = bin_centre((pred - zlo) >> kBinShift);
     xr = x;
   }
-  r_succ = succ != INT_MAX ? range_of((int64_t)vs - xr, max_range) : max_range;
-  r_pred = pred != INT_MIN ? range_of((int64_t)xr - vp, max_range) : max_range;
+  r_succ = succ != INT_MAX ? range_of((uint32_t)vs - (uint32_t)xr, max_range) : max_range;
+  r_pred = pred != INT_MIN ? range_of((uint32_t)xr - (uint32_t)vp, max_range) : max_range;
 }
 
 // Z: the caller's kernel handles maps with 16-bit zero points (Z = false
@@ -611,13 +614,13 @@ __device__ __forceinline__ void lane_search2(const MapDev& m, bool wa, int32_t r
   auto finish = [&](bool w, uint32_t st, int32_t ln, int32_t c, int32_t nx, int32_t pv, int32_t x, int32_t& rs,
                     int32_t& rp) {
     if (!w) return;
-    if (c < ln) rs = range_of((int64_t)nx - x, max_range);
+    if (c < ln) rs = range_of((uint32_t)nx - (uint32_t)x, max_range);
     if (c > 0) {
       if (pv == x) {  // rare: x equals a key; find the last key strictly below it
         const int32_t lb = lower_bound_i32(m.zeros + st, c, x);
         pv = lb > 0 ? ldg(m.zeros + st + lb - 1) : INT_MIN;
       }
-      if (pv != INT_MIN) rp = range_of((int64_t)x - pv, max_range);
+      if (pv != INT_MIN) rp = range_of((uint32_t)x - (uint32_t)pv, max_range);
     }
   };
   finish(wa, st_a, ln_a, ca, na, va, xa, sa, pa);
@@ -688,8 +691,8 @@ __device__ __forceinline__ bool quad_half_round(const MapDev& m, const int2* job
   const int32_t xm = x - 1;
   const int32_t nxt = has_above(d1, x) ? (int32_t)((uint32_t)x + 1u + d1) : INT_MAX;
   const int32_t prv = has_below(d2, xm) ? (int32_t)((uint32_t)xm - d2) : INT_MIN;
-  rs = nxt != INT_MAX ? range_of((int64_t)nxt - x, max_range) : max_range;
-  rp = prv != INT_MIN ? range_of((int64_t)x - prv, max_range) : max_range;
+  rs = nxt != INT_MAX ? range_of((uint32_t)nxt - (uint32_t)x, max_range) : max_range;
+  rp = prv != INT_MIN ? range_of((uint32_t)x - (uint32_t)prv, max_range) : max_range;
   if (f) rs = -1;
   return jo < njobs;
 }
@@ -761,8 +764,8 @@ __device__ __forceinline__ bool quad_half_round16(const MapDev& m, const int2* j
   const int32_t p16 = dp < 0x80000000u ? tp - (int32_t)dp : -1;
   const int32_t nxt = s16 != 0xffff ? bin_centre(base + s16) : e1;
   const int32_t prv = p16 >= 0 ? bin_centre(base + p16) : e0;
-  rs = nxt != INT_MAX ? range_of((int64_t)nxt - x, max_range) : max_range;
-  rp = prv != INT_MIN ? range_of((int64_t)x - prv, max_range) : max_range;
+  rs = nxt != INT_MAX ? range_of((uint32_t)nxt - (uint32_t)x, max_range) : max_range;
+  rp = prv != INT_MIN ? range_of((uint32_t)x - (uint32_t)prv, max_range) : max_range;
   if (f) rs = -1;
   return jo < njobs;
 }
