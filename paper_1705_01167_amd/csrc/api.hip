@@ -62,11 +62,13 @@ namespace {
 
 void release_scratch(cddt_map_s* m) {
   for (Scratch* s : {&m->upd_ops, &m->upd_changed, &m->upd_cand, &m->upd_edits, &m->upd_rec, &m->upd_rowcnt,
-                     &m->upd_misc, &m->upd_slot, &m->upd_touched, &m->upd_grp, &m->upd_tiles}) {
+                     &m->upd_slot, &m->upd_touched, &m->upd_grp, &m->upd_tiles}) {
     if (s->ptr) m->alloc.release(s->ptr);
     s->ptr = nullptr;
     s->bytes = 0;
   }
+  if (m->upd_host) (void)hipHostFree(m->upd_host);
+  m->upd_host = nullptr;
   m->upd_rowcnt_clear = false;
 }
 

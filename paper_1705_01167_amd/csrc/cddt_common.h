@@ -80,9 +80,10 @@ struct cddt_map_s {
   unsigned long long* d_bk_over = nullptr;  // overflowing buckets (device counter)
   int64_t bucket_overflow = 0;
   // update scratch (grown on demand, released with the map)
-  cddt::Scratch upd_ops, upd_changed, upd_cand, upd_edits, upd_rec, upd_rowcnt, upd_misc;
+  cddt::Scratch upd_ops, upd_changed, upd_cand, upd_edits, upd_rec, upd_rowcnt;
   cddt::Scratch upd_slot, upd_touched, upd_grp, upd_tiles;
   bool upd_rowcnt_clear = false;  // upd_rowcnt holds zeros for every band
+  void* upd_host = nullptr;       // pinned staging of a chunk's ops and counters (hipHostMalloc)
   cddt::MapDev dev() const {
     cddt::MapDev m;
     m.occ = d_occ;

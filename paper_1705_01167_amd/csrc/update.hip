@@ -43,6 +43,9 @@ constexpr int kScanItems = 4;
 constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr unsigned kEditBlocks = 4096;    // band-edit launch: waves take touched bands in turn
 constexpr unsigned kStrideBlocks = 2048;  // record-sized launches: threads take records in turn
+// A chunk's device staging: xs, ys (int32) and values (uint8), kOpChunk each,
+// then the counters.
+constexpr size_t kCounterOffset = (size_t)kOpChunk * 9;
 // Bytes per record of the record, grouping and touched-band arrays.
 constexpr uint64_t kRecordBytes = 8 + 4 + 2 + 8 + 12;
 // Record arrays up to this size are allocated for the chunk's worst case, so
@@ -60,6 +63,7 @@ struct UpdCounters {
   int32_t delta;      // change of the zero-point total when every record applies
   int32_t bk_over;    // change of the overflowing-bucket count
 };
+constexpr size_t kStageBytes = kCounterOffset + sizeof(UpdCounters);
 
 __device__ __forceinline__ uint32_t pack_cell(int i, int j) { return (uint32_t)i | ((uint32_t)j << 16); }
 __device__ __forceinline__ int cell_i(uint32_t p) { return (int)(p & 0xffffu); }
@@ -685,13 +689,21 @@ cddt_status apply_update(cddt_map_s* m, const int32_t* xs_h, const int32_t* ys_h
     CDDT_HIP(hipMemsetAsync(m->upd_rowcnt.ptr, 0, m->upd_rowcnt.bytes, st));
     m->upd_rowcnt_clear = true;
   }
-  CDDT_TRY(ensure(m->alloc, m->upd_misc, sizeof(UpdCounters), "update counters"));
-  CDDT_TRY(ensure(m->alloc, m->upd_ops, (size_t)kOpChunk * 9, "update ops"));
+  // A chunk's ops and its zeroed counters go to the device in one copy from
+  // pinned staging (the counters sit right after the ops on both sides); the
+  // counters come back into pinned memory.
+  CDDT_TRY(ensure(m->alloc, m->upd_ops, kStageBytes, "update ops"));
+  if (!m->upd_host &&
+      hipHostMalloc(&m->upd_host, kStageBytes + sizeof(UpdCounters), hipHostMallocDefault) != hipSuccess) {
+    m->upd_host = nullptr;
+    return fail(CDDT_ENOMEM, "cddt_update: pinned staging allocation failed");
+  }
   CDDT_TRY(ensure(m->alloc, m->upd_changed, (size_t)kOpChunk * sizeof(int2), "changed cells"));
   CDDT_TRY(ensure(m->alloc, m->upd_cand, (size_t)kOpChunk * 9 * sizeof(int2), "candidate cells"));
   CDDT_TRY(ensure(m->alloc, m->upd_edits, (size_t)kOpChunk * 9 * sizeof(int2), "edge flips"));
-  UpdCounters* ctr = (UpdCounters*)m->upd_misc.ptr;
-  std::vector<uint8_t> packed((size_t)kOpChunk * 9);
+  UpdCounters* ctr = (UpdCounters*)((uint8_t*)m->upd_ops.ptr + kCounterOffset);
+  uint8_t* packed = (uint8_t*)m->upd_host;
+  UpdCounters* host_ctr = (UpdCounters*)(packed + kStageBytes);
   // A pruned (PCDDT) structure depends on every free cell, not only on edge
   // flips: its grid takes the ops and the structure is rebuilt and pruned.
   const bool pruned = (m->flags & CDDT_FLAG_PRUNE) != 0;
@@ -702,11 +714,12 @@ cddt_status apply_update(cddt_map_s* m, const int32_t* xs_h, const int32_t* ys_h
     int32_t* d_xs = (int32_t*)m->upd_ops.ptr;
     int32_t* d_ys = d_xs + kOpChunk;
     uint8_t* d_vs = (uint8_t*)(d_ys + kOpChunk);
-    std::memcpy(packed.data(), xs_h + o0, 4 * (size_t)n);
-    std::memcpy(packed.data() + 4 * (size_t)kOpChunk, ys_h + o0, 4 * (size_t)n);
-    std::memcpy(packed.data() + 8 * (size_t)kOpChunk, vals_h + o0, (size_t)n);
-    CDDT_HIP(hipMemcpyAsync(d_xs, packed.data(), packed.size(), hipMemcpyHostToDevice, st));
-    CDDT_HIP(hipMemsetAsync(ctr, 0, sizeof(UpdCounters), st));
+    // (the previous chunk ended with a wait, so its copy has read the staging)
+    std::memcpy(packed, xs_h + o0, 4 * (size_t)n);
+    std::memcpy(packed + 4 * (size_t)kOpChunk, ys_h + o0, 4 * (size_t)n);
+    std::memcpy(packed + 8 * (size_t)kOpChunk, vals_h + o0, (size_t)n);
+    std::memset(packed + kCounterOffset, 0, sizeof(UpdCounters));
+    CDDT_HIP(hipMemcpyAsync(d_xs, packed, kCounterOffset + sizeof(UpdCounters), hipMemcpyHostToDevice, st));
     const int2* changed = (const int2*)m->upd_changed.ptr;
     const int2* cand = (const int2*)m->upd_cand.ptr;
     const int2* edits = (const int2*)m->upd_edits.ptr;
@@ -729,8 +742,9 @@ cddt_status apply_update(cddt_map_s* m, const int32_t* xs_h, const int32_t* ys_h
     const bool no_wait = !pruned && bound_rec * kRecordBytes <= kNoWaitBytes;
     uint64_t max_rec = bound_rec, max_edits = (uint64_t)n * 9;
     if (!no_wait) {
-      CDDT_HIP(hipMemcpyAsync(&hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
+      CDDT_HIP(hipMemcpyAsync(host_ctr, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
       CDDT_HIP(hipStreamSynchronize(st));
+      hc = *host_ctr;
       if (pruned) {
         grid_changed = grid_changed || hc.changed > 0;
         continue;
@@ -782,8 +796,9 @@ cddt_status apply_update(cddt_map_s* m, const int32_t* xs_h, const int32_t* ys_h
                        touched, (const int32_t*)tzlo, toff, rowcnt, (const Rec*)m->upd_grp.ptr, ctr, m->d_spare,
                        (uint64_t)m->spare_end, eb);
     CDDT_HIP(hipGetLastError());
-    CDDT_HIP(hipMemcpyAsync(&hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
+    CDDT_HIP(hipMemcpyAsync(host_ctr, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
     CDDT_HIP(hipStreamSynchronize(st));
+    hc = *host_ctr;
     if (hc.missing) {  // never expected: restore a consistent structure, then report
       CDDT_TRY(build_structure(m, st));
       ++m->rebuilds;

@@ -91,8 +91,11 @@ def test_overflow_relays_structure():
     assert _same_export(gm2.export(), gm.export())
 
 
-def test_outgrown_bands_move_to_spare_area():
-    """Bands that outgrow their slack move to the spare area: no re-layout, same structure as a fresh build."""
+@pytest.mark.parametrize("wall", [200, 40])
+def test_outgrown_bands_move_to_spare_area(wall):
+    """Bands that outgrow their slack move to the spare area: no re-layout, same structure as a fresh build.
+    Walls of 200 cells give the row band of the axis slice ~200 records (edited in place); walls of 40
+    give it 40 (edited in an LDS copy) against a capacity of 32."""
     occ = np.zeros((160, 200), np.uint8)
     occ[0, :] = 1
     for n in (108, 200):
@@ -101,12 +104,13 @@ def test_outgrown_bands_move_to_spare_area():
             cur = occ.copy()
             rng = wl.rng_for(405, n)
             for step in range(3):
-                # long walls: every row band of the axis slices gains ~200 zero points
+                # long walls: the row band of the axis slice gains one zero point per wall cell
                 j = int(rng.integers(10, 150))
-                xs = np.arange(200, dtype=np.int32)
-                ys = np.full(200, j, np.int32)
-                gm.update(xs, ys, np.ones(200, np.uint8))
-                wl.apply_ops(cur, xs, ys, np.ones(200, np.uint8))
+                i0 = int(rng.integers(0, 200 - wall + 1))
+                xs = np.arange(i0, i0 + wall, dtype=np.int32)
+                ys = np.full(wall, j, np.int32)
+                gm.update(xs, ys, np.ones(wall, np.uint8))
+                wl.apply_ops(cur, xs, ys, np.ones(wall, np.uint8))
                 assert gm.info()["rebuilds"] == 0
                 assert _same_export(gm.export(), oref.RefCDDT(cur, n).export())
             q = wl.rng_for(406, n)
