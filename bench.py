@@ -697,13 +697,16 @@ def make_requests(k: int, seed: int, pools, obs):
     return out
 
 
+SERVE_THREADS = 2  # submitting threads of the load generator (--serve-threads)
+
+
 def serve_at(srv, reqs, rate: float | None, seed: int):
     """Open-loop Poisson arrivals at `rate` requests/s (None: all at once); latency from scheduled arrival."""
     rng = np.random.default_rng(seed)
     k = len(reqs)
     gaps = rng.exponential(1.0 / rate, k) if rate else np.zeros(k)
-    # submitted from a native thread at the scheduled offsets (cddt_server_replay)
-    ids = srv.replay([r[:5] for r in reqs], np.cumsum(gaps))
+    # submitted from native threads at the scheduled offsets (cddt_server_replay_threads)
+    ids = srv.replay([r[:5] for r in reqs], np.cumsum(gaps), threads=SERVE_THREADS)
     t_sub = srv.last_replay_seconds
     if (ids < 0).any():
         raise RuntimeError("serving: a request was refused")
@@ -796,7 +799,8 @@ def run_serving(args, ref_rays_per_s: float | None = None, mode: str | None = No
                        "mode": "resident kernel, ring of slots" if mode == "r" else f"{mode} lanes",
                        "slots" if mode == "r" else "max_batch":
                            resident_slots(args.serve_budget) if mode == "r" else args.serve_batch,
-                       "requests_per_rate": args.serve_requests}}
+                       "requests_per_rate": args.serve_requests, "submitting_threads": SERVE_THREADS,
+                       "resident_tuning": list(SERVE_RESIDENT_TUNING) if mode == "r" else None}}
 
 
 def copy_calibration(mib: int) -> None:
@@ -812,6 +816,7 @@ def copy_calibration(mib: int) -> None:
 
 
 def main():
+    global BUCKETS, ZP16, PRUNE, SERVE_THREADS, SERVE_SLOTS, SERVE_RESIDENT_TUNING
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
@@ -844,18 +849,26 @@ def main():
                     help="batches in flight (streams, 1..4), or r for one resident kernel fed through a ring of "
                          "slots; the serving workload takes a comma-separated list")
     ap.add_argument("--serve-batch", type=int, default=512)
+    ap.add_argument("--serve-slots", type=int, default=SERVE_SLOTS,
+                    help="ring slots of the resident server (at most budget / 32 KiB)")
+    ap.add_argument("--serve-tuning", type=str, default=",".join(map(str, SERVE_RESIDENT_TUNING)),
+                    help="resident kernel tuning: particles/tile,waves/block,blocks/CU,search mode")
+    ap.add_argument("--serve-threads", type=int, default=2,
+                    help="threads of the load generator submitting the arrivals (one thread submits about "
+                         "0.6 M requests/s)")
     ap.add_argument("--probe-gib", type=str, default="4", help="probe buffer sizes in GiB, comma separated")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
-    global BUCKETS
     if args.buckets.lower() == "auto":
         BUCKETS = {"batched": 6, "floor": 7, "updates": 7}.get(args.workload)
     else:
         BUCKETS = None if args.buckets.lower() == "none" else int(args.buckets)
-    global ZP16, PRUNE
     ZP16 = bool(args.zp16)
     PRUNE = bool(args.prune)
+    SERVE_THREADS = max(1, min(16, args.serve_threads))
+    SERVE_SLOTS = max(1, min(65536, args.serve_slots))
+    SERVE_RESIDENT_TUNING = tuple(int(v) for v in args.serve_tuning.split(","))
     if ZP16 and BUCKETS is None:
         print("--zp16 needs a bucket index (--buckets k)", file=sys.stderr)
         sys.exit(2)

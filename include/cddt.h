@@ -465,9 +465,12 @@ cddt_status cddt_probe_gather(const void* buf, int64_t bytes, int32_t blocks, in
  * is written there by the submitting thread and published at once; the
  * kernel's waves take its tiles as they come, among every other request's,
  * and the last tile writes the request's completion word back to host memory.
- * No launch or copy happens per request.  The kernel leaves about a
- * millisecond after the last request finished and is launched again by the
- * next one.  Takes search modes 0, 6, 7 and 8; n_lanes must be 1.
+ * No launch or copy happens per request.  A request's tiles hold the
+ * tuning's particles_per_tile particles while the ring holds fewer tiles than
+ * the kernel has waves, and four times as many (at most 256) beyond that,
+ * which trades a little latency for throughput under load.  The kernel leaves
+ * about a millisecond after the last request finished and is launched again
+ * by the next one.  Takes search modes 0, 6, 7 and 8; n_lanes must be 1.
  * ------------------------------------------------------------------------- */
 typedef struct cddt_server_s* cddt_server;
 
@@ -518,6 +521,15 @@ cddt_status cddt_server_replay(cddt_server s, int32_t n, const int32_t* map_h, c
                                const float* const* px_h, const float* const* py_h,
                                const float* const* ptheta_h, const int32_t* const* obs_h,
                                const double* at_h, int64_t* ids_h);
+/* The same load generator with n_threads (1..16) submitting threads: thread k
+ * (the caller for k = 0) submits the requests i with i mod n_threads == k, each
+ * at its own arrival time, so arrivals faster than one thread can submit are
+ * still offered on time.  cddt_server_replay is the one-thread case.  Errors:
+ * EINVAL (nothing submitted). */
+cddt_status cddt_server_replay_threads(cddt_server s, int32_t n_threads, int32_t n, const int32_t* map_h,
+                                       const int32_t* count_h, const float* const* px_h,
+                                       const float* const* py_h, const float* const* ptheta_h,
+                                       const int32_t* const* obs_h, const double* at_h, int64_t* ids_h);
 /* Non-blocking: 1 if the request finished (logw copied to logw_h, which must
  * hold n_particles floats, and the request released), 0 if not yet. */
 cddt_status cddt_server_poll(cddt_server s, int64_t id, float* logw_h, int32_t* done_h);

@@ -125,6 +125,7 @@ SIGNATURES = {
     "cddt_server_create": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, C.POINTER(ServerConfig), C.POINTER(_vp)]),
     "cddt_server_submit": (_i32, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, C.POINTER(_i64)]),
     "cddt_server_replay": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cddt_server_replay_threads": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cddt_motion": (_i32, [_vp, _vp, _vp, _i64, C.c_float, C.c_float, C.c_float, _vp, _vp]),
     "cddt_resample": (_i32, [_vp, _i64, C.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cddt_plan_set_mcl": (_i32, [_vp, _vp, _vp, _vp]),
@@ -575,8 +576,9 @@ class Server:
         self._sizes[rid.value] = px.size
         return rid.value
 
-    def replay(self, reqs, at):
-        """Open-loop replay: request i = (map, px, py, pth, obs) submitted at[i] s after the call starts.
+    def replay(self, reqs, at, threads: int = 1):
+        """Open-loop replay: request i = (map, px, py, pth, obs) submitted at[i] s after the call starts,
+        from `threads` submitting threads (request i by thread i mod threads).
 
         Returns the request ids (-1 where refused); srv.times(id)[0] is the scheduled arrival."""
         n = len(reqs)
@@ -596,11 +598,11 @@ class Server:
         at = np.ascontiguousarray(at, np.float64)
         ids = np.full(n, -1, np.int64)
         t0 = time.perf_counter()
-        _check(lib().cddt_server_replay(self.handle, n, maps.ctypes.data_as(C.c_void_p),
-                                        counts.ctypes.data_as(C.c_void_p), C.cast(arr["px"], C.c_void_p),
-                                        C.cast(arr["py"], C.c_void_p), C.cast(arr["pth"], C.c_void_p),
-                                        C.cast(arr["obs"], C.c_void_p), at.ctypes.data_as(C.c_void_p),
-                                        ids.ctypes.data_as(C.c_void_p)))
+        _check(lib().cddt_server_replay_threads(self.handle, int(threads), n, maps.ctypes.data_as(C.c_void_p),
+                                                counts.ctypes.data_as(C.c_void_p), C.cast(arr["px"], C.c_void_p),
+                                                C.cast(arr["py"], C.c_void_p), C.cast(arr["pth"], C.c_void_p),
+                                                C.cast(arr["obs"], C.c_void_p), at.ctypes.data_as(C.c_void_p),
+                                                ids.ctypes.data_as(C.c_void_p)))
         self.last_replay_seconds = time.perf_counter() - t0  # the native submission loop alone
         for i, rid in enumerate(ids.tolist()):
             if rid >= 0:

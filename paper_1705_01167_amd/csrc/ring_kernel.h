@@ -50,7 +50,7 @@ struct RingSlot {
   FilterDev f;      // inputs and log-weights point into the slot's region of the pinned arena
   int64_t t_begin;  // global number of the request's first tile
   int32_t n_tiles;
-  int32_t pad;
+  int32_t ppt;      // particles per tile of this request
   int64_t id;       // the completion word receives id + 1
   int64_t pad2;
 };
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kMaxBatchThreads) void k_resident(RingCtl* ctl, con
                                                                const int32_t* __restrict__ tilemap, int64_t mask,
                                                                int64_t* done, RingDev* rd,
                                                                uint32_t* __restrict__ tiles_done, int32_t n_slots,
-                                                               int32_t ppt, uint64_t idle_ticks, uint64_t watch_ticks) {
+                                                               uint64_t idle_ticks, uint64_t watch_ticks) {
   extern __shared__ int2 smem_jobs[];
   constexpr int Q = tile_q(Mode);
   const int lane = threadIdx.x & (kWave - 1);
@@ -191,8 +191,8 @@ __global__ __launch_bounds__(kMaxBatchThreads) void k_resident(RingCtl* ctl, con
       t = claim();
       continue;
     }
-    const int64_t p0 = (int64_t)(t - (uint64_t)s.t_begin) * ppt;
-    const int64_t p1 = p0 + ppt < f.n_particles ? p0 + ppt : f.n_particles;
+    const int64_t p0 = (int64_t)(t - (uint64_t)s.t_begin) * s.ppt;
+    const int64_t p1 = p0 + s.ppt < f.n_particles ? p0 + s.ppt : f.n_particles;
     bool queued = false;
     if constexpr (Q > 0) {
       if (f.n_rays <= kWave) {

@@ -117,6 +117,7 @@ struct Resident {
   int32_t n_slots = 0;
   size_t slot_bytes = 0;
   int64_t tiles = 0;  // tile map entries (a power of two)
+  int64_t busy_tiles = 0;  // waves of the resident grid: more tiles than this in the ring count as busy
   hipStream_t stream = nullptr;
   hipEvent_t ev_start = nullptr, ev_end = nullptr;
   bool running = false, drain_asked = false;
@@ -400,6 +401,8 @@ void destroy_lanes(cddt_server_s* s) {
 // only matter if the host stops answering.
 constexpr double kResidentIdleSeconds = 1e-3;
 constexpr double kWatchSeconds = 1.0, kWorkerIdleSeconds = 2.0;
+// Tile size factor while the ring is busy (see ring_publish).
+constexpr int64_t kBusyTileFactor = 4;
 
 // Bytes a request takes in a slot: poses, observations, log-weights.
 size_t slot_need(const cddt_server_s* s, int32_t map, int32_t n) {
@@ -424,14 +427,18 @@ void ring_fill(cddt_server_s* s, int32_t sl, int32_t map, int32_t n, const float
 bool ring_publish(cddt_server_s* s, int32_t sl) {
   Resident& R = *s->res;
   Request* r = R.owner[sl];
-  const int64_t ppt = s->cfg.tuning.particles_per_tile;
-  const int64_t nt = ((int64_t)r->n + ppt - 1) / ppt;
   while (!R.order.empty()) {  // drop finished or renumbered entries from the front
     const auto& e = R.order.front();
     if (R.where[e.second] >= 0 && R.t_begin[e.second] == e.first) break;
     R.order.pop_front();
   }
   const int64_t oldest = R.order.empty() ? R.pub : R.order.front().first;
+  // Tiles of the tuning's size while the ring holds fewer tiles than the
+  // kernel has waves (latency: a request spreads over many waves); larger
+  // tiles beyond that (throughput: fewer per-tile host-memory round trips).
+  const int64_t base = s->cfg.tuning.particles_per_tile;
+  const int64_t ppt = R.pub - oldest < R.busy_tiles ? base : std::min<int64_t>(base * kBusyTileFactor, 256);
+  const int64_t nt = ((int64_t)r->n + ppt - 1) / ppt;
   if (R.pub + nt - oldest > R.tiles) return false;
   const ServedMap& m = s->maps[r->map];
   const size_t n = (size_t)r->n;
@@ -453,6 +460,7 @@ bool ring_publish(cddt_server_s* s, int32_t sl) {
   d.max_range = m.max_range;
   slot.t_begin = R.pub;
   slot.n_tiles = (int32_t)nt;
+  slot.ppt = (int32_t)ppt;
   slot.id = r->id;
   std::memcpy(&R.slots[sl], &slot, sizeof(RingSlot));
   for (int64_t k = 0; k < nt; ++k) R.tilemap[(R.pub + k) & (R.tiles - 1)] = sl;
@@ -521,12 +529,12 @@ void ring_launch_mode(cddt_server_s* s, unsigned blocks, unsigned threads, size_
   Resident& R = *s->res;
   if (s->zp16)
     hipLaunchKernelGGL((k_resident<Mode, true>), dim3(blocks), dim3(threads), lds, R.stream, R.ctl_d, R.slots_d,
-                       R.tilemap_d, R.tiles - 1, R.done_d, R.rd, R.tiles_done, R.n_slots,
-                       s->cfg.tuning.particles_per_tile, R.idle_ticks, R.watch_ticks);
+                       R.tilemap_d, R.tiles - 1, R.done_d, R.rd, R.tiles_done, R.n_slots, R.idle_ticks,
+                       R.watch_ticks);
   else
     hipLaunchKernelGGL((k_resident<Mode, false>), dim3(blocks), dim3(threads), lds, R.stream, R.ctl_d, R.slots_d,
-                       R.tilemap_d, R.tiles - 1, R.done_d, R.rd, R.tiles_done, R.n_slots,
-                       s->cfg.tuning.particles_per_tile, R.idle_ticks, R.watch_ticks);
+                       R.tilemap_d, R.tiles - 1, R.done_d, R.rd, R.tiles_done, R.n_slots, R.idle_ticks,
+                       R.watch_ticks);
 }
 
 // Launch the resident kernel with tickets from `base` (nothing below it is
@@ -587,7 +595,8 @@ void ring_driver(cddt_server_s* s) {
   (void)hipSetDevice(s->device);
   Resident& R = *s->res;
   std::vector<int32_t> finished;
-  double idle_since = -1.0, last_query = -1.0;
+  double idle_since = -1.0, last_query = -1.0, last_locked = -1.0;
+  int64_t seen_pub = -1;
   for (;;) {
     // 1. unlocked: completion words of every published slot, results out of
     // the pinned arena (a published slot keeps its request until this thread
@@ -612,9 +621,19 @@ void ring_driver(cddt_server_s* s) {
       ended = hipEventQuery(R.ev_end);
       last_query = tq;
     }
-    // 2. locked: publish completions, relaunch or drain
+    // 2. locked: publish completions, relaunch or drain.  Taken when a request
+    // finished, the kernel ended or a new one was published, and otherwise at
+    // most every 20 us (for the idle and stop checks), so that submissions do
+    // not queue behind this thread for the lock.
     bool launch = false, busy = false, stop = false;
     int64_t base = 0;
+    const int64_t pub_now = __atomic_load_n(&R.ctl->pub, __ATOMIC_ACQUIRE);
+    if (finished.empty() && ended == hipErrorNotReady && pub_now == seen_pub && tq - last_locked < 20e-6) {
+      std::this_thread::yield();
+      continue;
+    }
+    seen_pub = pub_now;
+    last_locked = tq;
     {
       std::lock_guard<std::mutex> g(s->mu);
       const double t = s->now();
@@ -758,6 +777,7 @@ cddt_status create_resident(cddt_server_s* s, const cddt_server_config& c) {
   const int64_t per_slot = (max_n + c.tuning.particles_per_tile - 1) / c.tuning.particles_per_tile;
   R.tiles = 1;
   while (R.tiles < (int64_t)R.n_slots * per_slot) R.tiles *= 2;
+  R.busy_tiles = (int64_t)s->cus * c.tuning.blocks_per_cu * c.tuning.waves_per_block;
   if (R.tiles > ((int64_t)1 << 28)) return fail(CDDT_EINVAL, "cddt_server_create: ring tile map too large");
   // the kernel's own exit limits in ticks of the device's constant wall clock
   int khz = 0;
@@ -894,11 +914,13 @@ cddt_status cddt_server_submit(cddt_server s, int32_t map_index, const float* px
   return submit_one(s, map_index, px_h, py_h, ptheta_h, n_particles, obs_h, -1.0, id_h);
 }
 
-cddt_status cddt_server_replay(cddt_server s, int32_t n, const int32_t* map_h, const int32_t* count_h,
-                               const float* const* px_h, const float* const* py_h, const float* const* ptheta_h,
-                               const int32_t* const* obs_h, const double* at_h, int64_t* ids_h) {
+cddt_status cddt_server_replay_threads(cddt_server s, int32_t n_threads, int32_t n, const int32_t* map_h,
+                                       const int32_t* count_h, const float* const* px_h,
+                                       const float* const* py_h, const float* const* ptheta_h,
+                                       const int32_t* const* obs_h, const double* at_h, int64_t* ids_h) {
   if (!s || n < 0 || (n > 0 && (!map_h || !count_h || !px_h || !py_h || !ptheta_h || !obs_h || !at_h || !ids_h)))
     return fail(CDDT_EINVAL, "cddt_server_replay: NULL argument");
+  if (n_threads < 1 || n_threads > 16) return fail(CDDT_EINVAL, "cddt_server_replay: n_threads must be in 1..16");
   for (int32_t i = 0; i < n; ++i) {  // validate everything before the first submission
     if (map_h[i] < 0 || map_h[i] >= (int32_t)s->maps.size()) return fail(CDDT_EINVAL, "cddt_server_replay: bad map");
     if (count_h[i] < 0 || (count_h[i] > 0 && (!px_h[i] || !py_h[i] || !ptheta_h[i])) || !obs_h[i])
@@ -907,14 +929,26 @@ cddt_status cddt_server_replay(cddt_server s, int32_t n, const int32_t* map_h, c
       return fail(CDDT_EINVAL, "cddt_server_replay: offsets must be non-negative and not decrease");
   }
   const double t0 = s->now();
-  for (int32_t i = 0; i < n; ++i) {
-    const double at = t0 + at_h[i];
-    while (s->now() < at) {
+  auto share = [&](int32_t k) {
+    for (int32_t i = k; i < n; i += n_threads) {
+      const double at = t0 + at_h[i];
+      while (s->now() < at) {
+      }
+      ids_h[i] = -1;
+      submit_one(s, map_h[i], px_h[i], py_h[i], ptheta_h[i], count_h[i], obs_h[i], at, &ids_h[i]);
     }
-    ids_h[i] = -1;
-    submit_one(s, map_h[i], px_h[i], py_h[i], ptheta_h[i], count_h[i], obs_h[i], at, &ids_h[i]);
-  }
+  };
+  std::vector<std::thread> others;
+  for (int32_t k = 1; k < n_threads; ++k) others.emplace_back(share, k);
+  share(0);
+  for (auto& th : others) th.join();
   return CDDT_OK;
+}
+
+cddt_status cddt_server_replay(cddt_server s, int32_t n, const int32_t* map_h, const int32_t* count_h,
+                               const float* const* px_h, const float* const* py_h, const float* const* ptheta_h,
+                               const int32_t* const* obs_h, const double* at_h, int64_t* ids_h) {
+  return cddt_server_replay_threads(s, 1, n, map_h, count_h, px_h, py_h, ptheta_h, obs_h, at_h, ids_h);
 }
 
 }  // extern "C"

@@ -128,3 +128,29 @@ def test_resident_close_with_work():
     # the device is free again for plain work
     got = _plain(maps, offs, tabs, M, reqs[0])
     assert got.size == reqs[0][1].size
+
+
+@pytest.mark.parametrize("resident", [True, False])
+def test_replay_from_several_threads(resident):
+    """Replay from three submitting threads (request i by thread i mod 3): every result equals the plain
+    call on its map, and every recorded submit time is the request's scheduled arrival."""
+    from paper_1705_01167_amd import cddt
+    rng, maps, offs, tabs, occs, M = _setup(seed=16)
+    reqs = _requests(rng, occs, M, 90)
+    srv = cddt.Server(maps, offs, tabs, [M] * len(maps), budget_bytes=16 << 20, n_lanes=1 if resident else 2,
+                      max_batch=64, tuning=TUNING, resident=resident)
+    at = np.cumsum(np.full(len(reqs), 1e-4))
+    ids = srv.replay(reqs, at, threads=3)
+    assert (ids >= 0).all() and len(set(ids.tolist())) == len(reqs)
+    t_first = None
+    for rid, r, a in zip(ids.tolist(), reqs, at):
+        got = srv.wait(rid)
+        assert _plain(maps, offs, tabs, M, r).tobytes() == got.tobytes()
+        s, d = srv.times(rid)
+        t_first = s - a if t_first is None else t_first
+        assert abs((s - a) - t_first) < 1e-9 and s <= d
+    with pytest.raises(cddt.CddtError):
+        srv.replay(reqs[:2], at[:2], threads=17)     # 1..16 threads
+    st = srv.stats()
+    srv.close()
+    assert st["submitted"] == len(reqs) and st["completed"] == len(reqs)
