@@ -826,19 +826,23 @@ __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, f
                                                     int32_t max_range, int32_t* __restrict__ ranges_row) {
   const int lane = threadIdx.x & (kWave - 1);
   const int32_t m1 = max_range + 1;
-  bool xy_ok = pose_inside(m, px, py);
+  // The pose's cell is read while the searches run: the searches assume a
+  // free cell, and an occupied one zeroes the ranges afterwards (the same for
+  // the whole wave, so the pairing below is unaffected).
+  const bool inside = pose_inside(m, px, py);
   int32_t xf = 0, yf = 0;
-  if (xy_ok) {
+  uint8_t cell = 1;
+  if (inside) {
     xf = quantize16(px);
     yf = quantize16(py);
-    xy_ok = ldg(m.occ + (size_t)(yf >> 16) * (size_t)m.w + (size_t)(xf >> 16)) == 0;
+    cell = ldg(m.occ + (size_t)(yf >> 16) * (size_t)m.w + (size_t)(xf >> 16));
   }
   float acc = 0.0f;
   for (int32_t base = 0; base < n_rays; base += kWave) {
     const int32_t r = base + lane;
     const bool active = r < n_rays;
     float th = active ? __fadd_rn(pth, ldg(offsets + r)) : 0.0f;
-    bool valid = active && xy_ok && (fabsf(th) < 1e6f);
+    bool valid = active && inside && (fabsf(th) < 1e6f);
     int32_t slice = 0;
     bool fwd = true;
     if (valid) {
@@ -864,7 +868,8 @@ __device__ __forceinline__ float wave_particle_logw(const MapDev& m, float px, f
     band_search<K, Z>(m, valid && !paired, l.row, l.xq, max_range, rs, rp);
     const int32_t opk = __shfl(rs | (rp << 16), src_c);  // partner's (successor, predecessor) ranges
     int32_t range = 0;
-    if (valid) range = paired ? (fwd ? (opk & 0xffff) : (int32_t)((uint32_t)opk >> 16)) : (fwd ? rs : rp);
+    if (valid && cell == 0)
+      range = paired ? (fwd ? (opk & 0xffff) : (int32_t)((uint32_t)opk >> 16)) : (fwd ? rs : rp);
     if (active) {
       int32_t zo = ldx<Sys>(obs + r);
       zo = zo < 0 ? 0 : (zo > max_range ? max_range : zo);
