@@ -790,23 +790,23 @@ __device__ __forceinline__ void band_search(const MapDev& m, bool want, int32_t 
 template <int K, bool Z>
 __device__ __forceinline__ int32_t wave_cast(const MapDev& m, bool active, float x, float y, float theta,
                                              int32_t max_range) {
-  bool valid = active && (fabsf(theta) < 1e6f) && pose_inside(m, x, y);
+  // the query's cell is read while the search runs (an occupied cell gives 0)
+  const bool valid = active && (fabsf(theta) < 1e6f) && pose_inside(m, x, y);
   int32_t xf = 0, yf = 0;
-  if (valid) {
-    xf = quantize16(x);
-    yf = quantize16(y);
-    valid = ldg(m.occ + (size_t)(yf >> 16) * (size_t)m.w + (size_t)(xf >> 16)) == 0;
-  }
+  uint8_t cell = 1;
   bool fwd = true;
   Landing l{0, 0};
   if (valid) {
+    xf = quantize16(x);
+    yf = quantize16(y);
+    cell = ldg(m.occ + (size_t)(yf >> 16) * (size_t)m.w + (size_t)(xf >> 16));
     int32_t k = theta_bin(theta, m.k_scale, m.n);
     fwd = k < m.half;
     l = land(m, fwd ? k : k - m.half, xf, yf);
   }
   int32_t rs, rp;
   band_search<K, Z>(m, valid, l.row, l.xq, max_range, rs, rp);
-  return valid ? (fwd ? rs : rp) : 0;
+  return valid && cell == 0 ? (fwd ? rs : rp) : 0;
 }
 
 // Log-weight of one particle, computed by all 64 lanes of a wave (lane = ray
