@@ -755,8 +755,8 @@ def make_server(maps, offs, tabs, args, mode: str, budget: int):
 
 def run_serving(args, ref_rays_per_s: float | None = None, mode: str | None = None) -> dict:
     """Open-loop Poisson arrivals at SERVE_FRACTIONS of the batched capacity, args.serve_requests each."""
-    # the serving maps have no bucket index unless one is asked for explicitly
-    buckets = None if args.buckets.lower() == "auto" else BUCKETS
+    # the serving maps take a 2^7-cell bucket index unless another layout is asked for
+    buckets = 7 if args.buckets.lower() == "auto" else BUCKETS
     mode = mode or str(args.serve_lanes).split(",")[0]
     maps, offs, tabs, pools, obs = build_serving(buckets)
     ref_kind = "the many-filter step's kernel rays/s in this run"
@@ -826,9 +826,8 @@ def main():
     ap.add_argument("--filters", type=int, default=64)
     ap.add_argument("--buckets", type=str, default="auto",
                     help="log2 bucket width in cells of the maps' bucket index, 'none' for no index, or 'auto': "
-                         "6 for the batched workload (185 GB of structure), 7 for floor and updates, none for "
-                         "small and serving (measured better there: small maps stay in cache; serving keeps a "
-                         "lower p99 at light load)")
+                         "6 for the batched workload (185 GB of structure), 7 for floor, updates and the serving "
+                         "maps, none for small (its map stays in cache)")
     ap.add_argument("--zp16", action="store_true",
                     help="16-bit zero points in the bucket lines (answers follow the 16-bit reading, not the "
                          "exact one; needs a bucket index)")
