@@ -221,6 +221,14 @@ cddt_status cddt_export(cddt_map m, int64_t* row_start_h, int32_t* row_len_h, in
 /* Current occupancy grid (host uint8[W*H]).  Blocks. */
 cddt_status cddt_export_grid(cddt_map m, uint8_t* occ_h);
 
+/* The bucket index lines (inspection helper; the line format follows the
+ * bucket index's description above): lines_h receives bucket_lines x 32
+ * int32 (band r's bucket b at line r * buckets-per-band + b), n_ints must be
+ * exactly that.  A map updated incrementally holds the same lines as a fresh
+ * build of its grid.  Blocks.  Errors: EINVAL (NULL, no bucket index, wrong
+ * size). */
+cddt_status cddt_export_buckets(cddt_map m, int32_t* lines_h, int64_t n_ints);
+
 /* ---------------------------------------------------------------------------
  * Many filters in one persistent launch.
  * A plan fixes a set of filters (each one cddt_weight call: its own map,

@@ -102,6 +102,7 @@ SIGNATURES = {
     "cddt_slice_table": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "cddt_export": (_i32, [_vp, _vp, _vp, _vp]),
     "cddt_export_grid": (_i32, [_vp, _vp]),
+    "cddt_export_buckets": (_i32, [_vp, _vp, _i64]),
     "cddt_plan_create": (_i32, [_vp, _i32, _vp, _vp, C.POINTER(_vp)]),
     "cddt_plan_set_tuning": (_i32, [_vp, C.POINTER(Tuning)]),
     "cddt_plan_get_tuning": (_i32, [_vp, C.POINTER(Tuning)]),
@@ -345,6 +346,13 @@ class Map:
                                  zz.ctypes.data_as(C.c_void_p)))
         out = (self.slice_table()[3], rl, zz[:st["zero_points"]])
         return out + (rs,) if with_starts else out
+
+    def bucket_lines(self) -> np.ndarray:
+        """The bucket index lines, int32[bucket_lines, 32] (the map must have a bucket index)."""
+        n = int(self.info()["bucket_lines"])
+        out = np.empty((n, 32), np.int32)
+        _check(lib().cddt_export_buckets(self.handle, out.ctypes.data_as(C.c_void_p), n * 32))
+        return out
 
     def grid(self) -> np.ndarray:
         g = np.zeros((self.height, self.width), np.uint8)

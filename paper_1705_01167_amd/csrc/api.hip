@@ -393,6 +393,17 @@ cddt_status cddt_export_grid(cddt_map m, uint8_t* occ_h) {
   return CDDT_OK;
 }
 
+cddt_status cddt_export_buckets(cddt_map m, int32_t* lines_h, int64_t n_ints) {
+  if (!m || !lines_h) return fail(CDDT_EINVAL, "cddt_export_buckets: NULL argument");
+  if (!m->d_bk) return fail(CDDT_EINVAL, "cddt_export_buckets: the map has no bucket index");
+  const int64_t want = m->rows * (int64_t)m->nbk * kLineInts;
+  if (n_ints != want)
+    return fail(CDDT_EINVAL, "cddt_export_buckets: n_ints must be " + std::to_string(want));
+  CDDT_HIP(hipDeviceSynchronize());
+  CDDT_HIP(hipMemcpy(lines_h, m->d_bk, 4 * (size_t)want, hipMemcpyDeviceToHost));
+  return CDDT_OK;
+}
+
 cddt_status cddt_update(cddt_map m, const int32_t* xs_h, const int32_t* ys_h, const uint8_t* values_h,
                         int64_t n_ops, void* stream) {
   if (!m) return fail(CDDT_EINVAL, "cddt_update: map is NULL");

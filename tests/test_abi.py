@@ -66,6 +66,8 @@ def test_validation_needs_no_gpu():
     assert not out.value
     assert L.cddt_cast(None, None, None, None, 1, 5, None, None) == cddt.EINVAL
     assert L.cddt_update(None, None, None, None, 1, None) == cddt.EINVAL
+    assert L.cddt_export_buckets(None, None, 0) == cddt.EINVAL
+    assert L.cddt_server_replay_threads(None, 2, 0, None, None, None, None, None, None, None, None) == cddt.EINVAL
     assert L.cddt_destroy(None) == cddt.OK
     assert L.cddt_plan_create(None, 0, None, None, C.byref(out)) == cddt.EINVAL
     # servers: at most 4 lanes (refused before any map is touched)

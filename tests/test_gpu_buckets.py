@@ -157,9 +157,11 @@ def test_bucket_updates_match_oracle(seed):
         want = rm.cast(x, y, th, M, threads=4)
         got = gb.cast(_dev(x), _dev(y), _dev(th), M).cpu().numpy()
         assert (got == want).all(), f"step {step}: {(got != want).sum()} rays differ"
-        # the overflow count kept across partial refreshes equals a fresh build's
+        # the lines rewritten in the edited bands, and the overflow count kept across the rewrites, equal a
+        # fresh build's
         fresh = _map(occ.copy(), n, buckets=lb)
         assert gb.info()["bucket_overflow"] == fresh.info()["bucket_overflow"]
+        assert (gb.bucket_lines() == fresh.bucket_lines()).all(), f"step {step}: bucket lines differ"
         fresh.close()
 
 

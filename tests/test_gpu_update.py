@@ -113,6 +113,10 @@ def test_outgrown_bands_move_to_spare_area(wall):
                 wl.apply_ops(cur, xs, ys, np.ones(wall, np.uint8))
                 assert gm.info()["rebuilds"] == 0
                 assert _same_export(gm.export(), oref.RefCDDT(cur, n).export())
+                if buckets is not None:  # moved bands' lines, rewritten from their new regions
+                    fresh = _map(cur, n, buckets=buckets)
+                    assert (gm.bucket_lines() == fresh.bucket_lines()).all()
+                    fresh.close()
             q = wl.rng_for(406, n)
             x = q.uniform(0, 200, 20000).astype(np.float32)
             y = q.uniform(0, 160, 20000).astype(np.float32)

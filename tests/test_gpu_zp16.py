@@ -89,6 +89,7 @@ def test_zp16_updates(seed):
     _say(f"zp16 updates seed={seed} {w}x{h} n={n} log2={lb}")
     rm = oref.RefCDDT(occ.copy(), n, zp16=True)
     gm = _map(occ, n, buckets=lb, zp16=True)
+    cur = occ.copy()
     for step in range(3):
         k = int(rng.integers(1, 300))
         xs = rng.integers(0, w, k).astype(np.int32)
@@ -96,10 +97,16 @@ def test_zp16_updates(seed):
         vs = rng.integers(0, 2, k).astype(np.uint8)
         gm.update(xs, ys, vs)
         rm.update(xs, ys, vs)
+        wl.apply_ops(cur, xs, ys, vs)
         x, y, th = _queries(rng, w, h, 8000)
         want = rm.cast(x, y, th, 300, threads=4)
         got = gm.cast(_dev(x), _dev(y), _dev(th), 300).cpu().numpy()
         assert (got == want).all(), f"step {step}: {(got != want).sum()} rays differ"
+        # the overflow count kept across the edited bands' line rewrites equals a fresh build's
+        fresh = _map(cur, n, buckets=lb, zp16=True)
+        assert gm.info()["bucket_overflow"] == fresh.info()["bucket_overflow"]
+        assert (gm.bucket_lines() == fresh.bucket_lines()).all(), f"step {step}: bucket lines differ"
+        fresh.close()
 
 
 def test_zp16_plan_equals_plain():
