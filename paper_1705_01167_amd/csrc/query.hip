@@ -40,7 +40,7 @@ __global__ __launch_bounds__(kCastThreads) void k_cast(MapDev m, const float* __
 
 // Casts on maps with a bucket index: kCastQ * 64 rays per wave through
 // the search queue (half-line first pass, deferred full searches).
-constexpr int kCastQ = 4;
+constexpr int kCastQ = 8;
 template <bool Z>
 __global__ __launch_bounds__(kCastThreads) void k_cast_tiles(MapDev m, const float* __restrict__ x,
                                                              const float* __restrict__ y,
