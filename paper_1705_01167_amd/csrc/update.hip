@@ -254,34 +254,19 @@ __global__ __launch_bounds__(kThreads) void k_records(const SliceDev* __restrict
 }
 
 // The first record of a band registers it: touched[s] = band, tzlo[s] = the
-// lowest zero point of its slice (the origin of its bucket index).  The slots
-// of a wave's first records come from one atomic on the touched count.
+// lowest zero point of its slice (the origin of its bucket index).
 __global__ void k_group_count(const Rec* __restrict__ rec, const uint16_t* __restrict__ rslice,
                               const SliceDev* __restrict__ slices, const UpdCounters* ctr_in,
                               uint32_t* __restrict__ rowcnt, uint32_t* __restrict__ row_slot,
                               uint32_t* __restrict__ touched, int32_t* __restrict__ tzlo,
                               uint32_t* __restrict__ local, UpdCounters* ctr) {
   const uint32_t n = ctr_in->records;
-  const int lane = threadIdx.x & 63;
-  // k0 is the same for the whole block, so every lane of a wave runs each pass
-  for (uint32_t k0 = blockIdx.x * blockDim.x; k0 < n; k0 += gridDim.x * blockDim.x) {
-    const uint32_t k = k0 + threadIdx.x;
-    const bool have = k < n;
-    uint32_t row = 0, l = 1;
-    if (have) {
-      row = rec[k].row & 0x7fffffffu;
-      l = atomicAdd(&rowcnt[row], 1u);
-      local[k] = l;
-    }
-    const bool first = have && l == 0;
-    const uint64_t fm = __ballot(first);
-    if (fm == 0) continue;
-    const int leader = __ffsll((unsigned long long)fm) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&ctr->touched, (uint32_t)__popcll(fm));
-    base = __shfl(base, leader);
-    if (first) {
-      const uint32_t s = base + (uint32_t)__popcll(fm & ((1ull << lane) - 1ull));
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const uint32_t row = rec[k].row & 0x7fffffffu;
+    const uint32_t l = atomicAdd(&rowcnt[row], 1u);
+    local[k] = l;
+    if (l == 0) {
+      const uint32_t s = atomicAdd(&ctr->touched, 1u);
       row_slot[row] = s;
       touched[s] = row;
       tzlo[s] = slices[rslice[k]].zlo;
