@@ -21,9 +21,9 @@ from oracle import ref as oref
 pytestmark = pytest.mark.gpu
 
 # (particles per tile, waves per block, blocks per CU, search mode): the
-# autotuner's usual winners on this workload (modes 7 and 8) and the other
-# search strategies it sweeps
-TUNINGS = [(8, 2, 8, 7), (16, 4, 4, 8), (8, 4, 4, 9), (4, 4, 2, 10), (2, 4, 8, 2), (1, 4, 8, 0)]
+# autotuner's usual winners on this workload (8,1,16,7 in recent default runs,
+# then 8,2,8,7 and mode 8) and the other search strategies it sweeps
+TUNINGS = [(8, 1, 16, 7), (8, 2, 8, 7), (16, 4, 4, 8), (8, 4, 4, 9), (4, 4, 2, 10), (2, 4, 8, 2), (1, 4, 8, 0)]
 RTOL = 1e-5
 
 
