@@ -41,7 +41,7 @@ constexpr int kThreads = 256;
 constexpr int kScanThreads = 1024;
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kScanThreads * kScanItems;
-constexpr unsigned kEditBlocks = 4096;    // band-edit launch: waves take touched bands in turn
+constexpr unsigned kEditBlocks = 16384;   // band-edit launch: waves take touched bands in turn
 constexpr unsigned kStrideBlocks = 2048;  // record-sized launches: threads take records in turn
 // A chunk's device staging: xs, ys (int32) and values (uint8), kOpChunk each,
 // then the counters.
