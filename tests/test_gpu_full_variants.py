@@ -1,12 +1,12 @@
-"""The 64-filter workload at full size in the two other layouts bench.py
-measures (`--buckets 7 --zp16`: 16-bit bucket lines; `--prune`: PCDDT with the
-2^6-cell index), built and launched as bench.py does them (graph replay, the
-8,1,16,7 tuning): on filters spread over the map sizes, every ray's range
-equals the oracle's reading of that layout (Sec. IV-C: 16-bit zero points at
-1/8-cell bin centres; PCDDT keeps the zero points some discrete state's cast
-returns) and every log-weight is within 1e-5 * max(1, |L|) of its double sum.
-The pruned oracle casts from every discrete state, so it is checked on the
-filters with the smallest maps.
+"""The 64-filter workload at full size in the other layouts bench.py measures
+(`--buckets 7`, `--buckets none`, `--buckets 7 --zp16`: 16-bit bucket lines;
+`--prune`: PCDDT with the 2^6-cell index), built and launched as bench.py does
+them (graph replay, the 8,1,16,7 tuning): on filters spread over the map sizes,
+every ray's range equals the oracle's reading of that layout (Sec. IV-B; for
+16-bit lines Sec. IV-C's zero points at 1/8-cell bin centres; for PCDDT the
+zero points some discrete state's cast returns) and every log-weight is within
+1e-5 * max(1, |L|) of its double sum.  The pruned oracle casts from every
+discrete state, so it is checked on the filters with the smallest maps.
 """
 import sys
 
@@ -70,6 +70,13 @@ def _spread(specs, k=8):
 
 def _smallest(specs, k=4):
     return sorted(np.argsort([sp["side"] for sp in specs], kind="stable")[:k].tolist())
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("buckets", [7, None])
+def test_full_workload_bucket_widths_against_oracle(monkeypatch, buckets):
+    _say(f"full variants: bucket index {buckets}")
+    assert len(_run(monkeypatch, buckets, False, False, _spread)) == 8
 
 
 @pytest.mark.timeout(900)
