@@ -171,6 +171,48 @@ def test_reveal_and_hide_interior():
 
 
 @pytest.mark.timeout(600)
+def test_toggle_workload_4000_zp16():
+    """The updates workload with 16-bit bucket lines (`bench.py --workload updates --zp16`): 4000^2 floor, 200
+    bins, 2^7-cell buckets, 1000 random toggles per step.  After every step 244,000 casts from free poses plus
+    50,000 from anywhere equal the oracle's 16-bit reading (Sec. IV-C) of its incrementally updated structure
+    (Sec. IV-D), and the rewritten bucket lines equal a fresh build's byte for byte."""
+    import torch
+    from paper_1705_01167_amd import cddt
+    _say("toggles 4000 zp16: build")
+    occ = wl.building_map(wl.rng_for(wl.UPDATES, wl.S_MAP), 4000, 4000)
+    n, M, B = 200, 500, 7
+    th = oref.default_threads()
+    gm = _map(occ, n, buckets=B, zp16=True)
+    rm = oref.RefCDDT(occ, n, threads=th, zp16=True)
+    cur = occ.copy()
+    rng = wl.rng_for(wl.UPDATES, wl.S_OPS)
+    off = wl.ray_offsets(61)
+    q = wl.rng_for(408, 0)
+    for step in range(3):
+        xs, ys, vals = wl.toggle_ops(rng, cur, 1000)
+        gm.update(xs, ys, vals)
+        rm.update(xs, ys, vals)
+        wl.apply_ops(cur, xs, ys, vals)
+        _say(f"toggles 4000 zp16: step {step}")
+        assert (gm.grid() == cur).all()
+        px, py, pth = wl.free_poses(wl.rng_for(wl.UPDATES, wl.S_POSES, step), cur, 4000)
+        x, y = np.repeat(px, 61), np.repeat(py, 61)
+        t = (np.repeat(pth, 61) + np.tile(off, px.size)).astype(np.float32)
+        xa, ya, ta = _random_queries(q, 4000, 4000, 50000)
+        x, y, t = np.concatenate([x, xa]), np.concatenate([y, ya]), np.concatenate([t, ta])
+        got = gm.cast(_dev(x), _dev(y), _dev(t), M).cpu().numpy()
+        want = rm.cast(x, y, t, M, threads=th)
+        assert (got == want).all(), f"step {step}: {(got != want).sum()} of {got.size} casts differ"
+        fresh = cddt.Map(_dev(cur), n, buckets=B, zp16=True)
+        assert gm.info()["bucket_overflow"] == fresh.info()["bucket_overflow"]
+        assert (gm.bucket_lines() == fresh.bucket_lines()).all(), f"step {step}: bucket lines differ"
+        fresh.close()
+        torch.cuda.empty_cache()
+    rm.close()
+    gm.close()
+
+
+@pytest.mark.timeout(600)
 def test_toggle_workload_4000():
     """The updates workload as bench.py runs it: 4000^2 floor, 200 bins, bucket index at 2^7 cells,
     1000 random toggles per step.  After every step the GPU structure equals the oracle's incrementally
